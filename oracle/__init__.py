@@ -1,0 +1,291 @@
+"""FP64 CPU oracle for prior-predictive sampling (arXiv:1902.09046).
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, obviously-correct
+reference that the GPU library is checked against.  Only the test suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+product path never does, and the two share no code: the C source here
+(``pps_oracle.c``) is written independently of the HIP library, and this
+wrapper marshals arguments with its own ctypes structures.
+
+Each function follows one passage of the paper:
+
+* ``philox`` / ``stream_block`` / ``uniform`` / ``box_muller`` -- the per-draw
+  random streams (Sec. 2.5, independent streams; Philox4x32-10 from Salmon et
+  al., SC'11) and the Box-Muller normal generator (Sec. 3.4 uses the
+  Box-Muller method of MKL).
+* ``simulate`` -- prior-predictive sampling, Eq. ppd and Alg. 1's first two
+  steps: theta ~ pi(theta), D ~ s(D; theta), reduced to its summaries.
+* ``abc`` -- ABC rejection in its fixed-N form (Alg. 1 and the paragraph after
+  it): accept rho <= eps, or the closest fraction with eps chosen a posteriori.
+* ``pvalue`` -- the prior-predictive p-value under each lambda of a
+  hyperparameter grid (Eqs. pppv, pppvhype), using a tail-area statistic.
+* ``summary_tally`` -- per-summary tail areas (the GARCH check).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Mapping, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pps_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+UNIFORM, NORMAL, LOGNORMAL, POINT = 0, 1, 2, 3
+LOGISTIC, GARCH11, NORMAL_MEAN = 0, 1, 2
+EPS_FIXED, EPS_TOP_FRACTION = 0, 1
+GARCH_NSUMM = 14
+
+_FAMILY = {"uniform": UNIFORM, "normal": NORMAL, "lognormal": LOGNORMAL, "point": POINT}
+_MODEL = {"logistic": LOGISTIC, "garch11": GARCH11, "normal_mean": NORMAL_MEAN}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` (gcc, -O2, OpenMP)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.run(
+        ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-Wall", _SRC, "-o", tmp, "-lm"],
+        check=True,
+    )
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Prior(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int32), ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_int32),
+        ("n_params", ctypes.c_int32),
+        ("prior", _Prior * 4),
+        ("constraint", ctypes.c_int32),
+        ("x0", ctypes.c_double),
+        ("t_end", ctypes.c_double),
+        ("steps", ctypes.c_int32),
+        ("n_obs", ctypes.c_int32),
+        ("noise_sd", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        mp = ctypes.POINTER(_Model)
+        lib.or_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        lib.or_stream_block.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, u32p]
+        lib.or_uniform.argtypes = [ctypes.c_uint32]
+        lib.or_uniform.restype = ctypes.c_double
+        lib.or_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        lib.or_path_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+        lib.or_path_normal.restype = ctypes.c_double
+        lib.or_prior_draw.argtypes = [mp, ctypes.c_uint64, ctypes.c_uint64, f64p]
+        lib.or_prior_draw.restype = ctypes.c_int
+        lib.or_n_summaries.argtypes = [mp]
+        lib.or_n_summaries.restype = ctypes.c_int
+        lib.or_simulate.argtypes = [mp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_void_p, f64p, f64p, f64p, f64p, i32p]
+        lib.or_simulate.restype = ctypes.c_int
+        lib.or_top_count.argtypes = [ctypes.c_double, ctypes.c_uint64]
+        lib.or_top_count.restype = ctypes.c_uint64
+        lib.or_abc.argtypes = [mp, f64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                               ctypes.c_int, ctypes.c_double, ctypes.c_uint64, u64p, f64p, f64p,
+                               ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double),
+                               f64p, f64p]
+        lib.or_abc.restype = ctypes.c_int
+        lib.or_pvalue.argtypes = [mp, ctypes.c_int, ctypes.c_int, f64p, ctypes.c_int, ctypes.c_uint64,
+                                  ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, u64p, f64p]
+        lib.or_pvalue.restype = ctypes.c_int
+        lib.or_summary_tally.argtypes = [mp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, f64p, u64p]
+        lib.or_summary_tally.restype = ctypes.c_int
+        lib.or_logistic_path.argtypes = [mp, f64p, ctypes.c_uint64, ctypes.c_uint64, f64p]
+        lib.or_logistic_path.restype = ctypes.c_int
+        lib.or_garch_series.argtypes = [mp, f64p, ctypes.c_uint64, ctypes.c_uint64, f64p]
+        lib.or_garch_series.restype = ctypes.c_int
+        lib.or_garch_summaries.argtypes = [f64p, ctypes.c_int, f64p]
+        lib.or_distance.argtypes = [f64p, f64p, ctypes.c_int]
+        lib.or_distance.restype = ctypes.c_double
+        lib.or_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _model(spec: Mapping) -> _Model:
+    m = _Model()
+    m.model = _MODEL[spec["model"]]
+    priors = spec["priors"]
+    m.n_params = len(priors)
+    for j, (fam, a, b) in enumerate(priors):
+        m.prior[j].family = _FAMILY[fam]
+        m.prior[j].a = float(a)
+        m.prior[j].b = float(b)
+    m.constraint = 1 if spec.get("constraint") == "garch_stationary" else 0
+    m.x0 = float(spec.get("x0", 0.0))
+    m.t_end = float(spec.get("t_end", 0.0))
+    m.steps = int(spec.get("steps", 0))
+    m.n_obs = int(spec.get("n_obs", 0))
+    m.noise_sd = float(spec.get("noise_sd", 0.0))
+    return m
+
+
+def threads() -> int:
+    """OpenMP threads the oracle will use."""
+    return int(_load().or_max_threads())
+
+
+def philox(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    _load().or_philox4x32_10(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def stream_block(seed: int, draw: int, block: int, purpose: int) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    _load().or_stream_block(seed, draw, block, purpose, out)
+    return out
+
+
+def uniform(word: int) -> float:
+    return float(_load().or_uniform(word))
+
+
+def box_muller(w0: int, w1: int) -> tuple[float, float]:
+    z0, z1 = ctypes.c_double(), ctypes.c_double()
+    _load().or_box_muller(w0, w1, ctypes.byref(z0), ctypes.byref(z1))
+    return z0.value, z1.value
+
+
+def path_normal(seed: int, draw: int, n: int) -> float:
+    return float(_load().or_path_normal(seed, draw, n))
+
+
+def n_summaries(spec: Mapping) -> int:
+    return int(_load().or_n_summaries(ctypes.byref(_model(spec))))
+
+
+def prior_draw(spec: Mapping, seed: int, draw: int) -> tuple[np.ndarray, int]:
+    m = _model(spec)
+    theta = np.zeros(m.n_params, np.float64)
+    attempts = _load().or_prior_draw(ctypes.byref(m), seed, draw, theta)
+    return theta, int(attempts)
+
+
+def simulate(spec: Mapping, seed: int, first: int, n: int, y_obs=None) -> dict:
+    """Per-draw theta, summaries, mean statistic, distance and prior attempts."""
+    m = _model(spec)
+    ns = n_summaries(spec)
+    theta = np.zeros((n, m.n_params), np.float64)
+    summ = np.zeros((n, ns), np.float64)
+    stat = np.zeros(n, np.float64)
+    dist = np.zeros(n, np.float64)
+    att = np.zeros(n, np.int32)
+    y = None
+    if y_obs is not None:
+        y = np.ascontiguousarray(y_obs, np.float64)
+        assert y.shape == (ns,)
+    rc = _load().or_simulate(ctypes.byref(m), seed, first, n,
+                             y.ctypes.data if y is not None else None,
+                             theta, summ, stat, dist, att)
+    if rc != 0:
+        raise ValueError("oracle: invalid model")
+    return {"theta": theta, "summ": summ, "stat": stat, "dist": dist, "attempts": att}
+
+
+def top_count(frac: float, n: int) -> int:
+    return int(_load().or_top_count(frac, n))
+
+
+def abc(spec: Mapping, y_obs, seed: int, first: int, n: int, mode: int, eps_or_frac: float,
+        capacity: int | None = None) -> dict:
+    m = _model(spec)
+    cap = n if capacity is None else capacity
+    idx = np.zeros(max(cap, 1), np.uint64)
+    th = np.zeros((max(cap, 1), m.n_params), np.float64)
+    d = np.zeros(max(cap, 1), np.float64)
+    nacc = ctypes.c_uint64()
+    eps = ctypes.c_double()
+    mean = np.zeros(4, np.float64)
+    var = np.zeros(4, np.float64)
+    rc = _load().or_abc(ctypes.byref(m), np.ascontiguousarray(y_obs, np.float64), seed, first, n,
+                        mode, eps_or_frac, cap, idx, th, d, ctypes.byref(nacc), ctypes.byref(eps),
+                        mean, var)
+    if rc < 0:
+        raise ValueError("oracle: invalid input")
+    k = min(int(nacc.value), cap)
+    return {"idx": idx[:k], "theta": th[:k], "dist": d[:k], "n_accepted": int(nacc.value),
+            "eps_used": float(eps.value), "mean": mean[: m.n_params], "var": var[: m.n_params],
+            "truncated": rc == 1}
+
+
+def pvalue(spec: Mapping, lambda_param: int, lambda_family: str, lambdas, seed: int, first: int,
+           n: int, t_obs: float) -> dict:
+    m = _model(spec)
+    lam = np.ascontiguousarray(lambdas, np.float64)
+    counts = np.zeros(len(lam), np.uint64)
+    p = np.zeros(len(lam), np.float64)
+    rc = _load().or_pvalue(ctypes.byref(m), lambda_param, _FAMILY[lambda_family], lam, len(lam),
+                           seed, first, n, t_obs, counts, p)
+    if rc != 0:
+        raise ValueError("oracle: invalid input")
+    return {"count_ge": counts, "pvalue": p}
+
+
+def summary_tally(spec: Mapping, seed: int, first: int, n: int, obs_summ) -> np.ndarray:
+    m = _model(spec)
+    ns = n_summaries(spec)
+    counts = np.zeros(ns, np.uint64)
+    rc = _load().or_summary_tally(ctypes.byref(m), seed, first, n,
+                                  np.ascontiguousarray(obs_summ, np.float64), counts)
+    if rc != 0:
+        raise ValueError("oracle: invalid input")
+    return counts
+
+
+def logistic_path(spec: Mapping, theta, seed: int, draw: int) -> np.ndarray:
+    m = _model(spec)
+    path = np.zeros(m.steps, np.float64)
+    rc = _load().or_logistic_path(ctypes.byref(m), np.ascontiguousarray(theta, np.float64), seed,
+                                  draw, path)
+    if rc != 0:
+        raise ValueError("oracle: not a logistic model")
+    return path
+
+
+def garch_series(spec: Mapping, theta, seed: int, draw: int) -> np.ndarray:
+    m = _model(spec)
+    r = np.zeros(m.steps, np.float64)
+    rc = _load().or_garch_series(ctypes.byref(m), np.ascontiguousarray(theta, np.float64), seed,
+                                 draw, r)
+    if rc != 0:
+        raise ValueError("oracle: not a GARCH model")
+    return r
+
+
+def garch_summaries(r) -> np.ndarray:
+    r = np.ascontiguousarray(r, np.float64)
+    s = np.zeros(GARCH_NSUMM, np.float64)
+    _load().or_garch_summaries(r, len(r), s)
+    return s
+
+
+def distance(x, y) -> float:
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    return float(_load().or_distance(x, y, len(x)))

@@ -1,0 +1,653 @@
+/*
+ * FP64 CPU oracle for prior-predictive sampling (Warne, Sisson & Drovandi,
+ * "Vector operations for accelerating expensive Bayesian computations -- a
+ * tutorial guide", arXiv:1902.09046).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Nothing in the product path may link,
+ * load or call it; it shares no code, header or constant table with the HIP
+ * library.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.
+ *
+ * What it computes, following the paper:
+ *   - prior-predictive sampling (Sec. 3.1, Eq. ppd): draw theta from the
+ *     prior, simulate data given theta;
+ *   - ABC rejection in its fixed-N form (Alg. 1 and the paragraph after it):
+ *     generate N (theta, D) pairs, then accept by a tolerance epsilon that is
+ *     either fixed or chosen a posteriori from the empirical distribution of
+ *     the discrepancy;
+ *   - the prior-predictive p-value under a family of priors pi(theta|lambda)
+ *     (Sec. 4.1, Eqs. pppv and pppvhype), with a tail-area statistic in place
+ *     of the predictive density;
+ *   - Euler-Maruyama time stepping (Sec. 3.3, Eq. gene_uv_SDE_EM) applied to a
+ *     stochastic logistic SDE; a GARCH(1,1) recursion (the Gaussian special
+ *     case of the volatility family of Sec. 4.2); a normal-mean model;
+ *   - independent random streams per draw (Sec. 2.5, option (ii) taken to
+ *     the limit): the counter-based Philox4x32-10 generator of Salmon, Moraes,
+ *     Dror and Shaw (SC'11), keyed by the seed, with the draw index in the
+ *     counter, so that every draw is reproducible on its own;
+ *   - a static partition of draws over threads (Listing of the multithreaded
+ *     sampler in Sec. 3.4; Appendix B discussion of static scheduling).
+ *
+ * Everything is IEEE double except the 32-bit integer RNG.  Where the paper is
+ * silent (observation times, uniform/normal generation, stream layout,
+ * boundary handling, GARCH summaries) the readings are listed in the design
+ * notes and restated at each function below.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11, Sec. 5 "Philox").                    */
+/* One round maps (c0,c1,c2,c3) with key (k0,k1) to                          */
+/*   (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0))        */
+/* and the key is bumped by the Weyl constants between rounds.               */
+/* ------------------------------------------------------------------------ */
+static const uint32_t PHILOX_M0 = 0xD2511F53u;
+static const uint32_t PHILOX_M1 = 0xCD9E8D57u;
+static const uint32_t PHILOX_W0 = 0x9E3779B9u; /* golden ratio */
+static const uint32_t PHILOX_W1 = 0xBB67AE85u; /* sqrt(3) - 1 */
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Stream layout (reading of "keyed by (seed, i)"): key = (lo32 seed, hi32
+ * seed); counter = (block b, purpose, lo32 i, hi32 i).  Purpose 0 = prior
+ * draws, 1 = the simulated path.                                            */
+enum { OR_PURPOSE_PRIOR = 0, OR_PURPOSE_PATH = 1 };
+
+void or_stream_block(uint64_t seed, uint64_t draw, uint32_t block, uint32_t purpose,
+                     uint32_t out[4])
+{
+    uint32_t ctr[4] = { block, purpose, (uint32_t)draw, (uint32_t)(draw >> 32) };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    or_philox4x32_10(ctr, key, out);
+}
+
+/* Uniform on the open interval: the top 23 bits of a word select the cell
+ * midpoint (2k+1)/2^24, so the value is never 0 or 1 and is exact in both
+ * float and double.                                                          */
+double or_uniform(uint32_t word)
+{
+    double k = (double)(word >> 9);
+    return (2.0 * k + 1.0) / 16777216.0;
+}
+
+/* Box-Muller transform (the paper's MKL generator uses the Box-Muller method,
+ * Sec. 3.4): two uniforms give two independent standard normals.            */
+void or_box_muller(uint32_t w0, uint32_t w1, double *z0, double *z1)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double u0 = or_uniform(w0);
+    double u1 = or_uniform(w1);
+    double radius = sqrt(-2.0 * log(u0));
+    *z0 = radius * cos(two_pi * u1);
+    *z1 = radius * sin(two_pi * u1);
+}
+
+/* Path normals of one draw: normal n comes from block n/4 of the PATH stream;
+ * words (0,1) give normals 4b, 4b+1 and words (2,3) give 4b+2, 4b+3.        */
+void or_path_block(uint64_t seed, uint64_t draw, uint32_t block, double z[4])
+{
+    uint32_t w[4];
+    or_stream_block(seed, draw, block, OR_PURPOSE_PATH, w);
+    or_box_muller(w[0], w[1], &z[0], &z[1]);
+    or_box_muller(w[2], w[3], &z[2], &z[3]);
+}
+
+double or_path_normal(uint64_t seed, uint64_t draw, uint64_t n)
+{
+    double z[4];
+    or_path_block(seed, draw, (uint32_t)(n / 4), z);
+    return z[n % 4];
+}
+
+/* Sequential reader of the path normals z_0, z_1, ... of one draw.          */
+typedef struct {
+    uint64_t seed, draw;
+    uint64_t next;
+    double buf[4];
+} normal_reader;
+
+static void reader_init(normal_reader *r, uint64_t seed, uint64_t draw)
+{
+    r->seed = seed;
+    r->draw = draw;
+    r->next = 0;
+}
+
+static double reader_next(normal_reader *r)
+{
+    if (r->next % 4 == 0)
+        or_path_block(r->seed, r->draw, (uint32_t)(r->next / 4), r->buf);
+    return r->buf[r->next++ % 4];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Model description (plain data; independent of the GPU library's structs). */
+/* ------------------------------------------------------------------------ */
+enum { OR_UNIFORM = 0, OR_NORMAL = 1, OR_LOGNORMAL = 2, OR_POINT = 3 };
+enum { OR_LOGISTIC = 0, OR_GARCH11 = 1, OR_NORMAL_MEAN = 2 };
+enum { OR_NO_CONSTRAINT = 0, OR_GARCH_STATIONARY = 1 };
+#define OR_MAX_PARAMS 4
+#define OR_MAX_ATTEMPTS 32
+#define OR_GARCH_LAGS 10
+#define OR_GARCH_NSUMM (4 + OR_GARCH_LAGS)
+
+typedef struct {
+    int32_t family;
+    double a, b;
+} or_prior;
+
+typedef struct {
+    int32_t model;
+    int32_t n_params;
+    or_prior prior[OR_MAX_PARAMS];
+    int32_t constraint;
+    double x0;        /* logistic: initial state */
+    double t_end;     /* logistic: final time T */
+    int32_t steps;    /* logistic: Euler-Maruyama steps S; GARCH: series length */
+    int32_t n_obs;    /* logistic: observations; normal-mean: sample size */
+    double noise_sd;  /* normal-mean: observation sd */
+} or_model;
+
+/* One prior value from PRIOR block (8*attempt + j): uniform from word 0,
+ * normal from words (0,1) through Box-Muller (first output).                */
+static double prior_value(const or_prior *p, uint64_t seed, uint64_t draw, int j, int attempt)
+{
+    uint32_t w[4];
+    or_stream_block(seed, draw, (uint32_t)(8 * attempt + j), OR_PURPOSE_PRIOR, w);
+    double z0, z1;
+    switch (p->family) {
+    case OR_UNIFORM:
+        return p->a + (p->b - p->a) * or_uniform(w[0]);
+    case OR_NORMAL:
+        or_box_muller(w[0], w[1], &z0, &z1);
+        return p->a + p->b * z0;
+    case OR_LOGNORMAL:
+        or_box_muller(w[0], w[1], &z0, &z1);
+        return exp(p->a + p->b * z0);
+    case OR_POINT:
+    default:
+        return p->a;
+    }
+}
+
+/* theta ~ pi(theta) (Alg. 1, first step).  With the GARCH stationarity
+ * constraint, an attempt whose (alpha, beta) = (theta[1], theta[2]) has
+ * alpha + beta >= 1 is rejected and the next attempt of the same draw's
+ * stream is used; after OR_MAX_ATTEMPTS the last attempt is kept.
+ * Returns the number of attempts used.                                      */
+int or_prior_draw(const or_model *m, uint64_t seed, uint64_t draw, double *theta)
+{
+    int attempt = 0;
+    for (;;) {
+        for (int j = 0; j < m->n_params; ++j)
+            theta[j] = prior_value(&m->prior[j], seed, draw, j, attempt);
+        if (m->constraint != OR_GARCH_STATIONARY)
+            return attempt + 1;
+        if (theta[1] + theta[2] < 1.0 || attempt + 1 == OR_MAX_ATTEMPTS)
+            return attempt + 1;
+        ++attempt;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Simulators.                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Stochastic logistic SDE dX = th1 X (1 - X/th2) dt + th3 X dW, integrated by
+ * Euler-Maruyama (Eq. gene_uv_SDE_EM) with dt = T/S:
+ *   X <- X + X (a - b X + c z),  a = th1 dt, b = th1 dt / th2, c = th3 sqrt(dt)
+ * then absorbed at zero, X <- max(X, 0) (the paper clamps its gene levels at a
+ * boundary the same way).  Observation k (k = 1..n_obs) is X after step
+ * k*S/n_obs.  S must be a multiple of n_obs.                                  */
+static void simulate_logistic(const or_model *m, const double *theta, uint64_t seed,
+                              uint64_t draw, double *obs)
+{
+    const double dt = m->t_end / (double)m->steps;
+    const double a = theta[0] * dt;
+    const double b = theta[0] * dt / theta[1];
+    const double c = theta[2] * sqrt(dt);
+    const int stride = m->steps / m->n_obs;
+    double x = m->x0;
+    int k = 0;
+    normal_reader rd;
+    reader_init(&rd, seed, draw);
+    for (int n = 0; n < m->steps; ++n) {
+        double z = reader_next(&rd);
+        x = x + x * (a - b * x + c * z);
+        if (x < 0.0)
+            x = 0.0;
+        if ((n + 1) % stride == 0)
+            obs[k++] = x;
+    }
+}
+
+/* Normal-mean model: y_j = mu + sd * z_j for j = 1..n_obs, mu = theta[0].    */
+static void simulate_normal_mean(const or_model *m, const double *theta, uint64_t seed,
+                                 uint64_t draw, double *obs)
+{
+    normal_reader rd;
+    reader_init(&rd, seed, draw);
+    for (int j = 0; j < m->n_obs; ++j)
+        obs[j] = theta[0] + m->noise_sd * reader_next(&rd);
+}
+
+/* GARCH(1,1) returns: sigma2_1 = omega / (1 - alpha - beta), then for
+ * t = 1..L:  r_t = sqrt(sigma2_t) z_t,  sigma2_{t+1} = omega + alpha r_t^2 +
+ * beta sigma2_t, z_t the t-th path normal.  No mean, no burn-in.              */
+static void simulate_garch_series(const or_model *m, const double *theta, uint64_t seed,
+                                  uint64_t draw, double *r)
+{
+    const double omega = theta[0], alpha = theta[1], beta = theta[2];
+    double sigma2 = omega / (1.0 - alpha - beta);
+    normal_reader rd;
+    reader_init(&rd, seed, draw);
+    for (int t = 0; t < m->steps; ++t) {
+        double z = reader_next(&rd);
+        r[t] = sqrt(sigma2) * z;
+        sigma2 = omega + alpha * r[t] * r[t] + beta * sigma2;
+    }
+}
+
+/* GARCH summaries by their definitions, two-pass:
+ *   s[0] mean, s[1] variance (1/L), s[2] skewness m3/m2^1.5,
+ *   s[3] kurtosis m4/m2^2 (not excess),
+ *   s[4+k-1] = sum_{t<=L-k} (a_t - abar)(a_{t+k} - abar) / sum_t (a_t - abar)^2
+ *   for the squared returns a_t = r_t^2, lags k = 1..10.                     */
+static void garch_summaries(const double *r, int len, double *s)
+{
+    double mean = 0.0;
+    for (int t = 0; t < len; ++t)
+        mean += r[t];
+    mean /= len;
+    double m2 = 0.0, m3 = 0.0, m4 = 0.0;
+    for (int t = 0; t < len; ++t) {
+        double d = r[t] - mean;
+        m2 += d * d;
+        m3 += d * d * d;
+        m4 += d * d * d * d;
+    }
+    m2 /= len; m3 /= len; m4 /= len;
+    s[0] = mean;
+    s[1] = m2;
+    s[2] = m3 / pow(m2, 1.5);
+    s[3] = m4 / (m2 * m2);
+    double abar = 0.0;
+    for (int t = 0; t < len; ++t)
+        abar += r[t] * r[t];
+    abar /= len;
+    double den = 0.0;
+    for (int t = 0; t < len; ++t)
+        den += (r[t] * r[t] - abar) * (r[t] * r[t] - abar);
+    for (int k = 1; k <= OR_GARCH_LAGS; ++k) {
+        double num = 0.0;
+        for (int t = 0; t + k < len; ++t)
+            num += (r[t] * r[t] - abar) * (r[t + k] * r[t + k] - abar);
+        s[4 + k - 1] = num / den;
+    }
+}
+
+/* Number of summaries (the "data" D of one draw) a model produces.          */
+int or_n_summaries(const or_model *m)
+{
+    if (m->model == OR_GARCH11)
+        return OR_GARCH_NSUMM;
+    return m->n_obs;
+}
+
+/* D ~ s(D; theta) reduced to its summaries (Alg. 1, second step).           */
+static void simulate_summaries(const or_model *m, const double *theta, uint64_t seed,
+                               uint64_t draw, double *summ, double *work)
+{
+    switch (m->model) {
+    case OR_LOGISTIC:
+        simulate_logistic(m, theta, seed, draw, summ);
+        break;
+    case OR_NORMAL_MEAN:
+        simulate_normal_mean(m, theta, seed, draw, summ);
+        break;
+    case OR_GARCH11:
+    default:
+        simulate_garch_series(m, theta, seed, draw, work);
+        garch_summaries(work, m->steps, summ);
+        break;
+    }
+}
+
+/* Euclidean discrepancy rho(S(D_obs), S(D)) between summary vectors.        */
+double or_distance(const double *x, const double *y, int n)
+{
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k)
+        acc += (x[k] - y[k]) * (x[k] - y[k]);
+    return sqrt(acc);
+}
+
+/* Tail-area statistic: the mean of the observations.                         */
+double or_mean_stat(const double *x, int n)
+{
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k)
+        acc += x[k];
+    return acc / n;
+}
+
+static int model_ok(const or_model *m)
+{
+    if (m->n_params < 1 || m->n_params > OR_MAX_PARAMS)
+        return 0;
+    if (m->model == OR_LOGISTIC)
+        return m->n_params >= 3 && m->n_obs > 0 && m->steps > 0 && m->steps % m->n_obs == 0;
+    if (m->model == OR_NORMAL_MEAN)
+        return m->n_obs > 0;
+    if (m->model == OR_GARCH11)
+        return m->n_params >= 3 && m->steps > OR_GARCH_LAGS;
+    return 0;
+}
+
+static size_t work_len(const or_model *m)
+{
+    return m->model == OR_GARCH11 ? (size_t)m->steps : 1;
+}
+
+/* Per-draw prior-predictive output for draws i in [first, first + n):
+ *   theta[(i-first)*n_params + j], summ[(i-first)*ns + k],
+ *   stat[i-first] = mean of the summaries (logistic / normal-mean) or NaN,
+ *   dist[i-first] = distance to y_obs (when y_obs != NULL) or NaN,
+ *   attempts[i-first] = prior attempts used (optional).
+ * Returns 0, or -1 for an invalid model.                                    */
+int or_simulate(const or_model *m, uint64_t seed, uint64_t first, uint64_t n,
+                const double *y_obs, double *theta, double *summ, double *stat,
+                double *dist, int32_t *attempts)
+{
+    if (!model_ok(m))
+        return -1;
+    const int np = m->n_params;
+    const int ns = or_n_summaries(m);
+    const size_t wl = work_len(m);
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(wl * sizeof(double));
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < (int64_t)n; ++q) {
+            uint64_t draw = first + (uint64_t)q;
+            double *th = theta + (size_t)q * np;
+            double *s = summ + (size_t)q * ns;
+            int at = or_prior_draw(m, seed, draw, th);
+            if (attempts)
+                attempts[q] = at;
+            simulate_summaries(m, th, seed, draw, s, work);
+            if (stat)
+                stat[q] = (m->model == OR_GARCH11) ? NAN : or_mean_stat(s, ns);
+            if (dist)
+                dist[q] = y_obs ? or_distance(s, y_obs, ns) : NAN;
+        }
+        free(work);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ABC rejection, fixed-N form (Alg. 1 and the paragraph after it).          */
+/* ------------------------------------------------------------------------ */
+enum { OR_EPS_FIXED = 0, OR_EPS_TOP_FRACTION = 1 };
+
+typedef struct {
+    double d;
+    uint64_t i;
+} dist_index;
+
+static int cmp_dist_index(const void *pa, const void *pb)
+{
+    const dist_index *a = (const dist_index *)pa, *b = (const dist_index *)pb;
+    if (a->d < b->d) return -1;
+    if (a->d > b->d) return 1;
+    if (a->i < b->i) return -1;
+    if (a->i > b->i) return 1;
+    return 0;
+}
+
+static int cmp_u64(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return (a > b) - (a < b);
+}
+
+/* Accepted count for the top-fraction mode: k = ceil(frac * N), at least 1
+ * and at most N.                                                             */
+uint64_t or_top_count(double frac, uint64_t n)
+{
+    double k = ceil(frac * (double)n);
+    if (k < 1.0) k = 1.0;
+    if (k > (double)n) k = (double)n;
+    return (uint64_t)k;
+}
+
+/* Accepts draws i in [first, first+n):
+ *   FIXED:        rho <= eps;
+ *   TOP_FRACTION: the k = ceil(frac N) smallest (rho, i) pairs, ordered by
+ *                 rho then by i, with eps_used = the k-th smallest rho.
+ * Outputs the accepted indices in increasing order with their theta (row
+ * major, n_params per row) and rho, up to `capacity` rows; *n_acc is the true
+ * count.  Posterior moments of the accepted theta: mean and unbiased variance
+ * (NaN when fewer than 2 draws), summed in index order.
+ * Returns 0, 1 when the output was truncated to capacity, -1 on bad input.  */
+int or_abc(const or_model *m, const double *y_obs, uint64_t seed, uint64_t first, uint64_t n,
+           int mode, double eps_or_frac, uint64_t capacity, uint64_t *acc_idx,
+           double *acc_theta, double *acc_dist, uint64_t *n_acc, double *eps_used,
+           double *mean, double *var)
+{
+    if (!model_ok(m) || n == 0)
+        return -1;
+    const int np = m->n_params;
+    const int ns = or_n_summaries(m);
+    double *theta = (double *)malloc((size_t)n * np * sizeof(double));
+    double *summ = (double *)malloc((size_t)n * ns * sizeof(double));
+    double *dist = (double *)malloc((size_t)n * sizeof(double));
+    or_simulate(m, seed, first, n, y_obs, theta, summ, NULL, dist, NULL);
+    free(summ);
+
+    /* accepted positions q (relative to first), in increasing order */
+    uint64_t *acc = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    uint64_t count = 0;
+    double eps;
+    if (mode == OR_EPS_FIXED) {
+        eps = eps_or_frac;
+        for (uint64_t q = 0; q < n; ++q)
+            if (dist[q] <= eps)
+                acc[count++] = q;
+    } else {
+        uint64_t k = or_top_count(eps_or_frac, n);
+        dist_index *order = (dist_index *)malloc((size_t)n * sizeof(dist_index));
+        for (uint64_t q = 0; q < n; ++q) {
+            order[q].d = dist[q];
+            order[q].i = q;
+        }
+        qsort(order, (size_t)n, sizeof(dist_index), cmp_dist_index);
+        eps = order[k - 1].d;
+        for (uint64_t r = 0; r < k; ++r)
+            acc[count++] = order[r].i;
+        free(order);
+        qsort(acc, (size_t)count, sizeof(uint64_t), cmp_u64);
+    }
+
+    for (uint64_t r = 0; r < count && r < capacity; ++r) {
+        uint64_t q = acc[r];
+        acc_idx[r] = first + q;
+        for (int j = 0; j < np; ++j)
+            acc_theta[r * np + j] = theta[q * np + j];
+        acc_dist[r] = dist[q];
+    }
+    for (int j = 0; j < np; ++j) {
+        double s = 0.0;
+        for (uint64_t r = 0; r < count; ++r)
+            s += theta[acc[r] * np + j];
+        double mu = count > 0 ? s / (double)count : NAN;
+        double ss = 0.0;
+        for (uint64_t r = 0; r < count; ++r) {
+            double d = theta[acc[r] * np + j] - mu;
+            ss += d * d;
+        }
+        mean[j] = mu;
+        var[j] = count > 1 ? ss / (double)(count - 1) : NAN;
+    }
+    *n_acc = count;
+    *eps_used = eps;
+    free(acc);
+    free(dist);
+    free(theta);
+    return count > capacity ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Prior-predictive p-values over a hyperparameter grid (Eq. pppvhype).      */
+/* ------------------------------------------------------------------------ */
+
+/* For each lambda_k the prior of parameter `lambda_param` becomes
+ * (lambda_family, a = the model's a for that parameter, b = lambda_k); the
+ * other priors are unchanged.  Draw i uses the same random numbers under
+ * every lambda_k (common random numbers).  count_ge[k] = #{i : T_i >= t_obs}
+ * with T the mean of the observations; pvalue[k] = count_ge[k] / n.         */
+int or_pvalue(const or_model *m, int lambda_param, int lambda_family, const double *lambda,
+              int n_lambda, uint64_t seed, uint64_t first, uint64_t n, double t_obs,
+              uint64_t *count_ge, double *pvalue)
+{
+    if (!model_ok(m) || m->model == OR_GARCH11 || lambda_param < 0 ||
+        lambda_param >= m->n_params || n_lambda < 1 || n == 0)
+        return -1;
+    const int np = m->n_params;
+    const int ns = or_n_summaries(m);
+    for (int k = 0; k < n_lambda; ++k) {
+        or_model mk = *m;
+        mk.prior[lambda_param].family = lambda_family;
+        mk.prior[lambda_param].b = lambda[k];
+        uint64_t count = 0;
+#pragma omp parallel reduction(+ : count)
+        {
+            double theta[OR_MAX_PARAMS];
+            double *summ = (double *)malloc((size_t)ns * sizeof(double));
+#pragma omp for schedule(static)
+            for (int64_t q = 0; q < (int64_t)n; ++q) {
+                uint64_t draw = first + (uint64_t)q;
+                or_prior_draw(&mk, seed, draw, theta);
+                simulate_summaries(&mk, theta, seed, draw, summ, NULL);
+                if (or_mean_stat(summ, ns) >= t_obs)
+                    ++count;
+            }
+            free(summ);
+        }
+        (void)np;
+        count_ge[k] = count;
+        pvalue[k] = (double)count / (double)n;
+    }
+    return 0;
+}
+
+/* Per-summary tail-area tallies for a summary-vector model (used for the
+ * GARCH prior-predictive check): count_ge[s] = #{i : S_s(D_i) >= obs[s]}.   */
+int or_summary_tally(const or_model *m, uint64_t seed, uint64_t first, uint64_t n,
+                     const double *obs_summ, uint64_t *count_ge)
+{
+    if (!model_ok(m))
+        return -1;
+    const int ns = or_n_summaries(m);
+    const size_t wl = work_len(m);
+    for (int s = 0; s < ns; ++s)
+        count_ge[s] = 0;
+#pragma omp parallel
+    {
+        double theta[OR_MAX_PARAMS];
+        double *summ = (double *)malloc((size_t)ns * sizeof(double));
+        double *work = (double *)malloc(wl * sizeof(double));
+        uint64_t *local = (uint64_t *)calloc((size_t)ns, sizeof(uint64_t));
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < (int64_t)n; ++q) {
+            uint64_t draw = first + (uint64_t)q;
+            or_prior_draw(m, seed, draw, theta);
+            simulate_summaries(m, theta, seed, draw, summ, work);
+            for (int s = 0; s < ns; ++s)
+                if (summ[s] >= obs_summ[s])
+                    ++local[s];
+        }
+#pragma omp critical
+        for (int s = 0; s < ns; ++s)
+            count_ge[s] += local[s];
+        free(local);
+        free(work);
+        free(summ);
+    }
+    return 0;
+}
+
+/* The full path of one draw at every step (for convergence checks):
+ * path[n] = X after step n+1, n = 0..S-1 (logistic only).                   */
+int or_logistic_path(const or_model *m, const double *theta, uint64_t seed, uint64_t draw,
+                     double *path)
+{
+    if (m->model != OR_LOGISTIC || m->steps < 1)
+        return -1;
+    const double dt = m->t_end / (double)m->steps;
+    const double a = theta[0] * dt;
+    const double b = theta[0] * dt / theta[1];
+    const double c = theta[2] * sqrt(dt);
+    double x = m->x0;
+    normal_reader rd;
+    reader_init(&rd, seed, draw);
+    for (int n = 0; n < m->steps; ++n) {
+        double z = reader_next(&rd);
+        x = x + x * (a - b * x + c * z);
+        if (x < 0.0)
+            x = 0.0;
+        path[n] = x;
+    }
+    return 0;
+}
+
+/* The GARCH return series of one draw (for checks of the summaries).        */
+int or_garch_series(const or_model *m, const double *theta, uint64_t seed, uint64_t draw,
+                    double *r)
+{
+    if (m->model != OR_GARCH11)
+        return -1;
+    simulate_garch_series(m, theta, seed, draw, r);
+    return 0;
+}
+
+/* Summaries of a given return series (exposes garch_summaries for checks).  */
+void or_garch_summaries(const double *r, int len, double *s)
+{
+    garch_summaries(r, len, s);
+}
+
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

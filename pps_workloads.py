@@ -1,0 +1,108 @@
+"""Seeded synthetic workloads shared by the GPU library's callers and the oracle.
+
+This module holds input recipes only -- model specifications, prior
+hyperparameters, the lambda grid, the serving job mix -- and none of the
+method's arithmetic (no random stream, simulator, discrepancy or tally).  Both
+sides turn a specification here into their own argument structures.
+
+A specification is a plain dict::
+
+    {"model": "logistic" | "garch11" | "normal_mean",
+     "priors": [(family, a, b), ...],   # family: uniform(a,b) | normal(mu,sd)
+                                        #   | lognormal(mu,sd) | point(a)
+     "constraint": None | "garch_stationary",
+     "x0": X0, "t_end": T, "steps": S, "n_obs": n, "noise_sd": sd}
+
+The workloads follow the paper's structure (prior-predictive sampling for ABC,
+Sec. 3; prior-predictive p-values over a hyperparameter family, Sec. 4.1) on
+synthetic models of the same shape: a stochastic logistic SDE observed at 20
+times, a GARCH(1,1) return series of length 2000, and a normal-mean model whose
+prior predictive has a closed form.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Seeds: the observed data set is draw 0 of seed 0 at a fixed theta; sampling
+# runs use seed 1 so that no sampled draw reuses the observed noise.
+OBS_SEED = 0
+OBS_DRAW = 0
+SAMPLING_SEED = 1
+
+LOGISTIC_THETA_OBS = (1.0, 100.0, 0.2)
+GARCH_THETA_OBS = (5e-5, 0.1, 0.85)
+
+
+def logistic_spec(steps: int = 1000, t_end: float = 10.0, n_obs: int = 20, x0: float = 10.0,
+                  theta1=("uniform", 0.0, 2.0), theta2=("uniform", 50.0, 150.0),
+                  theta3=("uniform", 0.0, 0.5)) -> dict:
+    """dX = th1 X (1 - X/th2) dt + th3 X dW on [0, T], X(0) = X0."""
+    return {"model": "logistic", "priors": [theta1, theta2, theta3], "constraint": None,
+            "x0": x0, "t_end": t_end, "steps": steps, "n_obs": n_obs, "noise_sd": 0.0}
+
+
+def logistic_point_spec(theta=LOGISTIC_THETA_OBS, **kw) -> dict:
+    """The logistic model with every prior a point mass (used to make y_obs)."""
+    return logistic_spec(theta1=("point", theta[0], 0.0), theta2=("point", theta[1], 0.0),
+                         theta3=("point", theta[2], 0.0), **kw)
+
+
+def garch_spec(series_len: int = 2000, omega=("uniform", 1e-6, 1e-4), alpha=("uniform", 0.0, 0.3),
+               beta=("uniform", 0.5, 0.99), constraint="garch_stationary") -> dict:
+    """GARCH(1,1) returns of length L; priors as listed, alpha + beta < 1."""
+    return {"model": "garch11", "priors": [omega, alpha, beta], "constraint": constraint,
+            "x0": 0.0, "t_end": 0.0, "steps": series_len, "n_obs": 0, "noise_sd": 0.0}
+
+
+def garch_point_spec(theta=GARCH_THETA_OBS, series_len: int = 2000) -> dict:
+    return garch_spec(series_len, ("point", theta[0], 0.0), ("point", theta[1], 0.0),
+                      ("point", theta[2], 0.0), constraint=None)
+
+
+def normal_mean_spec(n_obs: int = 20, noise_sd: float = 1.0, prior_sd: float = 1.0) -> dict:
+    """mu ~ N(0, prior_sd^2), y_j = mu + noise_sd z_j, j = 1..n."""
+    return {"model": "normal_mean", "priors": [("normal", 0.0, prior_sd)], "constraint": None,
+            "x0": 0.0, "t_end": 0.0, "steps": 0, "n_obs": n_obs, "noise_sd": noise_sd}
+
+
+def lambda_grid(n: int = 64, lo: float = 0.05, hi: float = 3.0) -> np.ndarray:
+    """n log-spaced values from lo to hi (inclusive)."""
+    k = np.arange(n, dtype=np.float64)
+    return lo * (hi / lo) ** (k / (n - 1))
+
+
+def pvalue_spec(steps: int = 1000) -> dict:
+    """The p-value batch: th1 ~ LogNormal(0, lambda) (lambda is the log-sd),
+    the other priors as in the ABC workload."""
+    return logistic_spec(steps=steps, theta1=("lognormal", 0.0, 1.0))
+
+
+# Named configurations (sizes of the paper-shaped workloads).
+ABC_SMALL = {"name": "abc_logistic_n1e4", "n": 10_000, "frac": 0.01}
+ABC_LARGE = {"name": "abc_logistic_n1e7", "n": 10_000_000, "pilot_n": 100_000, "pilot_frac": 0.001}
+PVALUE_BATCH = {"name": "pvalue_logistic_64lambda_n1e6", "n": 1_000_000, "n_lambda": 64}
+SERVING_MIX = {"name": "serving_mix_2000jobs_200hz", "n_jobs": 2000, "rate_hz": 200.0, "seed": 3}
+GARCH_CHECK = {"name": "garch11_L2000_n1e6", "n": 1_000_000, "series_len": 2000}
+
+
+def serving_jobs(n_jobs: int = 2000, rate_hz: float = 200.0, seed: int = 3,
+                 n_lo: float = 1e3, n_hi: float = 1e6, s_lo: float = 200.0, s_hi: float = 5000.0,
+                 n_obs: int = 20, n_lambda: int = 64) -> list[dict]:
+    """The serving mix: Poisson arrivals, N and steps log-uniform, half ABC
+    (closest 1%) and half p-value jobs at a lambda drawn from the grid."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=n_jobs)
+    arrival = np.cumsum(gaps) - gaps[0]
+    n_draws = np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), size=n_jobs)).astype(np.int64)
+    steps_raw = np.exp(rng.uniform(math.log(s_lo), math.log(s_hi), size=n_jobs))
+    steps = np.maximum(n_obs, (np.rint(steps_raw / n_obs) * n_obs).astype(np.int64))
+    kind = rng.integers(0, 2, size=n_jobs)
+    lam_idx = rng.integers(0, n_lambda, size=n_jobs)
+    jobs = []
+    for j in range(n_jobs):
+        jobs.append({"arrival_s": float(arrival[j]), "n": int(n_draws[j]), "steps": int(steps[j]),
+                     "kind": "abc" if kind[j] == 0 else "pvalue", "lambda_index": int(lam_idx[j]),
+                     "seed": 1000 + j})
+    return jobs

@@ -1,0 +1,47 @@
+"""Write the observed data sets used by the tests and the benchmark.
+
+Calls only the FP64 oracle.  The observed data of each workload is one
+prior-predictive simulation at a fixed theta (point priors), seed 0, draw 0:
+
+* logistic SDE, theta = (1, 100, 0.2), X0 = 10, T = 10, S = 1000, observed at
+  steps 50, 100, ..., 1000 -> ``y_obs`` (20 values) and ``t_obs`` = their mean;
+* GARCH(1,1), theta = (5e-5, 0.1, 0.85), L = 2000 -> the 14 summaries.
+
+Values are written with 17 significant digits so they round-trip exactly.
+Run:  python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import pps_workloads as W  # noqa: E402
+
+
+def main():
+    out = {}
+    for steps in (1000,):
+        spec = W.logistic_point_spec(steps=steps)
+        sim = oracle.simulate(spec, W.OBS_SEED, W.OBS_DRAW, 1)
+        y = sim["summ"][0]
+        out[f"logistic_S{steps}"] = {
+            "theta": list(W.LOGISTIC_THETA_OBS), "seed": W.OBS_SEED, "draw": W.OBS_DRAW,
+            "y_obs": [float(repr_) for repr_ in y], "t_obs": float(sim["stat"][0]),
+        }
+    gspec = W.garch_point_spec()
+    gs = oracle.simulate(gspec, W.OBS_SEED, W.OBS_DRAW, 1)
+    out["garch_L2000"] = {"theta": list(W.GARCH_THETA_OBS), "seed": W.OBS_SEED,
+                          "draw": W.OBS_DRAW, "summaries": [float(v) for v in gs["summ"][0]]}
+    path = os.path.join(HERE, "observed.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()
