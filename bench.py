@@ -1,0 +1,148 @@
+#!/usr/bin/env python3
+"""Benchmark of the prior-predictive sampler on one MI355X.
+
+Workload (default): ABC rejection on the stochastic logistic SDE,
+N = 1e7 prior draws, 1000 Euler-Maruyama steps each, 20 observations,
+accepted at the fixed tolerance eps = the 0.1% distance quantile of the FP64
+oracle's 1e5-draw pilot (stored in tests/golden/observed.json).  One step =
+one ``abc_sample`` call: prior draws, simulation, distances, ordered
+compaction of the accepted draws and their FP64 posterior moments, results
+copied back to the host.
+
+Prints one JSON line.  ``roofline`` reports the dominant kernel (the
+persistent simulation kernel) against the VALU issue peak; its duration is
+measured with HIP events that the library records around the kernel on the
+caller's stream.  ``cpu_baseline`` times the FP64 oracle on a bounded sample
+of the same workload on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "prior-predictive sims/s + % FP32 VALU peak vs plain GPU; p50/p99 job latency"
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one VALU lane-operation
+# per lane per cycle (157.3 TFLOP/s counts an FMA as 2 and packed FP32 as 2x).
+CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
+VALU_PEAK_OPS = CUS * SIMDS * LANES * CLOCK  # 3.93e13 lane-ops/s
+
+# Algorithmic VALU lane-operations of the logistic path (see the design notes):
+#   Philox4x32-10 call: 10 rounds x (2 mul_hi + 2 mul_lo + 4 xor) = 80
+#   Box-Muller pair: 2 x (shift, convert, fma) + log2, scale, sqrt, cos, sin,
+#                    2 multiplies = 12   -> 24 per call (4 normals)
+#   Euler-Maruyama step: 3 fma + max = 4
+#   observation: difference, Kahan (4) for rho^2, Kahan (4) for the sum = 9
+#   prior draw: 3 Philox calls + 3 uniform transforms ~ 250 per draw
+OPS_PHILOX = 80
+OPS_BM_PAIR = 12
+OPS_EM = 4
+OPS_OBS = 9
+OPS_PRIOR = 250
+
+
+def ops_per_draw(steps: int, n_obs: int) -> float:
+    per_step = (OPS_PHILOX + 2 * OPS_BM_PAIR) / 4.0 + OPS_EM
+    return steps * per_step + n_obs * OPS_OBS + OPS_PRIOR
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=10_000_000, help="prior draws per step")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000,
+                    help="draws of the oracle's timed sample (0 disables the CPU baseline)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding of draw ranges is described in the design notes, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1902_09046_amd as P
+    import pps_workloads as W
+
+    torch.cuda.set_device(0)
+    with open(os.path.join(ROOT, "tests", "golden", "observed.json")) as f:
+        golden = json.load(f)
+    y_obs = np.array(golden["logistic_S1000"]["y_obs"])
+    eps = golden["abc_n1e7_pilot"]["eps"]
+    steps_em, n_obs = 1000, 20
+    spec = W.logistic_spec(steps=steps_em, n_obs=n_obs)
+    model = P.make_model(spec)
+    n = args.n
+    sampling = P.make_sampling(n, 0, W.SAMPLING_SEED)
+    capacity = max(1024, n // 500)
+    idx = torch.empty(capacity, dtype=torch.int64, device="cuda")
+    th = torch.empty((3, capacity), dtype=torch.float32, device="cuda")
+    dd = torch.empty(capacity, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    P.pps_set_timing(True)
+    print(f"bench: warmup {args.warmup} x abc_sample N={n}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        P.abc_sample(model, y_obs, sampling, P.PPS_EPS_FIXED, eps, capacity, idx, th, dd)
+    kernel_ms = []
+    stats = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, stats = P.abc_sample(model, y_obs, sampling, P.PPS_EPS_FIXED, eps, capacity, idx, th, dd)
+        kernel_ms.append(P.pps_last_kernel_ms())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    print(f"bench: timed {args.steps} steps in {elapsed:.3f}s; accepted {stats['n_accepted']}",
+          file=sys.stderr, flush=True)
+
+    value = n * args.steps / elapsed
+    k_ms = float(np.mean(kernel_ms))
+    ops = ops_per_draw(steps_em, n_obs) * n
+    achieved = ops / (k_ms * 1e-3) / 1e12
+    peak = VALU_PEAK_OPS / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "k_simulate<256,path>", "kernel_ms": round(k_ms, 4),
+                "ops_per_draw": ops_per_draw(steps_em, n_obs)}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        import oracle
+        ns = min(args.cpu_sample, n)
+        print(f"bench: cpu_baseline oracle on {ns} draws", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        oracle.abc(spec, y_obs, W.SAMPLING_SEED, 0, ns, oracle.EPS_FIXED, eps, capacity=0)
+        c1 = time.perf_counter()
+        cpu = {"value": round(ns / (c1 - c0), 1), "unit": "sims/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"draws [0, {ns}) of the same workload (FP64, OpenMP static partition)"}
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "sims/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "abc_logistic_sde_n1e7_S1000_fixed_eps", "n_draws": n,
+                   "em_steps": steps_em, "n_obs": n_obs, "eps": eps,
+                   "accepted": stats["n_accepted"]},
+        "sde_steps_per_s": round(value * steps_em, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

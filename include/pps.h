@@ -1,0 +1,215 @@
+/*
+ * pps.h -- prior-predictive sampling on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libpps.so.  The method is the one of Warne, Sisson & Drovandi,
+ * "Vector operations for accelerating expensive Bayesian computations -- a
+ * tutorial guide" (arXiv:1902.09046):
+ *
+ *   prior-predictive sampling (Sec. 3.1, Eq. ppd): for each draw i, theta_i ~
+ *   pi(theta), data D_i ~ s(D; theta_i), reduced to summaries S(D_i);
+ *   ABC rejection in its fixed-N form (Alg. 1 and the paragraph after it):
+ *   accept draws whose discrepancy rho(S(D_obs), S(D_i)) <= eps, eps fixed or
+ *   chosen a posteriori as a quantile of rho;
+ *   prior-predictive p-values under a family of priors pi(theta | lambda)
+ *   (Sec. 4.1, Eqs. pppv and pppvhype), here with a tail-area statistic.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an int status: PPS_OK (0), PPS_PENDING (> 0),
+ *     or a negative error.  On error, pps_last_error() returns a message for
+ *     the calling thread.  No call aborts the process.
+ *   - "device" pointers are HIP device allocations owned by the caller
+ *     (typically torch tensors' data_ptr()); "host" pointers are ordinary
+ *     host memory.  The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is stream-ordered; the synchronous calls block only for their
+ *     final small device-to-host copy and return with all their work done.
+ *   - Draw i uses its own Philox4x32-10 stream: key = (lo32 seed, hi32 seed),
+ *     counter = (block, purpose, lo32 i, hi32 i), purpose 0 = prior, 1 = path
+ *     (Sec. 2.5: independent streams; Philox from Salmon et al., SC'11).  So
+ *     the result of a draw depends only on (seed, i) and the model, never on
+ *     launch shape, batching or which other jobs share the GPU.
+ *   - Simulation runs in FP32 on the GPU; priors, p-values (counts) and ABC
+ *     posterior moments are FP64.
+ */
+#ifndef PPS_H
+#define PPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PPS_OK 0
+#define PPS_PENDING 1    /* pps_poll: the job has not finished yet */
+#define PPS_EINVAL (-1)  /* invalid argument (message in pps_last_error) */
+#define PPS_ENOMEM (-2)  /* device or host allocation failed */
+#define PPS_EDEVICE (-3) /* a HIP runtime call failed */
+#define PPS_EBUSY (-4)   /* server queue full: retry later */
+#define PPS_ENOTFOUND (-5) /* unknown job id */
+#define PPS_ETRUNC (-6)  /* more accepted draws than `capacity`: the first
+                            `capacity` (by draw index) were written and
+                            stats->n_accepted holds the true count */
+
+/* ---- model description (the "prior, simulator, discrepancy" of Alg. 1) -- */
+#define PPS_MAX_PARAMS 4
+#define PPS_MAX_OBS 64
+#define PPS_GARCH_LAGS 10
+#define PPS_GARCH_NSUMM 14 /* mean, variance, skewness, kurtosis, ACF(r^2) lags 1..10 */
+
+enum pps_family {
+    PPS_UNIFORM = 0,   /* U(a, b) */
+    PPS_NORMAL = 1,    /* N(mean a, sd b) */
+    PPS_LOGNORMAL = 2, /* exp(N(a, b^2)): b is the log-sd */
+    PPS_POINT = 3      /* point mass at a (a may be +inf) */
+};
+
+enum pps_model_kind {
+    /* dX = th1 X (1 - X/th2) dt + th3 X dW on [0, t_end], X(0) = x0, by
+     * Euler-Maruyama (Eq. gene_uv_SDE_EM) in increment form
+     *   X <- max(0, X + X (th1 dt - th1 dt X / th2 + th3 sqrt(dt) z)),
+     * dt = t_end/steps, observed after steps k*steps/n_obs, k = 1..n_obs.
+     * Summaries: the n_obs observations; statistic: their mean. */
+    PPS_LOGISTIC_SDE = 0,
+    /* GARCH(1,1) returns (the Gaussian case of the volatility models of
+     * Sec. 4.2): theta = (omega, alpha, beta), sigma2_1 = omega/(1-alpha-beta),
+     * r_t = sigma_t z_t, sigma2_{t+1} = omega + alpha r_t^2 + beta sigma2_t,
+     * t = 1..steps.  Summaries: the PPS_GARCH_NSUMM values above. */
+    PPS_GARCH11 = 1,
+    /* y_j = th1 + noise_sd z_j, j = 1..n_obs.  Summaries: the y_j;
+     * statistic: their mean. */
+    PPS_NORMAL_MEAN = 2
+};
+
+enum pps_constraint {
+    PPS_NO_CONSTRAINT = 0,
+    /* GARCH: reject alpha + beta >= 1 (decided in FP64) and redraw from the
+     * same draw's stream (attempt t uses prior blocks 8t + j), up to 32
+     * attempts. */
+    PPS_GARCH_STATIONARY = 1
+};
+
+typedef struct {
+    int32_t family; /* enum pps_family */
+    double a, b;
+} pps_prior;
+
+typedef struct {
+    int32_t model;    /* enum pps_model_kind */
+    int32_t n_params; /* 1..PPS_MAX_PARAMS (logistic and GARCH: 3) */
+    pps_prior prior[PPS_MAX_PARAMS];
+    int32_t constraint; /* enum pps_constraint */
+    double x0;          /* logistic: X(0) */
+    double t_end;       /* logistic: final time T */
+    int32_t steps;      /* logistic: EM steps (multiple of n_obs); GARCH: series length (> 10) */
+    int32_t n_obs;      /* logistic / normal-mean: observations (1..PPS_MAX_OBS) */
+    double noise_sd;    /* normal-mean: observation sd */
+} pps_model;
+
+typedef struct {
+    uint64_t n_draws;    /* N >= 1 */
+    uint64_t first_draw; /* draws i in [first_draw, first_draw + n_draws) */
+    uint64_t seed;
+} pps_sampling;
+
+/* ---- random streams ----------------------------------------------------- */
+
+/* Raw Philox4x32-10 output: for q in [0, n) the 4 words of block `block`,
+ * purpose `purpose` of draw first_draw + q, written to out[4q .. 4q+3].
+ * out: device, 4*n uint32.  Errors: PPS_EINVAL for n == 0 or out == NULL. */
+int pps_philox(uint64_t seed, uint64_t first_draw, uint64_t n, uint32_t block,
+               uint32_t purpose, uint32_t *out, void *stream);
+
+/* FP32 path normals z_0 .. z_{m-1} of each draw (normal k from path block
+ * k/4 by Box-Muller: words (0,1) -> z_{4b}, z_{4b+1}; (2,3) -> z_{4b+2},
+ * z_{4b+3}; uniforms u = (2 (w >> 9) + 1) 2^-24).  out: device, m*n floats,
+ * out[k*n + q] (SoA).  Errors: PPS_EINVAL for n == 0, m == 0, out == NULL. */
+int pps_normals(uint64_t seed, uint64_t first_draw, uint64_t n, uint32_t m, float *out,
+                void *stream);
+
+/* ---- per-draw prior-predictive output (Eq. ppd; Alg. 1 steps 1-2) ------- */
+
+/* Simulates draws [first_draw, first_draw + n_draws) and writes, per draw q:
+ *   theta[j*n + q]  the prior draw (FP32; FP64 draw rounded), j < n_params;
+ *   summ[k*n + q]   summary k (logistic: observation k; GARCH: the 14
+ *                   summaries; normal-mean: y_k);
+ *   stat[q]         the mean of the observations (not for GARCH; may be NULL);
+ *   dist[q]         Euclidean distance to y_obs (only when y_obs != NULL;
+ *                   else may be NULL).
+ * y_obs: host, n_summaries doubles, or NULL.  theta and summ: device, may be
+ * NULL to skip.  Errors: PPS_EINVAL (bad model, N == 0). */
+int pps_simulate(const pps_model *model, const pps_sampling *sampling, const double *y_obs,
+                 float *theta, float *summ, float *stat, float *dist, void *stream);
+
+/* Number of summaries a model produces (n_obs, or PPS_GARCH_NSUMM), or a
+ * negative status for an invalid model. */
+int pps_n_summaries(const pps_model *model);
+
+/* ---- ABC rejection, fixed-N form (Alg. 1 and the paragraph after it) ---- */
+enum pps_eps_mode {
+    PPS_EPS_FIXED = 0,       /* accept rho <= eps (compared in FP64) */
+    PPS_EPS_TOP_FRACTION = 1 /* accept the k = ceil(frac N) smallest (rho, i),
+                                ties by lower i; eps_used = the k-th smallest rho */
+};
+
+typedef struct {
+    uint64_t n_accepted;          /* true count, even when truncated */
+    double eps_used;              /* eps, or the k-th smallest rho */
+    double mean[PPS_MAX_PARAMS];  /* FP64 posterior mean of accepted theta */
+    double var[PPS_MAX_PARAMS];   /* FP64 unbiased variance (NaN if < 2 accepted) */
+} pps_abc_stats;
+
+/* y_obs: host, n_summaries doubles (the observed summaries S(D_obs)).
+ * Accepted draws are written in increasing draw index:
+ *   acc_idx[r] (device uint64), acc_theta[j*capacity + r] (device float,
+ *   SoA), acc_dist[r] (device float), for r < min(n_accepted, capacity).
+ * The output pointers may be NULL when capacity == 0.  stats: host.
+ * Returns PPS_OK, PPS_ETRUNC (see above), PPS_EINVAL or PPS_EDEVICE. */
+int abc_sample(const pps_model *model, const double *y_obs, const pps_sampling *sampling,
+               int eps_mode, double eps_or_frac, uint64_t capacity, uint64_t *acc_idx,
+               float *acc_theta, float *acc_dist, pps_abc_stats *stats, void *stream);
+
+/* ---- prior-predictive p-values over a lambda grid (Eq. pppvhype) -------- */
+
+/* For each lambda_k, parameter `lambda_param` gets the prior
+ * (lambda_family, a = model->prior[lambda_param].a, b = lambda_k); the other
+ * priors are unchanged.  Every lambda_k uses the same draws and random
+ * numbers (common random numbers).  count_ge[k] = #{i : T_i >= t_obs} with
+ * T_i the mean of draw i's observations (compared in FP64) and
+ * pvalue[k] = count_ge[k] / N.  All lambda values run in one launch.
+ * lambda, count_ge, pvalue: host arrays of n_lambda (1..4096).
+ * Not for GARCH (use pps_summary_tally). */
+int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_family,
+                      const double *lambda, int n_lambda, const pps_sampling *sampling,
+                      double t_obs, uint64_t *count_ge, double *pvalue, void *stream);
+
+/* Per-summary tail-area counts (the prior-predictive check of a summary
+ * vector): count_ge[s] = #{i : S_s(D_i) >= obs_summ[s]}, s < n_summaries.
+ * obs_summ, count_ge: host. */
+int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
+                      const double *obs_summ, uint64_t *count_ge, void *stream);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* Kernel timing.  While enabled (process-wide; off by default) every call
+ * that launches the simulation kernel records a HIP event pair around that
+ * kernel on the caller's stream; pps_last_kernel_ms() then returns the
+ * kernel's duration in milliseconds for the most recent such call on the
+ * current device, or a negative value if none was timed.  Returns PPS_OK. */
+int pps_set_timing(int enable);
+double pps_last_kernel_ms(void);
+
+/* ---- errors ------------------------------------------------------------- */
+const char *pps_strerror(int status);
+const char *pps_last_error(void); /* thread-local; "" when none */
+
+/* Library version string. */
+const char *pps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPS_H */

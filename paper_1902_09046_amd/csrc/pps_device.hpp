@@ -1,0 +1,158 @@
+// Device building blocks of the prior-predictive sampler (gfx950):
+// counter-based random streams, prior draws and the per-draw simulators.
+// One lane owns one draw; all model state lives in VGPRs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pps_internal.hpp"
+
+namespace pps {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round multiplies
+// counter words 0 and 2 by the two Philox multipliers, swaps the halves and
+// xors in the key; the key advances by the Weyl increments between rounds.
+// The key is the seed and is wave-uniform, so its schedule lives in SGPRs.
+// ---------------------------------------------------------------------------
+struct Words4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+enum : uint32_t { PURPOSE_PRIOR = 0, PURPOSE_PATH = 1 };
+
+struct StreamKey {
+    uint32_t k0, k1;  // (lo32 seed, hi32 seed)
+};
+
+__device__ __forceinline__ StreamKey make_key(uint64_t seed)
+{
+    return {static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)};
+}
+
+__device__ __forceinline__ Words4 stream_block(StreamKey key, uint64_t draw, uint32_t block,
+                                               uint32_t purpose)
+{
+    return philox4x32_10(block, purpose, static_cast<uint32_t>(draw),
+                         static_cast<uint32_t>(draw >> 32), key.k0, key.k1);
+}
+
+// ---------------------------------------------------------------------------
+// Uniforms on the open unit interval: the top 23 bits pick the cell midpoint
+// (2k+1) 2^-24; exact in FP32 and FP64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float uniform_f32(uint32_t w)
+{
+    return __builtin_fmaf(static_cast<float>(w >> 9), 0x1p-23f, 0x1p-24f);
+}
+
+__device__ __forceinline__ double uniform_f64(uint32_t w)
+{
+    return static_cast<double>(w >> 9) * 0x1p-23 + 0x1p-24;
+}
+
+// Box-Muller in FP32 with the hardware transcendentals: v_log_f32 is log2,
+// v_sin_f32 / v_cos_f32 take their argument in revolutions (x -> sin(2 pi x)),
+// so the angle 2 pi u1 needs no range reduction.
+__device__ __forceinline__ void box_muller_f32(uint32_t w0, uint32_t w1, float &z0, float &z1)
+{
+    const float u0 = uniform_f32(w0);
+    const float u1 = uniform_f32(w1);
+    // -2 ln u0 = log2(u0) * (-2 ln 2)
+    const float r = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(u0) * -1.38629436111989061883f);
+    z0 = r * __builtin_amdgcn_cosf(u1);
+    z1 = r * __builtin_amdgcn_sinf(u1);
+}
+
+// FP64 Box-Muller (prior draws only: once per parameter per draw).
+__device__ __forceinline__ double box_muller_f64_first(uint32_t w0, uint32_t w1)
+{
+    const double u0 = uniform_f64(w0);
+    const double u1 = uniform_f64(w1);
+    return sqrt(-2.0 * log(u0)) * cos(6.283185307179586476925286766559 * u1);
+}
+
+// Four path normals z_{4b..4b+3} of one draw.
+__device__ __forceinline__ void path_normals4(StreamKey key, uint64_t draw, uint32_t block,
+                                              float &z0, float &z1, float &z2, float &z3)
+{
+    const Words4 w = stream_block(key, draw, block, PURPOSE_PATH);
+    box_muller_f32(w.x, w.y, z0, z1);
+    box_muller_f32(w.z, w.w, z2, z3);
+}
+
+// ---------------------------------------------------------------------------
+// Prior draws (FP64).  Parameter j of attempt t uses PRIOR block 8t + j:
+// uniform from word 0, normal / log-normal from words (0, 1).  The uniform
+// transform is written with explicit round-to-nearest operations so that the
+// GARCH constraint is decided exactly as an unfused IEEE evaluation.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double prior_value(const PriorDev &p, StreamKey key, uint64_t draw,
+                                              int j, int attempt)
+{
+    if (p.family == PPS_POINT)
+        return p.a;
+    const Words4 w = stream_block(key, draw, static_cast<uint32_t>(8 * attempt + j), PURPOSE_PRIOR);
+    if (p.family == PPS_UNIFORM)
+        return __dadd_rn(p.a, __dmul_rn(__dsub_rn(p.b, p.a), uniform_f64(w.x)));
+    const double z = box_muller_f64_first(w.x, w.y);
+    const double v = __dadd_rn(p.a, __dmul_rn(p.b, z));
+    return p.family == PPS_LOGNORMAL ? exp(v) : v;
+}
+
+constexpr int MAX_PRIOR_ATTEMPTS = 32;
+
+// theta ~ pi(theta); with the GARCH constraint, attempts whose
+// theta[1] + theta[2] >= 1 are redrawn (the last attempt is kept after 32).
+__device__ __forceinline__ void prior_draw(const PriorDev *prior, int n_params, int constraint,
+                                           StreamKey key, uint64_t draw, double *theta)
+{
+    for (int attempt = 0;; ++attempt) {
+        for (int j = 0; j < n_params; ++j)
+            theta[j] = prior_value(prior[j], key, draw, j, attempt);
+        if (constraint != PPS_GARCH_STATIONARY)
+            return;
+        if (__dadd_rn(theta[1], theta[2]) < 1.0 || attempt + 1 == MAX_PRIOR_ATTEMPTS)
+            return;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compensated (Kahan) FP32 accumulation: sum = s - c.
+// ---------------------------------------------------------------------------
+struct Kahan {
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float v)
+    {
+        const float y = v - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const
+    {
+        return static_cast<double>(s) - static_cast<double>(c);
+    }
+};
+
+}  // namespace pps

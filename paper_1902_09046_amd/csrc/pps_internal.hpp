@@ -1,0 +1,122 @@
+// Internal structures shared by the host runtime and the HIP kernels of
+// libpps.  Not part of the public ABI (see include/pps.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pps.h"
+
+namespace pps {
+
+// Job flags: what a job does with each simulated draw.
+enum : int32_t {
+    JOB_WRITE_DIST = 1 << 0,  // write rho_i to job.dist (ABC)
+    JOB_TALLY_STAT = 1 << 1,  // count T_i >= t_obs into job.counts[0] (p-value)
+    JOB_TALLY_SUMM = 1 << 2,  // count S_s(D_i) >= summ_obs[s] into job.counts[s]
+    JOB_DUMP = 1 << 3,        // write theta / summaries / stat / dist per draw
+};
+
+// Model classes compiled into separate simulation kernels.
+enum : int { CLASS_PATH = 0, CLASS_GARCH = 1 };
+
+struct PriorDev {
+    int32_t family;
+    int32_t pad;
+    double a, b;
+};
+
+// One row of the device job table.  A launch processes the tiles
+// [tile_begin, tile_begin + n_tiles) of the launch's global tile range for
+// this job; local tile t of the job covers draws
+// [t * tile_size, (t + 1) * tile_size) of the job, clipped to n_draws.
+struct alignas(16) JobDev {
+    int32_t model;
+    int32_t flags;
+    int32_t n_params;
+    int32_t n_summ;
+    int32_t steps;
+    int32_t obs_stride;
+    int32_t constraint;
+    int32_t tile_size;
+    uint64_t seed;
+    uint64_t first_draw;
+    uint64_t n_draws;
+    uint64_t tile_begin;   // first global tile id of this row in the launch
+    uint64_t n_tiles;      // tiles of this row in the launch
+    uint64_t tile_offset;  // first local tile of the job processed in the launch
+    PriorDev prior[PPS_MAX_PARAMS];
+    double x0;
+    double dt;
+    double noise_sd;
+    double t_obs;
+    double summ_obs[PPS_GARCH_NSUMM];
+    float y_obs[PPS_MAX_OBS];
+    float *dist;                 // JOB_WRITE_DIST: n_draws floats
+    unsigned long long *counts;  // tallies
+    float *dump_theta;           // JOB_DUMP outputs (SoA, stride n_draws), may be null
+    float *dump_summ;
+    float *dump_stat;
+    float *dump_dist;
+    unsigned int *tiles_done;    // optional: incremented once per finished tile
+    uint32_t lambda_group;       // rows sharing draws under common random numbers
+    uint32_t pad2;
+};
+
+// Device-side launch state (reset by a kernel before each launch).
+struct alignas(64) LaunchState {
+    unsigned long long next_tile;
+    unsigned long long pad[7];
+};
+
+// ---- ABC finalisation (select / compaction / moments) -------------------
+
+// Elements per compaction / histogram workgroup: 4 waves x 16 rows x 64.
+constexpr int FIN_BLOCK = 256;
+constexpr int FIN_ROWS = 16;
+constexpr int FIN_TILE = FIN_BLOCK * FIN_ROWS;
+constexpr int SEL_BITS0 = 11, SEL_BITS1 = 11, SEL_BITS2 = 10;
+constexpr int SEL_BINS = 1 << 11;
+
+struct alignas(16) FinJob {
+    const float *dist;          // rho_i, n floats
+    uint64_t n;
+    uint64_t first_draw;
+    uint64_t seed;
+    int32_t mode;               // PPS_EPS_FIXED / PPS_EPS_TOP_FRACTION
+    int32_t n_params;
+    int32_t constraint;
+    int32_t pad;
+    double eps;                 // FIXED threshold
+    uint64_t k;                 // TOP_FRACTION: number to accept
+    uint64_t capacity;
+    uint64_t block_begin;       // first global finalisation block of this job
+    uint64_t n_blocks;
+    PriorDev prior[PPS_MAX_PARAMS];
+    uint64_t *acc_idx;
+    float *acc_theta;
+    float *acc_dist;
+    // scratch (device, owned by the library)
+    unsigned int *hist;         // SEL_BINS counters
+    unsigned long long *block_counts;  // 2 * n_blocks: (lt, eq) per block, then offsets
+    double *partials;           // n_blocks * (1 + 2 * n_params): (n, mean[], m2[])
+    struct FinResult *result;   // device result row
+};
+
+struct alignas(16) FinResult {
+    uint64_t n_accepted;
+    double eps_used;
+    double mean[PPS_MAX_PARAMS];
+    double var[PPS_MAX_PARAMS];
+    // select state
+    uint32_t sel_prefix;
+    uint32_t sel_mask;
+    uint64_t sel_rank;          // rank (1-based) still to find among matching
+    uint64_t lt_total;
+    uint64_t eq_total;
+    uint64_t quota;             // ties (rho == threshold) to accept
+    uint32_t thresh_bits;
+    uint32_t pad;
+};
+
+}  // namespace pps

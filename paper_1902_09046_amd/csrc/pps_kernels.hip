@@ -1,0 +1,878 @@
+// HIP kernels of the prior-predictive sampler for gfx950 (MI355X).
+//
+// k_simulate      persistent tile-queue kernel: one lane per prior draw;
+//                 theta ~ prior (FP64, rounded to FP32), then the model
+//                 simulated in VGPRs with its Philox stream regenerated in
+//                 registers (no random-number buffers), then per-draw
+//                 epilogues: rho to HBM (ABC), tail-area tallies by wave
+//                 ballot + popcount (p-values), or a full per-draw dump.
+// k_sel_*         radix select of the k-th smallest rho on its FP32 bit
+//                 pattern (rho >= 0, so bit order = value order): 11/11/10
+//                 bit digits, LDS histograms merged into a global histogram.
+// k_compact_*     ordered stream compaction of accepted draws (wave ballot +
+//                 mbcnt rank, LDS prefix over waves, scanned block offsets),
+//                 so records come out in increasing draw index with no sort.
+// k_moments_final FP64 posterior mean / variance of the accepted theta from
+//                 per-block (n, mean, M2) partials combined in block order.
+#include <hip/hip_runtime.h>
+
+#include "pps_device.hpp"
+#include "pps_internal.hpp"
+#include "pps_launch.hpp"
+
+namespace pps {
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// ===========================================================================
+// Per-draw simulators.  Each returns the summaries the epilogue needs.
+// ===========================================================================
+
+// Stochastic logistic SDE by Euler-Maruyama, increment form, absorbed at 0:
+//   X <- max(0, X + X (a - b X + c z)), a = th1 dt, b = th1 dt / th2,
+//   c = th3 sqrt(dt).  Observation k = X after step k * stride.
+// Accumulates rho^2 = sum_k (X_k - y_k)^2 and sum_k X_k with Kahan sums.
+template <bool DUMP>
+__device__ __forceinline__ void sim_logistic(const JobDev *__restrict__ J, StreamKey key,
+                                             uint64_t draw, const double *theta, uint64_t q,
+                                             bool valid, Kahan &d2, Kahan &sum)
+{
+    const double dt = J->dt;
+    const float a = static_cast<float>(theta[0] * dt);
+    const float b = static_cast<float>(theta[0] * dt / theta[1]);
+    const float c = static_cast<float>(theta[2] * sqrt(dt));
+    const int steps = J->steps;
+    const int stride = J->obs_stride;
+    const uint64_t n = J->n_draws;
+    float x = static_cast<float>(J->x0);
+    int next_obs = stride;
+    int k = 0;
+    const int nblk = (steps + 3) >> 2;
+    for (int blk = 0; blk < nblk; ++blk) {
+        float z[4];
+        path_normals4(key, draw, static_cast<uint32_t>(blk), z[0], z[1], z[2], z[3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int step = 4 * blk + j + 1;  // steps done after this update
+            if (step > steps)
+                break;
+            float g = __builtin_fmaf(-b, x, a);
+            g = __builtin_fmaf(c, z[j], g);
+            x = __builtin_fmaxf(__builtin_fmaf(x, g, x), 0.0f);
+            if (step == next_obs) {
+                const float diff = x - J->y_obs[k];
+                d2.add(diff * diff);
+                sum.add(x);
+                if (DUMP && valid && J->dump_summ)
+                    J->dump_summ[static_cast<uint64_t>(k) * n + q] = x;
+                ++k;
+                next_obs += stride;
+            }
+        }
+    }
+}
+
+// Normal-mean model: y_j = mu + sd z_j.
+template <bool DUMP>
+__device__ __forceinline__ void sim_normal_mean(const JobDev *__restrict__ J, StreamKey key,
+                                                uint64_t draw, const double *theta, uint64_t q,
+                                                bool valid, Kahan &d2, Kahan &sum)
+{
+    const float mu = static_cast<float>(theta[0]);
+    const float sd = static_cast<float>(J->noise_sd);
+    const int m = J->n_summ;
+    const uint64_t n = J->n_draws;
+    const int nblk = (m + 3) >> 2;
+    for (int blk = 0; blk < nblk; ++blk) {
+        float z[4];
+        path_normals4(key, draw, static_cast<uint32_t>(blk), z[0], z[1], z[2], z[3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * blk + j;
+            if (k >= m)
+                break;
+            const float y = __builtin_fmaf(sd, z[j], mu);
+            const float diff = y - J->y_obs[k];
+            d2.add(diff * diff);
+            sum.add(y);
+            if (DUMP && valid && J->dump_summ)
+                J->dump_summ[static_cast<uint64_t>(k) * n + q] = y;
+        }
+    }
+}
+
+// GARCH(1,1) in scaled form: with sbar^2 = omega/(1-alpha-beta) and
+// s_t = r_t / sbar, h_t = sigma2_t / sbar^2:
+//   h_1 = 1,  s_t = sqrt(h_t) z_t,  h_{t+1} = (1-alpha-beta) + alpha s_t^2 + beta h_t.
+// Streaming summaries: plain FP32 sums over 20-step blocks folded into Kahan
+// totals; b_t = s_t^2 - 1 kept in a 10-deep register ring for the lag
+// products; the first and last 10 b_t give the ACF centring terms.  The
+// closing algebra is FP64.  Requires the length to be a multiple of 20.
+__device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKey key,
+                                          uint64_t draw, const double *theta, double *summ)
+{
+    const double alpha_d = theta[1], beta_d = theta[2];
+    const double oab = 1.0 - alpha_d - beta_d;
+    const float om = static_cast<float>(oab);
+    const float al = static_cast<float>(alpha_d);
+    const float be = static_cast<float>(beta_d);
+    const int len = J->steps;
+    float h = 1.0f;
+    Kahan K1, K2, K3, K4, KL[PPS_GARCH_LAGS];
+    float ring[PPS_GARCH_LAGS];
+    float head[PPS_GARCH_LAGS];
+#pragma unroll
+    for (int k = 0; k < PPS_GARCH_LAGS; ++k) {
+        ring[k] = 0.0f;
+        head[k] = 0.0f;
+    }
+    const int nblk20 = len / 20;
+    for (int blk = 0; blk < nblk20; ++blk) {
+        float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, s4 = 0.0f;
+        float lag[PPS_GARCH_LAGS];
+#pragma unroll
+        for (int k = 0; k < PPS_GARCH_LAGS; ++k)
+            lag[k] = 0.0f;
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            float z[4];
+            path_normals4(key, draw, static_cast<uint32_t>(blk * 5 + p), z[0], z[1], z[2], z[3]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int jj = 4 * p + j;  // position in the 20-step block
+                const float s = __builtin_amdgcn_sqrtf(h) * z[j];
+                const float sq = s * s;
+                h = __builtin_fmaf(al, sq, __builtin_fmaf(be, h, om));
+                s1 += s;
+                s2 += sq;
+                s3 = __builtin_fmaf(sq, s, s3);
+                s4 = __builtin_fmaf(sq, sq, s4);
+                const float bt = sq - 1.0f;
+#pragma unroll
+                for (int k = 1; k <= PPS_GARCH_LAGS; ++k)
+                    lag[k - 1] = __builtin_fmaf(bt, ring[(jj - k + 20) % 10], lag[k - 1]);
+                ring[jj % 10] = bt;
+                if (jj < 10 && blk == 0)
+                    head[jj] = bt;
+            }
+        }
+        K1.add(s1);
+        K2.add(s2);
+        K3.add(s3);
+        K4.add(s4);
+#pragma unroll
+        for (int k = 0; k < PPS_GARCH_LAGS; ++k)
+            KL[k].add(lag[k]);
+    }
+    // Closing algebra in FP64.
+    const double T = static_cast<double>(len);
+    const double S1 = K1.value(), S2 = K2.value(), S3 = K3.value(), S4 = K4.value();
+    const double m = S1 / T, e2 = S2 / T, e3 = S3 / T, e4 = S4 / T;
+    const double m2 = e2 - m * m;
+    const double m3 = e3 - 3.0 * m * e2 + 2.0 * m * m * m;
+    const double m4 = e4 - 4.0 * m * e3 + 6.0 * m * m * e2 - 3.0 * m * m * m * m;
+    const double sbar2 = theta[0] / oab;
+    summ[0] = sqrt(sbar2) * m;
+    summ[1] = sbar2 * m2;
+    summ[2] = m3 / (m2 * sqrt(m2));
+    summ[3] = m4 / (m2 * m2);
+    // ACF of r^2: a_t - abar = sbar^2 (b_t - bbar), bbar = S2/T - 1.
+    const double B = S2 - T;
+    const double bbar = B / T;
+    const double den = (S4 - 2.0 * S2 + T) - T * bbar * bbar;
+    // tail_k = sum of the last k b_t: b_{len-m} sits in ring[(len-m) % 10],
+    // and len is a multiple of 20, so b_{len-m} = ring[(20-m) % 10].
+    double headk = 0.0, tailk = 0.0;
+#pragma unroll
+    for (int k = 1; k <= PPS_GARCH_LAGS; ++k) {
+        headk += static_cast<double>(head[k - 1]);
+        tailk += static_cast<double>(ring[(20 - k) % 10]);
+        const double num = KL[k - 1].value() - bbar * ((B - tailk) + (B - headk)) +
+                           (T - k) * bbar * bbar;
+        summ[3 + k] = num / den;
+    }
+}
+
+// ===========================================================================
+// Persistent simulation kernel.
+// ===========================================================================
+// CLASS selects the model family compiled into this instance, so that each
+// family gets its own register allocation: CLASS_PATH = logistic SDE and
+// normal-mean (short per-draw state), CLASS_GARCH = GARCH(1,1) (summary ring).
+template <int BLOCK, int CLASS>
+__global__ __launch_bounds__(BLOCK) void k_simulate(const JobDev *__restrict__ jobs, int n_jobs,
+                                                    uint64_t total_tiles,
+                                                    LaunchState *__restrict__ state)
+{
+    constexpr int NW = BLOCK / 64;
+    __shared__ unsigned long long s_tile;
+    __shared__ unsigned s_cnt[PPS_GARCH_NSUMM][NW];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    for (;;) {
+        if (tid == 0)
+            s_tile = atomicAdd(&state->next_tile, 1ull);
+        __syncthreads();
+        const uint64_t t = uniform_u64(s_tile);
+        __syncthreads();
+        if (t >= total_tiles)
+            break;
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const JobDev *__restrict__ J = jobs + lo;
+        const int flags = J->flags;
+        const uint64_t n = J->n_draws;
+        const uint64_t q0 = (t - J->tile_begin + J->tile_offset) * static_cast<uint64_t>(J->tile_size);
+        const uint64_t q = q0 + static_cast<uint64_t>(tid);
+        const bool valid = q < n;
+        const bool wave_live = q0 + static_cast<uint64_t>(wave) * 64 < n;
+        const uint64_t draw = J->first_draw + q;
+        const StreamKey key = make_key(J->seed);
+
+        double theta[PPS_MAX_PARAMS] = {0.0, 0.0, 0.0, 0.0};
+        double summ[PPS_GARCH_NSUMM];
+        Kahan d2, sum;
+        const int model = J->model;
+        if (wave_live) {
+            prior_draw(J->prior, J->n_params, J->constraint, key, draw, theta);
+            if constexpr (CLASS == CLASS_GARCH) {
+                sim_garch(J, key, draw, theta, summ);
+            } else if (model == PPS_LOGISTIC_SDE) {
+                if (flags & JOB_DUMP)
+                    sim_logistic<true>(J, key, draw, theta, q, valid, d2, sum);
+                else
+                    sim_logistic<false>(J, key, draw, theta, q, valid, d2, sum);
+            } else {
+                if (flags & JOB_DUMP)
+                    sim_normal_mean<true>(J, key, draw, theta, q, valid, d2, sum);
+                else
+                    sim_normal_mean<false>(J, key, draw, theta, q, valid, d2, sum);
+            }
+        }
+        constexpr bool garch = CLASS == CLASS_GARCH;
+        (void)model;
+        const float dist = garch ? 0.0f : static_cast<float>(sqrt(d2.value()));
+        const double stat = garch ? 0.0 : sum.value() / static_cast<double>(J->n_summ);
+
+        if ((flags & JOB_WRITE_DIST) && valid)
+            J->dist[q] = dist;
+        if ((flags & JOB_DUMP) && valid) {
+            if (J->dump_theta)
+                for (int j = 0; j < J->n_params; ++j)
+                    J->dump_theta[static_cast<uint64_t>(j) * n + q] = static_cast<float>(theta[j]);
+            if (garch && J->dump_summ)
+                for (int s = 0; s < PPS_GARCH_NSUMM; ++s)
+                    J->dump_summ[static_cast<uint64_t>(s) * n + q] = static_cast<float>(summ[s]);
+            if (!garch && J->dump_stat)
+                J->dump_stat[q] = static_cast<float>(stat);
+            if (!garch && J->dump_dist)
+                J->dump_dist[q] = dist;
+        }
+        if (flags & (JOB_TALLY_STAT | JOB_TALLY_SUMM)) {
+            const int ns = (flags & JOB_TALLY_SUMM) ? (garch ? PPS_GARCH_NSUMM : 0) : 1;
+            for (int s = 0; s < ns; ++s) {
+                const double v = (flags & JOB_TALLY_SUMM) ? summ[s] : stat;
+                const double ref = (flags & JOB_TALLY_SUMM) ? J->summ_obs[s] : J->t_obs;
+                const uint64_t m = __ballot(valid && v >= ref);
+                if (lane_id() == 0)
+                    s_cnt[s][wave] = static_cast<unsigned>(__popcll(m));
+            }
+            __syncthreads();
+            if (tid < ns) {
+                unsigned tot = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+                    tot += s_cnt[tid][w];
+                if (tot)
+                    atomicAdd(&J->counts[tid], static_cast<unsigned long long>(tot));
+            }
+        }
+    }
+}
+
+__global__ void k_reset_state(LaunchState *state)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        state->next_tile = 0;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v)
+{
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+// ===========================================================================
+// Random-stream dumps.
+// ===========================================================================
+__global__ void k_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t block,
+                         uint32_t purpose, uint32_t *__restrict__ out)
+{
+    const StreamKey key = make_key(seed);
+    for (uint64_t q = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; q < n;
+         q += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const Words4 w = stream_block(key, first + q, block, purpose);
+        uint4 v;
+        v.x = w.x;
+        v.y = w.y;
+        v.z = w.z;
+        v.w = w.w;
+        reinterpret_cast<uint4 *>(out)[q] = v;
+    }
+}
+
+__global__ void k_normals(uint64_t seed, uint64_t first, uint64_t n, uint32_t m,
+                          float *__restrict__ out)
+{
+    const StreamKey key = make_key(seed);
+    for (uint64_t q = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; q < n;
+         q += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        for (uint32_t b = 0; 4 * b < m; ++b) {
+            float z[4];
+            path_normals4(key, first + q, b, z[0], z[1], z[2], z[3]);
+            for (uint32_t j = 0; j < 4 && 4 * b + j < m; ++j)
+                out[static_cast<uint64_t>(4 * b + j) * n + q] = z[j];
+        }
+    }
+}
+
+// ===========================================================================
+// ABC finalisation.
+// ===========================================================================
+__device__ __forceinline__ int fin_locate(const FinJob *__restrict__ fins, int n_fins, uint64_t b)
+{
+    int lo = 0, hi = n_fins - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fins[mid].block_begin <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void sel_digit(int pass, int &shift, int &bits)
+{
+    if (pass == 0) {
+        shift = 32 - SEL_BITS0;
+        bits = SEL_BITS0;
+    } else if (pass == 1) {
+        shift = 32 - SEL_BITS0 - SEL_BITS1;
+        bits = SEL_BITS1;
+    } else {
+        shift = 0;
+        bits = SEL_BITS2;
+    }
+}
+
+// One block per job: reset the select state and zero the histogram.
+__global__ __launch_bounds__(FIN_BLOCK) void k_fin_init(const FinJob *__restrict__ fins)
+{
+    const FinJob *F = fins + blockIdx.x;
+    for (int i = threadIdx.x; i < SEL_BINS; i += FIN_BLOCK)
+        F->hist[i] = 0;
+    if (threadIdx.x == 0) {
+        FinResult *R = F->result;
+        R->sel_prefix = 0;
+        R->sel_mask = 0;
+        R->sel_rank = F->k;
+        R->thresh_bits = 0;
+        R->quota = 0;
+        R->lt_total = 0;
+        R->eq_total = 0;
+        R->n_accepted = 0;
+    }
+}
+
+__global__ __launch_bounds__(FIN_BLOCK) void k_sel_hist(const FinJob *__restrict__ fins,
+                                                         int n_fins, int pass)
+{
+    __shared__ unsigned h[SEL_BINS];
+    const int jb = fin_locate(fins, n_fins, blockIdx.x);
+    const FinJob *F = fins + jb;
+    if (F->mode != PPS_EPS_TOP_FRACTION)
+        return;
+    int shift, bits;
+    sel_digit(pass, shift, bits);
+    const uint32_t dmask = (1u << bits) - 1u;
+    const uint32_t prefix = F->result->sel_prefix;
+    const uint32_t pmask = F->result->sel_mask;
+    for (int i = threadIdx.x; i < SEL_BINS; i += FIN_BLOCK)
+        h[i] = 0;
+    __syncthreads();
+    const uint64_t base = (blockIdx.x - F->block_begin) * static_cast<uint64_t>(FIN_TILE);
+    const uint32_t *d = reinterpret_cast<const uint32_t *>(F->dist);
+#pragma unroll 4
+    for (int r = 0; r < FIN_ROWS; ++r) {
+        const uint64_t e = base + static_cast<uint64_t>(r) * FIN_BLOCK + threadIdx.x;
+        if (e < F->n) {
+            const uint32_t v = d[e];
+            if ((v & pmask) == prefix)
+                atomicAdd(&h[(v >> shift) & dmask], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= static_cast<int>(dmask); i += FIN_BLOCK)
+        if (h[i])
+            atomicAdd(&F->hist[i], h[i]);
+}
+
+// One block per job: find the digit holding the rank still sought.
+__global__ __launch_bounds__(FIN_BLOCK) void k_sel_pick(const FinJob *__restrict__ fins, int pass)
+{
+    __shared__ unsigned long long s_sum[FIN_BLOCK];
+    const FinJob *F = fins + blockIdx.x;
+    if (F->mode != PPS_EPS_TOP_FRACTION)
+        return;
+    FinResult *R = F->result;
+    int shift, bits;
+    sel_digit(pass, shift, bits);
+    const int nb = 1 << bits;
+    const int per = nb / FIN_BLOCK;  // 8 or 4 bins per thread
+    const int b0 = threadIdx.x * per;
+    unsigned long long local = 0;
+    for (int i = 0; i < per; ++i)
+        local += F->hist[b0 + i];
+    s_sum[threadIdx.x] = local;
+    __syncthreads();
+    // inclusive Hillis-Steele scan over the per-thread sums
+    for (int off = 1; off < FIN_BLOCK; off <<= 1) {
+        const unsigned long long v = threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        s_sum[threadIdx.x] += v;
+        __syncthreads();
+    }
+    const uint64_t rank = R->sel_rank;
+    const unsigned long long incl = s_sum[threadIdx.x];
+    const unsigned long long before = incl - local;
+    __syncthreads();
+    if (before < rank && rank <= incl) {
+        unsigned long long cum = before;
+        for (int i = 0; i < per; ++i) {
+            const unsigned c = F->hist[b0 + i];
+            if (cum + c >= rank) {
+                R->sel_prefix |= static_cast<uint32_t>(b0 + i) << shift;
+                R->sel_mask |= static_cast<uint32_t>(nb - 1) << shift;
+                R->sel_rank = rank - cum;
+                break;
+            }
+            cum += c;
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < per; ++i)
+        F->hist[b0 + i] = 0;
+    if (pass == 2 && threadIdx.x == 0) {
+        __threadfence_block();
+        R->thresh_bits = R->sel_prefix;
+        R->quota = R->sel_rank;
+    }
+}
+
+__device__ __forceinline__ void fin_pred(const FinJob *F, uint32_t thresh, uint64_t e, bool &lt,
+                                         bool &eq, float &d)
+{
+    lt = false;
+    eq = false;
+    d = 0.0f;
+    if (e >= F->n)
+        return;
+    d = F->dist[e];
+    if (F->mode == PPS_EPS_FIXED) {
+        lt = static_cast<double>(d) <= F->eps;
+    } else {
+        const uint32_t v = __float_as_uint(d);
+        lt = v < thresh;
+        eq = v == thresh;
+    }
+}
+
+// Per block: (count rho "below", count "tied") over its FIN_TILE elements.
+__global__ __launch_bounds__(FIN_BLOCK) void k_compact_count(const FinJob *__restrict__ fins,
+                                                              int n_fins)
+{
+    __shared__ unsigned s_lt[FIN_BLOCK / 64], s_eq[FIN_BLOCK / 64];
+    const int jb = fin_locate(fins, n_fins, blockIdx.x);
+    const FinJob *F = fins + jb;
+    const uint64_t lb = blockIdx.x - F->block_begin;
+    const int wave = threadIdx.x >> 6;
+    const uint32_t thresh = F->result->thresh_bits;
+    const uint64_t wbase = lb * FIN_TILE + static_cast<uint64_t>(wave) * (FIN_ROWS * 64);
+    unsigned clt = 0, ceq = 0;
+#pragma unroll 4
+    for (int r = 0; r < FIN_ROWS; ++r) {
+        bool lt, eq;
+        float d;
+        fin_pred(F, thresh, wbase + r * 64 + lane_id(), lt, eq, d);
+        clt += __popcll(__ballot(lt));
+        ceq += __popcll(__ballot(eq));
+    }
+    if (lane_id() == 0) {
+        s_lt[wave] = clt;
+        s_eq[wave] = ceq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+        for (int w = 0; w < FIN_BLOCK / 64; ++w) {
+            a += s_lt[w];
+            b += s_eq[w];
+        }
+        F->block_counts[2 * lb] = a;
+        F->block_counts[2 * lb + 1] = b;
+    }
+}
+
+// One block per job: exclusive scan of the per-block (lt, eq) counts.
+__global__ __launch_bounds__(FIN_BLOCK) void k_compact_scan(const FinJob *__restrict__ fins)
+{
+    __shared__ unsigned long long s_a[FIN_BLOCK], s_b[FIN_BLOCK];
+    const FinJob *F = fins + blockIdx.x;
+    FinResult *R = F->result;
+    unsigned long long carry_a = 0, carry_b = 0;
+    for (uint64_t c0 = 0; c0 < F->n_blocks; c0 += FIN_BLOCK) {
+        const uint64_t i = c0 + threadIdx.x;
+        const unsigned long long a = i < F->n_blocks ? F->block_counts[2 * i] : 0ull;
+        const unsigned long long b = i < F->n_blocks ? F->block_counts[2 * i + 1] : 0ull;
+        s_a[threadIdx.x] = a;
+        s_b[threadIdx.x] = b;
+        __syncthreads();
+        for (int off = 1; off < FIN_BLOCK; off <<= 1) {
+            const unsigned long long va = threadIdx.x >= off ? s_a[threadIdx.x - off] : 0ull;
+            const unsigned long long vb = threadIdx.x >= off ? s_b[threadIdx.x - off] : 0ull;
+            __syncthreads();
+            s_a[threadIdx.x] += va;
+            s_b[threadIdx.x] += vb;
+            __syncthreads();
+        }
+        if (i < F->n_blocks) {
+            F->block_counts[2 * i] = carry_a + s_a[threadIdx.x] - a;
+            F->block_counts[2 * i + 1] = carry_b + s_b[threadIdx.x] - b;
+        }
+        carry_a += s_a[FIN_BLOCK - 1];
+        carry_b += s_b[FIN_BLOCK - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        R->lt_total = carry_a;
+        R->eq_total = carry_b;
+        const uint64_t take = F->mode == PPS_EPS_FIXED ? 0 : (carry_b < R->quota ? carry_b : R->quota);
+        R->n_accepted = carry_a + take;
+        R->eps_used = F->mode == PPS_EPS_FIXED ? F->eps
+                                               : static_cast<double>(__uint_as_float(R->thresh_bits));
+    }
+}
+
+struct Moments {
+    double n;
+    double mean[PPS_MAX_PARAMS];
+    double m2[PPS_MAX_PARAMS];
+};
+
+// Chan et al. pairwise update: a <- a (+) b (a first in index order).
+__device__ __forceinline__ void moments_merge(Moments &a, const Moments &b, int np)
+{
+    if (b.n == 0.0)
+        return;
+    if (a.n == 0.0) {
+        a = b;
+        return;
+    }
+    const double n = a.n + b.n;
+    for (int j = 0; j < np; ++j) {
+        const double delta = b.mean[j] - a.mean[j];
+        a.mean[j] += delta * (b.n / n);
+        a.m2[j] += b.m2[j] + delta * delta * (a.n * b.n / n);
+    }
+    a.n = n;
+}
+
+__device__ __forceinline__ Moments moments_shfl_down(const Moments &m, int off)
+{
+    Moments r;
+    r.n = __shfl_down(m.n, off);
+#pragma unroll
+    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+        r.mean[j] = __shfl_down(m.mean[j], off);
+        r.m2[j] = __shfl_down(m.m2[j], off);
+    }
+    return r;
+}
+
+constexpr int PARTIAL_STRIDE = 1 + 2 * PPS_MAX_PARAMS;
+
+// Writes accepted records in draw-index order and per-block moment partials.
+__global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const FinJob *__restrict__ fins,
+                                                              int n_fins)
+{
+    constexpr int NW = FIN_BLOCK / 64;
+    __shared__ unsigned s_lt[NW], s_eq[NW];
+    __shared__ Moments s_mom[NW];
+    const int jb = fin_locate(fins, n_fins, blockIdx.x);
+    const FinJob *F = fins + jb;
+    const FinResult *R = F->result;
+    const uint64_t lb = blockIdx.x - F->block_begin;
+    const int wave = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
+    const uint32_t thresh = R->thresh_bits;
+    const uint64_t quota = F->mode == PPS_EPS_FIXED ? 0 : R->quota;
+    const uint64_t wbase = lb * FIN_TILE + static_cast<uint64_t>(wave) * (FIN_ROWS * 64);
+    const int np = F->n_params;
+    // pass 1: this wave's totals, for the prefix over the block's waves
+    unsigned clt = 0, ceq = 0;
+    for (int r = 0; r < FIN_ROWS; ++r) {
+        bool lt, eq;
+        float d;
+        fin_pred(F, thresh, wbase + r * 64 + lane, lt, eq, d);
+        clt += __popcll(__ballot(lt));
+        ceq += __popcll(__ballot(eq));
+    }
+    if (lane == 0) {
+        s_lt[wave] = clt;
+        s_eq[wave] = ceq;
+    }
+    __syncthreads();
+    uint64_t lt_before = F->block_counts[2 * lb];
+    uint64_t eq_before = F->block_counts[2 * lb + 1];
+    for (int w = 0; w < wave; ++w) {
+        lt_before += s_lt[w];
+        eq_before += s_eq[w];
+    }
+    Moments mom;
+    mom.n = 0.0;
+    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+        mom.mean[j] = 0.0;
+        mom.m2[j] = 0.0;
+    }
+    const StreamKey key = make_key(F->seed);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // pass 2: ranks and writes
+    for (int r = 0; r < FIN_ROWS; ++r) {
+        const uint64_t e = wbase + r * 64 + lane;
+        bool lt, eq;
+        float d;
+        fin_pred(F, thresh, e, lt, eq, d);
+        const uint64_t mlt = __ballot(lt);
+        const uint64_t meq = __ballot(eq);
+        if (mlt | meq) {
+            const uint64_t my_lt = lt_before + __popcll(mlt & below);
+            const uint64_t my_eq = eq_before + __popcll(meq & below);
+            const bool acc = lt || (eq && my_eq < quota);
+            if (acc) {
+                const uint64_t pos = my_lt + (my_eq < quota ? my_eq : quota);
+                double theta[PPS_MAX_PARAMS];
+                prior_draw(F->prior, np, F->constraint, key, F->first_draw + e, theta);
+                if (pos < F->capacity) {
+                    F->acc_idx[pos] = F->first_draw + e;
+                    F->acc_dist[pos] = d;
+                    for (int j = 0; j < np; ++j)
+                        F->acc_theta[static_cast<uint64_t>(j) * F->capacity + pos] =
+                            static_cast<float>(theta[j]);
+                }
+                // Welford update in index order
+                mom.n += 1.0;
+                for (int j = 0; j < np; ++j) {
+                    const double delta = theta[j] - mom.mean[j];
+                    mom.mean[j] += delta / mom.n;
+                    mom.m2[j] += delta * (theta[j] - mom.mean[j]);
+                }
+            }
+            lt_before += __popcll(mlt);
+            eq_before += __popcll(meq);
+        }
+    }
+    // lanes -> wave (fixed tree order), waves -> block
+    for (int off = 1; off < 64; off <<= 1) {
+        const Moments other = moments_shfl_down(mom, off);
+        if ((lane & (2 * off - 1)) == 0)
+            moments_merge(mom, other, np);
+    }
+    if (lane == 0)
+        s_mom[wave] = mom;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Moments acc = s_mom[0];
+        for (int w = 1; w < NW; ++w)
+            moments_merge(acc, s_mom[w], np);
+        double *p = F->partials + lb * PARTIAL_STRIDE;
+        p[0] = acc.n;
+        for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+            p[1 + j] = acc.mean[j];
+            p[1 + PPS_MAX_PARAMS + j] = acc.m2[j];
+        }
+    }
+}
+
+// One block per job: fold the per-block partials in block order.
+__global__ __launch_bounds__(FIN_BLOCK) void k_moments_final(const FinJob *__restrict__ fins)
+{
+    __shared__ Moments s_m[FIN_BLOCK];
+    const FinJob *F = fins + blockIdx.x;
+    FinResult *R = F->result;
+    const int np = F->n_params;
+    const uint64_t nb = F->n_blocks;
+    const uint64_t chunk = (nb + FIN_BLOCK - 1) / FIN_BLOCK;
+    Moments m;
+    m.n = 0.0;
+    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+        m.mean[j] = 0.0;
+        m.m2[j] = 0.0;
+    }
+    for (uint64_t b = threadIdx.x * chunk; b < (threadIdx.x + 1) * chunk && b < nb; ++b) {
+        const double *p = F->partials + b * PARTIAL_STRIDE;
+        Moments o;
+        o.n = p[0];
+        for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+            o.mean[j] = p[1 + j];
+            o.m2[j] = p[1 + PPS_MAX_PARAMS + j];
+        }
+        moments_merge(m, o, np);
+    }
+    s_m[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 1; off < FIN_BLOCK; off <<= 1) {
+        if ((threadIdx.x & (2 * off - 1)) == 0 && threadIdx.x + off < FIN_BLOCK)
+            moments_merge(s_m[threadIdx.x], s_m[threadIdx.x + off], np);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const Moments &t = s_m[0];
+        const double nan = __longlong_as_double(0x7ff8000000000000ll);
+        for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+            R->mean[j] = (j < np && t.n > 0.0) ? t.mean[j] : nan;
+            R->var[j] = (j < np && t.n > 1.0) ? t.m2[j] / (t.n - 1.0) : nan;
+        }
+    }
+}
+
+// ===========================================================================
+// Host-side launchers.
+// ===========================================================================
+static inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap)
+{
+    uint64_t g = (n + block - 1) / block;
+    if (g < 1)
+        g = 1;
+    if (g > cap)
+        g = cap;
+    return static_cast<unsigned>(g);
+}
+
+template <int BLOCK, int CLASS>
+static hipError_t launch_sim_t(const JobDev *jobs, int n_jobs, uint64_t total_tiles,
+                               LaunchState *state, unsigned grid, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1)
+{
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, state);
+    if (e0) {
+        hipError_t e = hipEventRecord(e0, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL((k_simulate<BLOCK, CLASS>), dim3(grid), dim3(BLOCK), 0, s, jobs, n_jobs,
+                       total_tiles, state);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && e1)
+        e = hipEventRecord(e1, s);
+    return e;
+}
+
+template <int CLASS>
+static hipError_t launch_sim_c(int block, const JobDev *jobs, int n_jobs, uint64_t total_tiles,
+                               LaunchState *state, unsigned grid, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1)
+{
+    switch (block) {
+    case 64: return launch_sim_t<64, CLASS>(jobs, n_jobs, total_tiles, state, grid, s, e0, e1);
+    case 128: return launch_sim_t<128, CLASS>(jobs, n_jobs, total_tiles, state, grid, s, e0, e1);
+    case 512: return launch_sim_t<512, CLASS>(jobs, n_jobs, total_tiles, state, grid, s, e0, e1);
+    case 256:
+    default: return launch_sim_t<256, CLASS>(jobs, n_jobs, total_tiles, state, grid, s, e0, e1);
+    }
+}
+
+hipError_t launch_simulate(int cls, int block, const JobDev *jobs, int n_jobs, uint64_t total_tiles,
+                           LaunchState *state, unsigned grid, hipStream_t s, hipEvent_t ev_start,
+                           hipEvent_t ev_stop)
+{
+    if (cls == CLASS_GARCH)
+        return launch_sim_c<CLASS_GARCH>(block, jobs, n_jobs, total_tiles, state, grid, s,
+                                         ev_start, ev_stop);
+    return launch_sim_c<CLASS_PATH>(block, jobs, n_jobs, total_tiles, state, grid, s, ev_start,
+                                    ev_stop);
+}
+
+template <int CLASS>
+static hipError_t occ_c(int block, int *blocks_per_cu)
+{
+    switch (block) {
+    case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_simulate<64, CLASS>, 64, 0);
+    case 128: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_simulate<128, CLASS>, 128, 0);
+    case 512: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_simulate<512, CLASS>, 512, 0);
+    case 256:
+    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_simulate<256, CLASS>, 256, 0);
+    }
+}
+
+hipError_t simulate_occupancy(int cls, int block, int *blocks_per_cu)
+{
+    return cls == CLASS_GARCH ? occ_c<CLASS_GARCH>(block, blocks_per_cu)
+                              : occ_c<CLASS_PATH>(block, blocks_per_cu);
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t block,
+                         uint32_t purpose, uint32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_philox, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, seed, first, n,
+                       block, purpose, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_normals(uint64_t seed, uint64_t first, uint64_t n, uint32_t m, float *out,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_normals, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, seed, first, n,
+                       m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_abc_finalize(const FinJob *fins, int n_fins, uint64_t total_blocks,
+                               bool any_top, hipStream_t s)
+{
+    const unsigned tb = static_cast<unsigned>(total_blocks);
+    hipLaunchKernelGGL(k_fin_init, dim3(n_fins), dim3(FIN_BLOCK), 0, s, fins);
+    if (any_top) {
+        for (int pass = 0; pass < 3; ++pass) {
+            hipLaunchKernelGGL(k_sel_hist, dim3(tb), dim3(FIN_BLOCK), 0, s, fins, n_fins, pass);
+            hipLaunchKernelGGL(k_sel_pick, dim3(n_fins), dim3(FIN_BLOCK), 0, s, fins, pass);
+        }
+    }
+    hipLaunchKernelGGL(k_compact_count, dim3(tb), dim3(FIN_BLOCK), 0, s, fins, n_fins);
+    hipLaunchKernelGGL(k_compact_scan, dim3(n_fins), dim3(FIN_BLOCK), 0, s, fins);
+    hipLaunchKernelGGL(k_compact_write, dim3(tb), dim3(FIN_BLOCK), 0, s, fins, n_fins);
+    hipLaunchKernelGGL(k_moments_final, dim3(n_fins), dim3(FIN_BLOCK), 0, s, fins);
+    return hipGetLastError();
+}
+
+}  // namespace pps

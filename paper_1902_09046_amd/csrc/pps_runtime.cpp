@@ -1,0 +1,317 @@
+// Host runtime of libpps: errors, per-device contexts, buffers, validation
+// and job-table launches of the persistent simulation kernel.
+#include "pps_runtime.hpp"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "pps_launch.hpp"
+
+namespace pps {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? PPS_ENOMEM : PPS_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+const char *last_error() { return g_last_error.c_str(); }
+void clear_error() { g_last_error.clear(); }
+
+hipError_t DevBuf::ensure(size_t need)
+{
+    if (need <= bytes && p)
+        return hipSuccess;
+    if (p) {
+        hipError_t e = hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (e != hipSuccess)
+            return e;
+    }
+    size_t grow = need < 4096 ? 4096 : need + need / 4;
+    hipError_t e = hipMalloc(&p, grow);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return e;
+    }
+    bytes = grow;
+    return hipSuccess;
+}
+
+hipError_t HostBuf::ensure(size_t need)
+{
+    if (need <= bytes && p)
+        return hipSuccess;
+    if (p) {
+        hipError_t e = hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (e != hipSuccess)
+            return e;
+    }
+    size_t grow = need < 4096 ? 4096 : need + need / 4;
+    hipError_t e = hipHostMalloc(&p, grow, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return e;
+    }
+    bytes = grow;
+    return hipSuccess;
+}
+
+static constexpr int kMaxDevices = 64;
+static Context *g_contexts[kMaxDevices];
+static std::mutex g_contexts_mu;
+
+Context *current_context(int *status)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *status = fail_hip(e, "hipGetDevice");
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *status = fail(PPS_EDEVICE, "device %d out of range", dev);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_contexts_mu);
+    if (!g_contexts[dev]) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) {
+            *status = fail_hip(e, "hipGetDeviceProperties");
+            return nullptr;
+        }
+        Context *c = new Context();
+        c->device = dev;
+        c->cu_count = prop.multiProcessorCount;
+        g_contexts[dev] = c;
+    }
+    *status = PPS_OK;
+    return g_contexts[dev];
+}
+
+static int block_index(int block)
+{
+    switch (block) {
+    case 64: return 0;
+    case 128: return 1;
+    case 512: return 3;
+    default: return 2;
+    }
+}
+
+int blocks_per_cu(Context &c, int cls, int block)
+{
+    int &occ = c.occupancy[cls][block_index(block)];
+    if (occ == 0) {
+        int v = 0;
+        if (simulate_occupancy(cls, block, &v) != hipSuccess || v < 1)
+            v = 1;
+        occ = v;
+    }
+    return occ;
+}
+
+int model_class(const pps_model *m) { return m->model == PPS_GARCH11 ? CLASS_GARCH : CLASS_PATH; }
+
+static bool finite(double v) { return std::isfinite(v); }
+
+int validate_model(const pps_model *m, int *n_summ)
+{
+    if (!m)
+        return fail(PPS_EINVAL, "model is NULL");
+    if (m->n_params < 1 || m->n_params > PPS_MAX_PARAMS)
+        return fail(PPS_EINVAL, "n_params %d out of range [1, %d]", m->n_params, PPS_MAX_PARAMS);
+    for (int j = 0; j < m->n_params; ++j) {
+        const pps_prior &p = m->prior[j];
+        switch (p.family) {
+        case PPS_UNIFORM:
+            if (!finite(p.a) || !finite(p.b) || !(p.a < p.b))
+                return fail(PPS_EINVAL, "prior %d: uniform needs finite a < b", j);
+            break;
+        case PPS_NORMAL:
+        case PPS_LOGNORMAL:
+            if (!finite(p.a) || !finite(p.b) || p.b < 0.0)
+                return fail(PPS_EINVAL, "prior %d: (log)normal needs finite mean and sd >= 0", j);
+            break;
+        case PPS_POINT:
+            if (std::isnan(p.a))
+                return fail(PPS_EINVAL, "prior %d: point mass at NaN", j);
+            break;
+        default:
+            return fail(PPS_EINVAL, "prior %d: unknown family %d", j, p.family);
+        }
+    }
+    if (m->constraint != PPS_NO_CONSTRAINT && m->constraint != PPS_GARCH_STATIONARY)
+        return fail(PPS_EINVAL, "unknown constraint %d", m->constraint);
+    switch (m->model) {
+    case PPS_LOGISTIC_SDE:
+        if (m->n_params != 3)
+            return fail(PPS_EINVAL, "logistic SDE needs 3 parameters");
+        if (m->n_obs < 1 || m->n_obs > PPS_MAX_OBS)
+            return fail(PPS_EINVAL, "n_obs %d out of range [1, %d]", m->n_obs, PPS_MAX_OBS);
+        if (m->steps < 1 || m->steps % m->n_obs != 0)
+            return fail(PPS_EINVAL, "steps %d must be a positive multiple of n_obs %d", m->steps,
+                        m->n_obs);
+        if (!finite(m->t_end) || !(m->t_end > 0.0) || !finite(m->x0))
+            return fail(PPS_EINVAL, "logistic SDE needs finite t_end > 0 and x0");
+        if (m->constraint != PPS_NO_CONSTRAINT)
+            return fail(PPS_EINVAL, "constraint only applies to GARCH");
+        *n_summ = m->n_obs;
+        return PPS_OK;
+    case PPS_NORMAL_MEAN:
+        if (m->n_obs < 1 || m->n_obs > PPS_MAX_OBS)
+            return fail(PPS_EINVAL, "n_obs %d out of range [1, %d]", m->n_obs, PPS_MAX_OBS);
+        if (!finite(m->noise_sd) || m->noise_sd < 0.0)
+            return fail(PPS_EINVAL, "noise_sd must be finite and >= 0");
+        if (m->constraint != PPS_NO_CONSTRAINT)
+            return fail(PPS_EINVAL, "constraint only applies to GARCH");
+        *n_summ = m->n_obs;
+        return PPS_OK;
+    case PPS_GARCH11:
+        if (m->n_params != 3)
+            return fail(PPS_EINVAL, "GARCH needs 3 parameters (omega, alpha, beta)");
+        if (m->steps < 20 || m->steps % 20 != 0)
+            return fail(PPS_EINVAL, "GARCH series length %d must be a positive multiple of 20",
+                        m->steps);
+        *n_summ = PPS_GARCH_NSUMM;
+        return PPS_OK;
+    default:
+        return fail(PPS_EINVAL, "unknown model %d", m->model);
+    }
+}
+
+int validate_sampling(const pps_sampling *s)
+{
+    if (!s)
+        return fail(PPS_EINVAL, "sampling is NULL");
+    if (s->n_draws == 0)
+        return fail(PPS_EINVAL, "n_draws must be >= 1");
+    if (s->first_draw + s->n_draws < s->first_draw)
+        return fail(PPS_EINVAL, "draw range overflows 64 bits");
+    return PPS_OK;
+}
+
+void fill_job(JobDev &J, const pps_model *m, const pps_sampling *s, int n_summ, int flags)
+{
+    std::memset(&J, 0, sizeof J);
+    J.model = m->model;
+    J.flags = flags;
+    J.n_params = m->n_params;
+    J.n_summ = n_summ;
+    J.constraint = m->constraint;
+    if (m->model == PPS_LOGISTIC_SDE) {
+        J.steps = m->steps;
+        J.obs_stride = m->steps / m->n_obs;
+        J.dt = m->t_end / static_cast<double>(m->steps);
+    } else if (m->model == PPS_GARCH11) {
+        J.steps = m->steps;
+        J.obs_stride = 1;
+    } else {
+        J.steps = m->n_obs;
+        J.obs_stride = 1;
+    }
+    J.seed = s->seed;
+    J.first_draw = s->first_draw;
+    J.n_draws = s->n_draws;
+    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+        J.prior[j].family = j < m->n_params ? m->prior[j].family : PPS_POINT;
+        J.prior[j].a = j < m->n_params ? m->prior[j].a : 0.0;
+        J.prior[j].b = j < m->n_params ? m->prior[j].b : 0.0;
+    }
+    J.x0 = m->x0;
+    J.noise_sd = m->noise_sd;
+}
+
+int launch_rows(Context &c, int cls, std::vector<JobDev> &rows, hipStream_t stream)
+{
+    const int block = c.shape[cls].block;
+    uint64_t tiles = 0;
+    for (JobDev &r : rows) {
+        r.tile_size = block;
+        r.tile_offset = 0;
+        r.n_tiles = (r.n_draws + block - 1) / block;
+        r.tile_begin = tiles;
+        tiles += r.n_tiles;
+    }
+    const size_t bytes = rows.size() * sizeof(JobDev);
+    hipError_t e = c.h_jobs.ensure(bytes);
+    if (e != hipSuccess)
+        return fail_hip(e, "pinned job staging");
+    e = c.jobs.ensure(bytes);
+    if (e != hipSuccess)
+        return fail_hip(e, "device job table");
+    e = c.state.ensure(sizeof(LaunchState));
+    if (e != hipSuccess)
+        return fail_hip(e, "device launch state");
+    std::memcpy(c.h_jobs.p, rows.data(), bytes);
+    e = hipMemcpyAsync(c.jobs.p, c.h_jobs.p, bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "job table upload");
+    const uint64_t resident = static_cast<uint64_t>(blocks_per_cu(c, cls, block)) * c.cu_count;
+    const unsigned grid = static_cast<unsigned>(tiles < resident ? tiles : resident);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_timing) {
+        if (!c.ev_start) {
+            e = hipEventCreate(&c.ev_start);
+            if (e == hipSuccess)
+                e = hipEventCreate(&c.ev_stop);
+            if (e != hipSuccess)
+                return fail_hip(e, "timing events");
+        }
+        e0 = c.ev_start;
+        e1 = c.ev_stop;
+        c.ev_pending = true;
+    }
+    e = launch_simulate(cls, block, c.jobs.as<JobDev>(), static_cast<int>(rows.size()), tiles,
+                        c.state.as<LaunchState>(), grid, stream, e0, e1);
+    if (e != hipSuccess)
+        return fail_hip(e, "simulation launch");
+    return PPS_OK;
+}
+
+bool g_timing = false;
+
+void collect_timing(Context &c)
+{
+    if (!c.ev_pending)
+        return;
+    c.ev_pending = false;
+    float ms = -1.0f;
+    if (hipEventElapsedTime(&ms, c.ev_start, c.ev_stop) == hipSuccess)
+        c.last_kernel_ms = ms;
+    else
+        (void)hipGetLastError();
+}
+
+uint64_t top_count(double frac, uint64_t n)
+{
+    double k = std::ceil(frac * static_cast<double>(n));
+    if (k < 1.0)
+        k = 1.0;
+    if (k > static_cast<double>(n))
+        k = static_cast<double>(n);
+    return static_cast<uint64_t>(k);
+}
+
+}  // namespace pps

@@ -5,7 +5,10 @@ prior-predictive simulation at a fixed theta (point priors), seed 0, draw 0:
 
 * logistic SDE, theta = (1, 100, 0.2), X0 = 10, T = 10, S = 1000, observed at
   steps 50, 100, ..., 1000 -> ``y_obs`` (20 values) and ``t_obs`` = their mean;
-* GARCH(1,1), theta = (5e-5, 0.1, 0.85), L = 2000 -> the 14 summaries.
+* GARCH(1,1), theta = (5e-5, 0.1, 0.85), L = 2000 -> the 14 summaries;
+* the fixed tolerance of the 1e7-draw ABC workload: the 0.1% distance
+  quantile of the oracle's pilot on draws [0, 1e5) of the sampling seed
+  (the 100th smallest distance, type-1 inverse empirical CDF).
 
 Values are written with 17 significant digits so they round-trip exactly.
 Run:  python tests/golden/make_golden.py
@@ -32,6 +35,15 @@ def main():
             "theta": list(W.LOGISTIC_THETA_OBS), "seed": W.OBS_SEED, "draw": W.OBS_DRAW,
             "y_obs": [float(repr_) for repr_ in y], "t_obs": float(sim["stat"][0]),
         }
+    spec = W.logistic_spec(steps=1000)
+    y = out["logistic_S1000"]["y_obs"]
+    pilot_n = W.ABC_LARGE["pilot_n"]
+    pilot = oracle.abc(spec, y, W.SAMPLING_SEED, 0, pilot_n, oracle.EPS_TOP_FRACTION,
+                       W.ABC_LARGE["pilot_frac"], capacity=0)
+    out["abc_n1e7_pilot"] = {"seed": W.SAMPLING_SEED, "first": 0, "n": pilot_n,
+                             "k": oracle.top_count(W.ABC_LARGE["pilot_frac"], pilot_n),
+                             "eps": pilot["eps_used"], "mean": list(pilot["mean"]),
+                             "var": list(pilot["var"])}
     gspec = W.garch_point_spec()
     gs = oracle.simulate(gspec, W.OBS_SEED, W.OBS_DRAW, 1)
     out["garch_L2000"] = {"theta": list(W.GARCH_THETA_OBS), "seed": W.OBS_SEED,

@@ -1,0 +1,146 @@
+"""The C ABI without a GPU: libpps.so loads, exports every function that
+include/pps.h declares, its structs have the layout the binding assumes, and
+argument validation answers before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pps.h")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1902_09046_amd as P
+    from paper_1902_09046_amd import build
+    if not os.path.exists(P.LIB_PATH):
+        build.build()
+    return P
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("abc_sample", "prior_pred_pvalue", "pps_simulate", "pps_philox", "pps_normals",
+              "pps_summary_tally", "pps_strerror", "pps_last_error", "pps_n_summaries"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(P):
+    L = P.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(ln.split()[-1] for ln in out.splitlines() if " T " in ln)
+    assert set(declared_functions()) <= exported
+    # no bare poll/submit that would interpose libc
+    assert "poll" not in exported and "submit" not in exported
+
+
+_LAYOUT_PROG = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "pps.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(pps_prior), sizeof(pps_model), sizeof(pps_sampling), sizeof(pps_abc_stats));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(pps_model, prior), offsetof(pps_model, constraint),
+         offsetof(pps_model, x0), offsetof(pps_model, t_end), offsetof(pps_model, steps),
+         offsetof(pps_model, n_obs), offsetof(pps_model, noise_sd));
+  printf("%zu %zu %zu\n", offsetof(pps_abc_stats, eps_used), offsetof(pps_abc_stats, mean), offsetof(pps_abc_stats, var));
+  return 0;
+}
+"""
+
+
+def test_struct_layout_matches_binding(P):
+    from paper_1902_09046_amd import _pps as B
+    d = tempfile.mkdtemp(prefix="pps_layout_")
+    src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+    with open(src, "w") as f:
+        f.write(_LAYOUT_PROG)
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+    lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    sizes = [int(v) for v in lines[0].split()]
+    assert sizes == [ctypes.sizeof(B.pps_prior), ctypes.sizeof(B.pps_model),
+                     ctypes.sizeof(B.pps_sampling), ctypes.sizeof(B.pps_abc_stats)]
+    offs = [int(v) for v in lines[1].split()]
+    assert offs == [getattr(B.pps_model, f).offset for f in
+                    ("prior", "constraint", "x0", "t_end", "steps", "n_obs", "noise_sd")]
+    offs2 = [int(v) for v in lines[2].split()]
+    assert offs2 == [getattr(B.pps_abc_stats, f).offset for f in ("eps_used", "mean", "var")]
+
+
+def test_validation_without_device(P):
+    import pps_workloads as W
+    L = P.lib()
+    assert P.pps_n_summaries(W.logistic_spec()) == 20
+    assert P.pps_n_summaries(W.garch_spec()) == 14
+    assert P.pps_n_summaries(W.normal_mean_spec(n_obs=7)) == 7
+    bad = [W.logistic_spec(steps=999), W.logistic_spec(n_obs=0), W.logistic_spec(n_obs=65, steps=65),
+           W.garch_spec(series_len=1990), W.logistic_spec(theta1=("uniform", 2.0, 1.0)),
+           W.logistic_spec(theta1=("normal", 0.0, -1.0)), W.logistic_spec(t_end=-1.0)]
+    for spec in bad:
+        assert L.pps_n_summaries(ctypes.byref(P.make_model(spec))) == P.PPS_EINVAL
+        assert L.pps_last_error()
+    m = P.make_model(W.logistic_spec())
+    bad_family = P.make_model(W.logistic_spec())
+    bad_family.prior[0].family = 9
+    assert L.pps_n_summaries(ctypes.byref(bad_family)) == P.PPS_EINVAL
+    st = P._pps.pps_abc_stats()
+    y = np.zeros(20)
+    s0 = P.make_sampling(0, 0, 1)
+    s1 = P.make_sampling(100, 0, 1)
+    # N = 0
+    assert L.abc_sample(ctypes.byref(m), y.ctypes.data, ctypes.byref(s0), 1, 0.01, 0, None, None, None,
+                        ctypes.byref(st), None) == P.PPS_EINVAL
+    # NULL y_obs, NULL stats, bad mode, bad fraction, missing buffers with capacity
+    assert L.abc_sample(ctypes.byref(m), None, ctypes.byref(s1), 1, 0.01, 0, None, None, None,
+                        ctypes.byref(st), None) == P.PPS_EINVAL
+    assert L.abc_sample(ctypes.byref(m), y.ctypes.data, ctypes.byref(s1), 1, 0.01, 0, None, None, None,
+                        None, None) == P.PPS_EINVAL
+    assert L.abc_sample(ctypes.byref(m), y.ctypes.data, ctypes.byref(s1), 7, 0.01, 0, None, None, None,
+                        ctypes.byref(st), None) == P.PPS_EINVAL
+    assert L.abc_sample(ctypes.byref(m), y.ctypes.data, ctypes.byref(s1), 1, 0.0, 0, None, None, None,
+                        ctypes.byref(st), None) == P.PPS_EINVAL
+    assert L.abc_sample(ctypes.byref(m), y.ctypes.data, ctypes.byref(s1), 1, 0.01, 5, None, None, None,
+                        ctypes.byref(st), None) == P.PPS_EINVAL
+    y_bad = y.copy()
+    y_bad[3] = np.nan
+    assert L.abc_sample(ctypes.byref(m), y_bad.ctypes.data, ctypes.byref(s1), 1, 0.01, 0, None, None,
+                        None, ctypes.byref(st), None) == P.PPS_EINVAL
+    lam = np.array([1.0, 2.0])
+    cnt = np.zeros(2, np.uint64)
+    pv = np.zeros(2)
+    assert L.prior_pred_pvalue(ctypes.byref(m), 3, 2, lam.ctypes.data, 2, ctypes.byref(s1), 1.0,
+                               cnt.ctypes.data, pv.ctypes.data, None) == P.PPS_EINVAL
+    assert L.prior_pred_pvalue(ctypes.byref(m), 0, 2, lam.ctypes.data, 0, ctypes.byref(s1), 1.0,
+                               cnt.ctypes.data, pv.ctypes.data, None) == P.PPS_EINVAL
+    lam_bad = np.array([-1.0, 2.0])  # negative log-sd
+    assert L.prior_pred_pvalue(ctypes.byref(m), 0, 2, lam_bad.ctypes.data, 2, ctypes.byref(s1), 1.0,
+                               cnt.ctypes.data, pv.ctypes.data, None) == P.PPS_EINVAL
+    g = P.make_model(W.garch_spec())
+    assert L.prior_pred_pvalue(ctypes.byref(g), 0, 2, lam.ctypes.data, 2, ctypes.byref(s1), 1.0,
+                               cnt.ctypes.data, pv.ctypes.data, None) == P.PPS_EINVAL
+    assert L.pps_summary_tally(ctypes.byref(m), ctypes.byref(s1), y.ctypes.data, cnt.ctypes.data,
+                               None) == P.PPS_EINVAL
+    assert L.pps_philox(1, 0, 0, 0, 0, None, None) == P.PPS_EINVAL
+    assert L.pps_normals(1, 0, 10, 0, None, None) == P.PPS_EINVAL
+
+
+def test_strerror(P):
+    L = P.lib()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, 42):
+        assert L.pps_strerror(code)
+    assert L.pps_strerror(-6) == b"output truncated to capacity"

@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (from the method's definition and the precision split: FP32 simulation,
+FP64 priors / tallies / moments):
+  * random streams: bit-exact;
+  * prior draws: the FP32 theta equals the oracle's FP64 theta rounded to
+    FP32 (uniform priors are computed with the same IEEE operations);
+  * summaries, distance, statistic: within 1e-5 relative of the oracle;
+  * accept sets: identical except draws whose oracle distance lies within
+    1e-5 * eps of eps;
+  * p-value tallies: identical counts over draws whose EM map is contracting
+    (th1 dt < 2); decisions of chaotic draws are counted and reported.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import pps_workloads as W
+from gpu_helpers import observed, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def P(torch):
+    import paper_1902_09046_amd as P
+    return P
+
+
+def test_philox_bit_exact(P, torch):
+    for seed, first, block, purpose, n in [(1, 0, 0, 0, 3000), (0xDEADBEEFCAFEF00D, 2**32 - 1000, 249, 1, 2500),
+                                            (7, 123456789, 3, 0, 1001)]:
+        out = torch.empty(4 * n, dtype=torch.int32, device="cuda")
+        P.pps_philox(seed, first, n, block, purpose, out)
+        got = out.cpu().numpy().view(np.uint32).reshape(n, 4)
+        ref = np.array([oracle.stream_block(seed, first + q, block, purpose) for q in range(n)])
+        np.testing.assert_array_equal(got, ref)
+
+
+def test_path_normals_fp32_vs_fp64(P, torch):
+    seed, first, n, m = 3, 2**32 - 37, 1500, 22  # draw indices cross the 2^32 boundary
+    out = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    P.pps_normals(seed, first, n, m, out)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = np.array([[oracle.path_normal(seed, first + q, k) for q in range(n)] for k in range(m)])
+    err = np.abs(got - ref)
+    print("normals: max abs err", err.max(), "max rel err", (err / np.maximum(np.abs(ref), 1)).max())
+    assert err.max() < 2e-5 * max(1.0, np.abs(ref).max())
+
+
+def _logistic_parity(P, spec, seed, first, n, y):
+    g = P.simulate(spec, seed, first, n, y_obs=y)
+    o = oracle.simulate(spec, seed, first, n, y_obs=y)
+    th = g["theta"].cpu().numpy().T
+    np.testing.assert_array_equal(th, o["theta"].astype(np.float32))
+    summ = g["summ"].cpu().numpy().T
+    scale = np.abs(o["summ"]).max()
+    e_obs = rel_err(summ, o["summ"], floor=1e-3 * scale)
+    e_d = rel_err(g["dist"].cpu().numpy(), o["dist"])
+    e_t = rel_err(g["stat"].cpu().numpy(), o["stat"], floor=1e-3 * scale)
+    print(f"logistic S={spec['steps']} n={n}: obs {e_obs.max():.2e} dist {e_d.max():.2e} "
+          f"stat {e_t.max():.2e}")
+    assert e_obs.max() <= TOL and e_d.max() <= TOL and e_t.max() <= TOL
+    return g, o
+
+
+def test_logistic_summaries_ragged(P, torch):
+    y = np.array(observed()["logistic_S1000"]["y_obs"])
+    spec = W.logistic_spec(steps=1000)
+    _logistic_parity(P, spec, W.SAMPLING_SEED, 0, 5003, y)  # 19.5 tiles of 256
+
+
+@pytest.mark.parametrize("steps,n_obs,t_end", [(20, 4, 2.0), (200, 20, 10.0), (5000, 20, 10.0), (30, 3, 1.0)])
+def test_logistic_step_counts(P, torch, steps, n_obs, t_end):
+    spec = W.logistic_spec(steps=steps, n_obs=n_obs, t_end=t_end)
+    y = np.linspace(20, 90, n_obs)
+    n = 700 if steps >= 5000 else 1337
+    _logistic_parity(P, spec, 9, 77, n, y)
+
+
+def test_self_distance_point_priors(P, torch):
+    ob = observed()["logistic_S1000"]
+    spec = W.logistic_point_spec(steps=1000)
+    g = P.simulate(spec, 0, 0, 1, y_obs=ob["y_obs"])
+    d = float(g["dist"][0])
+    print("self distance", d, "norm", np.linalg.norm(ob["y_obs"]))
+    assert d <= 1e-5 * np.linalg.norm(ob["y_obs"])
+
+
+def test_normal_mean_summaries(P, torch):
+    spec = W.normal_mean_spec(n_obs=20, noise_sd=1.5, prior_sd=2.0)
+    g = P.simulate(spec, 5, 11, 3001, y_obs=np.zeros(20))
+    o = oracle.simulate(spec, 5, 11, 3001, y_obs=np.zeros(20))
+    np.testing.assert_array_equal(g["theta"].cpu().numpy().T, o["theta"].astype(np.float32))
+    err = np.abs(g["summ"].cpu().numpy().T - o["summ"])
+    assert err.max() <= 1e-5 * np.abs(o["summ"]).max()
+
+
+def test_abc_top_fraction_small_workload(P, torch):
+    """N = 1e4, closest 1%: accept set, eps and FP64 posterior moments."""
+    y = np.array(observed()["logistic_S1000"]["y_obs"])
+    spec = W.logistic_spec(steps=1000)
+    n, frac = W.ABC_SMALL["n"], W.ABC_SMALL["frac"]
+    g = P.abc(spec, y, W.SAMPLING_SEED, 0, n, P.PPS_EPS_TOP_FRACTION, frac)
+    o = oracle.abc(spec, y, W.SAMPLING_SEED, 0, n, oracle.EPS_TOP_FRACTION, frac)
+    assert g["n_accepted"] == o["n_accepted"] == 100
+    assert abs(g["eps_used"] - o["eps_used"]) <= TOL * o["eps_used"]
+    gi = g["idx"].cpu().numpy()
+    assert np.all(np.diff(gi) > 0)  # increasing draw index
+    sim = oracle.simulate(spec, W.SAMPLING_SEED, 0, n, y_obs=y)
+    eps = o["eps_used"]
+    band = set(np.nonzero(np.abs(sim["dist"] - eps) <= TOL * eps)[0].tolist())
+    diff = set(gi.tolist()) ^ set(o["idx"].tolist())
+    assert diff <= band, (diff, band)
+    if not diff:
+        np.testing.assert_allclose(g["mean"][:3], o["mean"], rtol=1e-12)
+        np.testing.assert_allclose(g["var"][:3], o["var"], rtol=1e-10)
+        np.testing.assert_array_equal(g["theta"].cpu().numpy().T, o["theta"].astype(np.float32))
+        np.testing.assert_allclose(g["dist"].cpu().numpy(), o["dist"], rtol=TOL)
+
+
+def test_abc_fixed_eps_and_truncation(P, torch):
+    y = np.array(observed()["logistic_S1000"]["y_obs"])
+    spec = W.logistic_spec(steps=200)
+    n = 9000
+    sim = oracle.simulate(spec, 4, 1000, n, y_obs=y)
+    eps = float(np.quantile(sim["dist"], 0.05))
+    g = P.abc(spec, y, 4, 1000, n, P.PPS_EPS_FIXED, eps)
+    ref = np.nonzero(sim["dist"] <= eps)[0] + 1000
+    band = set((np.nonzero(np.abs(sim["dist"] - eps) <= TOL * eps)[0] + 1000).tolist())
+    got = g["idx"].cpu().numpy()
+    assert set(got.tolist()) ^ set(ref.tolist()) <= band
+    assert g["eps_used"] == eps
+    # truncation: first `capacity` by index, true count reported
+    t = P.abc(spec, y, 4, 1000, n, P.PPS_EPS_FIXED, eps, capacity=7)
+    assert t["status"] == P.PPS_ETRUNC and t["n_accepted"] == g["n_accepted"]
+    np.testing.assert_array_equal(t["idx"].cpu().numpy(), got[:7])
+    np.testing.assert_allclose(t["mean"], g["mean"], rtol=0, atol=0)
+    # capacity 0: statistics only
+    z = P.abc(spec, y, 4, 1000, n, P.PPS_EPS_FIXED, eps, capacity=0)
+    assert z["n_accepted"] == g["n_accepted"]
+
+
+def test_abc_ties_by_index(P, torch):
+    spec = W.logistic_spec(steps=100, theta1=("point", 1, 0), theta2=("point", 100, 0),
+                           theta3=("point", 0.0, 0))
+    g = P.abc(spec, np.full(20, 50.0), 1, 10, 3000, P.PPS_EPS_TOP_FRACTION, 0.05)
+    np.testing.assert_array_equal(g["idx"].cpu().numpy(), np.arange(10, 160))
+    assert g["n_accepted"] == 150
+
+
+def test_abc_single_draw_and_full_fraction(P, torch):
+    y = np.array(observed()["logistic_S1000"]["y_obs"])
+    spec = W.logistic_spec(steps=100)
+    g = P.abc(spec, y, 2, 5, 1, P.PPS_EPS_TOP_FRACTION, 0.01)
+    assert g["n_accepted"] == 1 and int(g["idx"][0]) == 5 and math.isnan(g["var"][0])
+    g = P.abc(spec, y, 2, 0, 777, P.PPS_EPS_TOP_FRACTION, 1.0)
+    assert g["n_accepted"] == 777
+    np.testing.assert_array_equal(g["idx"].cpu().numpy(), np.arange(777))
+
+
+def _chaotic(theta1, dt):
+    return theta1 * dt >= 2.0
+
+
+def test_pvalue_lambda_grid_parity(P, torch):
+    """64-lambda grid at reduced N: counts equal up to chaotic-draw flips."""
+    spec = W.pvalue_spec(steps=1000)
+    t_obs = observed()["logistic_S1000"]["t_obs"]
+    lam = W.lambda_grid(64)
+    n = 3000
+    counts, p = P.prior_pred_pvalue(spec, 0, P.PPS_LOGNORMAL, lam, P.make_sampling(n, 0, 1), t_obs)
+    ref = oracle.pvalue(spec, 0, "lognormal", lam, 1, 0, n, t_obs)
+    np.testing.assert_array_equal(p, counts / n)
+    flips_total = 0
+    for k in (0, 20, 40, 63):
+        sk = dict(spec, priors=[("lognormal", 0.0, float(lam[k]))] + spec["priors"][1:])
+        o = oracle.simulate(sk, 1, 0, n)
+        g = P.simulate(sk, 1, 0, n)
+        dec_o = o["stat"] >= t_obs
+        dec_g = g["stat"].cpu().numpy().astype(np.float64) >= t_obs
+        chaotic = _chaotic(o["theta"][:, 0], 0.01)
+        assert np.array_equal(dec_o[~chaotic], dec_g[~chaotic]), k
+        flips_total += int((dec_o != dec_g).sum())
+        assert int(dec_g.sum()) == int(counts[k])
+    diff = np.abs(counts.astype(np.int64) - ref["count_ge"].astype(np.int64))
+    print("p-value count differences per lambda:", diff.max(), "flips in sampled lambdas:", flips_total)
+    small = lam <= 1.0
+    np.testing.assert_array_equal(counts[small], ref["count_ge"][small])
+    assert diff.max() <= max(3, int(2e-3 * n))
+
+
+def test_conjugate_normal_pvalue_gpu(P, torch):
+    spec = W.normal_mean_spec(n_obs=20, noise_sd=1.0)
+    n, t_obs = 200000, 0.4
+    lam = [0.3, 1.0, 2.0]
+    counts, p = P.prior_pred_pvalue(spec, 0, P.PPS_NORMAL, lam, P.make_sampling(n, 0, 21), t_obs)
+    ref = oracle.pvalue(spec, 0, "normal", lam, 21, 0, n, t_obs)
+    np.testing.assert_array_equal(counts, ref["count_ge"])
+    for k, l in enumerate(lam):
+        pe = 1 - 0.5 * math.erfc(-(t_obs / math.sqrt(l * l + 1 / 20)) / math.sqrt(2))
+        assert abs(p[k] - pe) <= 4 * math.sqrt(pe * (1 - pe) / n)
+
+
+GARCH_TOL = {"mean": 1e-5, "var": 1e-5, "skew": 1e-5, "kurt": 1e-5, "acf": 1e-5}
+
+
+def garch_errors(g, o):
+    """Per-summary errors: relative for variance and kurtosis; the mean
+    relative to the series sd; skewness and ACFs absolute (they sit near 0)."""
+    errs = {}
+    sd = np.sqrt(o[:, 1])
+    errs["mean"] = np.abs(g[:, 0] - o[:, 0]) / sd
+    errs["var"] = rel_err(g[:, 1], o[:, 1])
+    errs["skew"] = np.abs(g[:, 2] - o[:, 2])
+    errs["kurt"] = rel_err(g[:, 3], o[:, 3])
+    errs["acf"] = np.abs(g[:, 4:] - o[:, 4:]).max(axis=1)
+    return errs
+
+
+def test_garch_summaries(P, torch):
+    spec = W.garch_spec()
+    n = 2003
+    g = P.simulate(spec, 1, 0, n)
+    o = oracle.simulate(spec, 1, 0, n)
+    np.testing.assert_array_equal(g["theta"].cpu().numpy().T, o["theta"].astype(np.float32))
+    gs = g["summ"].cpu().numpy().T.astype(np.float64)
+    errs = garch_errors(gs, o["summ"])
+    for k, e in errs.items():
+        print(f"GARCH {k}: max {e.max():.2e} median {np.median(e):.2e} p99 {np.quantile(e, 0.99):.2e}")
+    for k, e in errs.items():
+        assert np.median(e) <= GARCH_TOL[k], k
+
+
+def test_garch_tally(P, torch):
+    spec = W.garch_spec()
+    obs = observed()["garch_L2000"]["summaries"]
+    n = 3000
+    counts = P.pps_summary_tally(spec, P.make_sampling(n, 0, 1), obs)
+    ref = oracle.summary_tally(spec, 1, 0, n, obs)
+    print("GARCH tallies", counts, ref)
+    assert np.abs(counts.astype(np.int64) - ref.astype(np.int64)).max() <= 2
+
+
+def test_sharding_invariance(P, torch):
+    """[0, N) equals [0, N/2) + [N/2, N) bit for bit."""
+    y = np.array(observed()["logistic_S1000"]["y_obs"])
+    spec = W.logistic_spec(steps=200)
+    a = P.simulate(spec, 3, 0, 4000, y_obs=y)
+    b = P.simulate(spec, 3, 0, 1700, y_obs=y)
+    c = P.simulate(spec, 3, 1700, 2300, y_obs=y)
+    for key in ("theta", "summ"):
+        np.testing.assert_array_equal(a[key].cpu().numpy(),
+                                      np.concatenate([b[key].cpu().numpy(), c[key].cpu().numpy()], axis=1))
+    for key in ("stat", "dist"):
+        np.testing.assert_array_equal(a[key].cpu().numpy(),
+                                      np.concatenate([b[key].cpu().numpy(), c[key].cpu().numpy()]))
+
+
+def test_invalid_arguments_raise(P, torch):
+    spec = W.logistic_spec(steps=999)
+    with pytest.raises(P.PPSError):
+        P.simulate(spec, 1, 0, 10)
+    with pytest.raises(P.PPSError):
+        P.abc(W.logistic_spec(), np.zeros(20), 1, 0, 100, P.PPS_EPS_TOP_FRACTION, 1.5)
