@@ -26,10 +26,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "prior-predictive sims/s + % FP32 VALU peak vs plain GPU; p50/p99 job latency"
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one VALU lane-operation
-# per lane per cycle (157.3 TFLOP/s counts an FMA as 2 and packed FP32 as 2x).
-CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
-VALU_PEAK_OPS = CUS * SIMDS * LANES * CLOCK  # 3.93e13 lane-ops/s
+# MI355X VALU issue peak: 256 CUs x 128 FP32 lanes per CU per cycle x 2.4 GHz
+# = 7.86e13 lane-operations/s, i.e. the published 157.3 TFLOP/s FP32 vector
+# peak with an FMA counted as one operation (two flops).
+CUS, LANES_PER_CU, CLOCK = 256, 128, 2.4e9
+VALU_PEAK_OPS = CUS * LANES_PER_CU * CLOCK  # 7.86e13 lane-ops/s
 
 # Algorithmic VALU lane-operations of the logistic path (see the design notes):
 #   Philox4x32-10 call: 10 rounds x (2 mul_hi + 2 mul_lo + 4 xor) = 80
