@@ -59,7 +59,24 @@ def parse():
     ap.add_argument("--n", type=int, default=10_000_000, help="prior draws per step")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="draws of the oracle's timed sample (0 disables the CPU baseline)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy of known size (1 GiB read + 1 GiB written), for scaling
+    the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": nbytes, "calibrate_copy_bytes_written": nbytes,
+                      "copies": 3}), flush=True)
 
 
 def main():
@@ -69,6 +86,9 @@ def main():
               "(multi-GPU sharding of draw ranges is described in the design notes, not built)",
               file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     import numpy as np
     import torch
 

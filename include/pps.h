@@ -201,6 +201,16 @@ int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
 int pps_set_timing(int enable);
 double pps_last_kernel_ms(void);
 
+/* ---- launch shape ------------------------------------------------------- */
+
+/* Workgroup size of the persistent simulation kernel for a model class
+ * (0: logistic SDE and normal-mean; 1: GARCH): 64, 128, 256 or 512.  Results
+ * do not depend on it (draw i's arithmetic depends only on (seed, i)).
+ * Returns PPS_OK or PPS_EINVAL.  pps_get_block_size returns the current
+ * size, or PPS_EINVAL for an unknown class. */
+int pps_set_block_size(int model_class, int block);
+int pps_get_block_size(int model_class);
+
 /* ---- errors ------------------------------------------------------------- */
 const char *pps_strerror(int status);
 const char *pps_last_error(void); /* thread-local; "" when none */

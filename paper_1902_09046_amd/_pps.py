@@ -93,6 +93,10 @@ def lib():
         L.pps_set_timing.argtypes = [ctypes.c_int]
         L.pps_set_timing.restype = ctypes.c_int
         L.pps_last_kernel_ms.restype = ctypes.c_double
+        L.pps_set_block_size.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.pps_set_block_size.restype = ctypes.c_int
+        L.pps_get_block_size.argtypes = [ctypes.c_int]
+        L.pps_get_block_size.restype = ctypes.c_int
         for name in ("pps_philox", "pps_normals", "pps_simulate", "pps_n_summaries", "abc_sample",
                      "prior_pred_pvalue", "pps_summary_tally"):
             getattr(L, name).restype = ctypes.c_int
@@ -159,6 +163,14 @@ def pps_set_timing(enable: bool) -> None:
 
 def pps_last_kernel_ms() -> float:
     return float(lib().pps_last_kernel_ms())
+
+
+def pps_set_block_size(model_class: int, block: int) -> None:
+    _check(lib().pps_set_block_size(model_class, block))
+
+
+def pps_get_block_size(model_class: int) -> int:
+    return _check_count(lib().pps_get_block_size(model_class))
 
 
 def pps_n_summaries(model) -> int:

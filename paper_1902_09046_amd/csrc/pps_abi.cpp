@@ -45,6 +45,35 @@ double pps_last_kernel_ms(void)
     return c->last_kernel_ms;
 }
 
+int pps_set_block_size(int model_class, int block)
+{
+    clear_error();
+    if (model_class != CLASS_PATH && model_class != CLASS_GARCH)
+        return fail(PPS_EINVAL, "unknown model class %d", model_class);
+    if (block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(PPS_EINVAL, "block size %d not in {64, 128, 256, 512}", block);
+    int rc;
+    Context *c = current_context(&rc);
+    if (!c)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->shape[model_class].block = block;
+    return PPS_OK;
+}
+
+int pps_get_block_size(int model_class)
+{
+    clear_error();
+    if (model_class != CLASS_PATH && model_class != CLASS_GARCH)
+        return fail(PPS_EINVAL, "unknown model class %d", model_class);
+    int rc;
+    Context *c = current_context(&rc);
+    if (!c)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    return c->shape[model_class].block;
+}
+
 const char *pps_strerror(int status)
 {
     switch (status) {
