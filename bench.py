@@ -16,6 +16,7 @@ caller's stream.  ``cpu_baseline`` times the FP64 oracle on a bounded sample
 of the same workload on the host cores.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -51,6 +52,49 @@ def ops_per_draw(steps: int, n_obs: int) -> float:
     return steps * per_step + n_obs * OPS_OBS + OPS_PRIOR
 
 
+# GARCH(1,1) step: the shared normal (26) + sqrt, 2 multiplies, 2 fma for the
+# variance, 4 moment sums, b_t, 10 lag products = 46, plus 14 Kahan folds
+# (4 ops) every 20 steps = 2.8; closing algebra and prior ~ 600 per draw.
+GARCH_OPS_PER_STEP = 48.8
+GARCH_OPS_PER_DRAW_FIXED = 600
+
+
+def kernel_source_digest() -> str:
+    """sha256 of the device sources; HBM traffic taken from the PMC counters is
+    reported only while it matches the digest recorded with them."""
+    csrc = os.path.join(ROOT, "paper_1902_09046_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("pps_device.hpp", "pps_internal.hpp", "pps_kernels.hip"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_digest() or key not in t:
+        return None
+    return t[key]["bytes_per_launch"]
+
+
+def time_calls(P, torch, fn, warmup: int, reps: int):
+    """Wall time per call (host clock, synchronised) and mean kernel time."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ks = []
+    for _ in range(reps):
+        fn()
+        ks.append(P.pps_last_kernel_ms())
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, sum(ks) / len(ks)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +103,8 @@ def parse():
     ap.add_argument("--n", type=int, default=10_000_000, help="prior draws per step")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="draws of the oracle's timed sample (0 disables the CPU baseline)")
+    ap.add_argument("--only-main", action="store_true",
+                    help="skip the p-value batch and GARCH workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -134,9 +180,38 @@ def main():
     achieved = ops / (k_ms * 1e-3) / 1e12
     peak = VALU_PEAK_OPS / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TOP/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic("k_simulate_path_abc_n1e7"),
                 "kernel": "k_simulate<256,path>", "kernel_ms": round(k_ms, 4),
                 "ops_per_draw": ops_per_draw(steps_em, n_obs)}
+
+    workloads = {}
+    if not args.only_main:
+        # 64-lambda p-value batch, 1e6 draws per lambda, one launch.
+        t_obs = golden["logistic_S1000"]["t_obs"]
+        pspec = W.pvalue_spec(steps=steps_em)
+        lam = W.lambda_grid(64)
+        pn = 1_000_000
+        print("bench: p-value batch 64 x 1e6", file=sys.stderr, flush=True)
+        wall, kms = time_calls(P, torch, lambda: P.prior_pred_pvalue(
+            pspec, 0, P.PPS_LOGNORMAL, lam, P.make_sampling(pn, 0, W.SAMPLING_SEED), t_obs), 1, 3)
+        pops = ops_per_draw(steps_em, n_obs) * pn * 64
+        workloads["pvalue_logistic_64lambda_n1e6"] = {
+            "sims_per_s": round(64 * pn / wall, 1), "ms_per_batch": round(wall * 1e3, 3),
+            "kernel_ms": round(kms, 3), "valu_frac": round(pops / (kms * 1e-3) / VALU_PEAK_OPS, 4)}
+        # GARCH(1,1) prior-predictive check: 1e6 series of length 2000,
+        # 14 summaries per draw written out, then tail-area tallies.
+        gspec = W.garch_spec(series_len=2000)
+        gn = 1_000_000
+        gth = torch.empty((3, gn), dtype=torch.float32, device="cuda")
+        gsm = torch.empty((14, gn), dtype=torch.float32, device="cuda")
+        print("bench: GARCH 1e6 x 2000", file=sys.stderr, flush=True)
+        wall, kms = time_calls(P, torch, lambda: P.pps_simulate(
+            gspec, P.make_sampling(gn, 0, W.SAMPLING_SEED), None, gth, gsm, None, None), 1, 3)
+        gops = (GARCH_OPS_PER_STEP * 2000 + GARCH_OPS_PER_DRAW_FIXED) * gn
+        workloads["garch11_L2000_n1e6_summaries"] = {
+            "sims_per_s": round(gn / wall, 1), "ms": round(wall * 1e3, 3), "kernel_ms": round(kms, 3),
+            "valu_frac": round(gops / (kms * 1e-3) / VALU_PEAK_OPS, 4)}
 
     cpu = None
     if args.cpu_sample > 0:
@@ -161,6 +236,7 @@ def main():
         "sde_steps_per_s": round(value * steps_em, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "workloads": workloads,
     }
     print(json.dumps(line), flush=True)
 

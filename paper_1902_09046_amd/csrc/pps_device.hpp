@@ -84,12 +84,13 @@ __device__ __forceinline__ void box_muller_f32(uint32_t w0, uint32_t w1, float &
     z1 = r * __builtin_amdgcn_sinf(u1);
 }
 
-// FP64 Box-Muller (prior draws only: once per parameter per draw).
+// FP64 Box-Muller (prior draws only: once per parameter per draw);
+// cos(2 pi u1) is evaluated as cospi(2 u1), which needs no range reduction.
 __device__ __forceinline__ double box_muller_f64_first(uint32_t w0, uint32_t w1)
 {
     const double u0 = uniform_f64(w0);
     const double u1 = uniform_f64(w1);
-    return sqrt(-2.0 * log(u0)) * cos(6.283185307179586476925286766559 * u1);
+    return sqrt(-2.0 * log(u0)) * cospi(2.0 * u1);
 }
 
 // Four path normals z_{4b..4b+3} of one draw.
@@ -106,8 +107,10 @@ __device__ __forceinline__ void path_normals4(StreamKey key, uint64_t draw, uint
 // uniform from word 0, normal / log-normal from words (0, 1).  The uniform
 // transform is written with explicit round-to-nearest operations so that the
 // GARCH constraint is decided exactly as an unfused IEEE evaluation.
+// Kept out of line: the FP64 log / cospi / exp would otherwise set the
+// register budget of the whole simulation loop (117 vs 58 VGPRs).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double prior_value(const PriorDev &p, StreamKey key, uint64_t draw,
+__device__ __attribute__((noinline)) double prior_value(const PriorDev &p, StreamKey key, uint64_t draw,
                                               int j, int attempt)
 {
     if (p.family == PPS_POINT)
@@ -128,8 +131,10 @@ __device__ __forceinline__ void prior_draw(const PriorDev *prior, int n_params, 
                                            StreamKey key, uint64_t draw, double *theta)
 {
     for (int attempt = 0;; ++attempt) {
-        for (int j = 0; j < n_params; ++j)
-            theta[j] = prior_value(prior[j], key, draw, j, attempt);
+#pragma unroll
+        for (int j = 0; j < PPS_MAX_PARAMS; ++j)
+            if (j < n_params)
+                theta[j] = prior_value(prior[j], key, draw, j, attempt);
         if (constraint != PPS_GARCH_STATIONARY)
             return;
         if (__dadd_rn(theta[1], theta[2]) < 1.0 || attempt + 1 == MAX_PRIOR_ATTEMPTS)

@@ -594,10 +594,13 @@ __device__ __forceinline__ void moments_merge(Moments &a, const Moments &b, int 
         return;
     }
     const double n = a.n + b.n;
-    for (int j = 0; j < np; ++j) {
-        const double delta = b.mean[j] - a.mean[j];
-        a.mean[j] += delta * (b.n / n);
-        a.m2[j] += b.m2[j] + delta * delta * (a.n * b.n / n);
+#pragma unroll
+    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+        if (j < np) {
+            const double delta = b.mean[j] - a.mean[j];
+            a.mean[j] += delta * (b.n / n);
+            a.m2[j] += b.m2[j] + delta * delta * (a.n * b.n / n);
+        }
     }
     a.n = n;
 }
@@ -655,6 +658,7 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const FinJob *__res
     }
     Moments mom;
     mom.n = 0.0;
+#pragma unroll
     for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
         mom.mean[j] = 0.0;
         mom.m2[j] = 0.0;
@@ -680,16 +684,22 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const FinJob *__res
                 if (pos < F->capacity) {
                     F->acc_idx[pos] = F->first_draw + e;
                     F->acc_dist[pos] = d;
-                    for (int j = 0; j < np; ++j)
-                        F->acc_theta[static_cast<uint64_t>(j) * F->capacity + pos] =
-                            static_cast<float>(theta[j]);
+#pragma unroll
+                    for (int j = 0; j < PPS_MAX_PARAMS; ++j)
+                        if (j < np)
+                            F->acc_theta[static_cast<uint64_t>(j) * F->capacity + pos] =
+                                static_cast<float>(theta[j]);
                 }
                 // Welford update in index order
                 mom.n += 1.0;
-                for (int j = 0; j < np; ++j) {
-                    const double delta = theta[j] - mom.mean[j];
-                    mom.mean[j] += delta / mom.n;
-                    mom.m2[j] += delta * (theta[j] - mom.mean[j]);
+                const double inv_n = 1.0 / mom.n;
+#pragma unroll
+                for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+                    if (j < np) {
+                        const double delta = theta[j] - mom.mean[j];
+                        mom.mean[j] += delta * inv_n;
+                        mom.m2[j] += delta * (theta[j] - mom.mean[j]);
+                    }
                 }
             }
             lt_before += __popcll(mlt);
