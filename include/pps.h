@@ -204,12 +204,20 @@ double pps_last_kernel_ms(void);
 /* ---- launch shape ------------------------------------------------------- */
 
 /* Workgroup size of the persistent simulation kernel for a model class
- * (0: logistic SDE and normal-mean; 1: GARCH): 64, 128, 256 or 512.  Results
+ * (0: logistic SDE and normal-mean; 1: GARCH): 64, 128 or 256.  Results
  * do not depend on it (draw i's arithmetic depends only on (seed, i)).
  * Returns PPS_OK or PPS_EINVAL.  pps_get_block_size returns the current
  * size, or PPS_EINVAL for an unknown class. */
 int pps_set_block_size(int model_class, int block);
 int pps_get_block_size(int model_class);
+
+/* Full launch shape of a model class: workgroup size, draws simulated
+ * interleaved per lane (1 or 2) and Philox blocks generated per loop trip
+ * (1 or 2; logistic SDE).  Supported shapes: class 0 block {64, 128, 256} x
+ * draws_per_lane {1, 2} x unroll {1, 2}; class 1 block {64, 128, 256} with
+ * (1, 1).  Results do not depend on the shape.  PPS_EINVAL otherwise. */
+int pps_set_launch_shape(int model_class, int block, int draws_per_lane, int unroll);
+int pps_get_launch_shape(int model_class, int *block, int *draws_per_lane, int *unroll);
 
 /* ---- errors ------------------------------------------------------------- */
 const char *pps_strerror(int status);

@@ -14,6 +14,7 @@ from ._pps import (  # noqa: F401
     PPS_LOGISTIC_SDE, PPS_GARCH11, PPS_NORMAL_MEAN,
     PPS_EPS_FIXED, PPS_EPS_TOP_FRACTION, PPS_GARCH_NSUMM,
     PPSError, LIB_PATH, lib, make_model, make_sampling,
-    pps_version, pps_n_summaries, pps_set_timing, pps_last_kernel_ms, pps_set_block_size, pps_get_block_size, pps_philox, pps_normals, pps_simulate,
+    pps_version, pps_n_summaries, pps_set_timing, pps_last_kernel_ms, pps_set_block_size, pps_get_block_size,
+    pps_set_launch_shape, pps_get_launch_shape, PATH_SHAPES, GARCH_SHAPES, pps_philox, pps_normals, pps_simulate,
     abc_sample, prior_pred_pvalue, pps_summary_tally, simulate, abc,
 )

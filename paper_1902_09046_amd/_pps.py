@@ -97,6 +97,11 @@ def lib():
         L.pps_set_block_size.restype = ctypes.c_int
         L.pps_get_block_size.argtypes = [ctypes.c_int]
         L.pps_get_block_size.restype = ctypes.c_int
+        L.pps_set_launch_shape.argtypes = [ctypes.c_int] * 4
+        L.pps_set_launch_shape.restype = ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.pps_get_launch_shape.argtypes = [ctypes.c_int, ip, ip, ip]
+        L.pps_get_launch_shape.restype = ctypes.c_int
         for name in ("pps_philox", "pps_normals", "pps_simulate", "pps_n_summaries", "abc_sample",
                      "prior_pred_pvalue", "pps_summary_tally"):
             getattr(L, name).restype = ctypes.c_int
@@ -171,6 +176,21 @@ def pps_set_block_size(model_class: int, block: int) -> None:
 
 def pps_get_block_size(model_class: int) -> int:
     return _check_count(lib().pps_get_block_size(model_class))
+
+
+def pps_set_launch_shape(model_class: int, block: int, draws_per_lane: int = 1,
+                         unroll: int = 1) -> None:
+    _check(lib().pps_set_launch_shape(model_class, block, draws_per_lane, unroll))
+
+
+def pps_get_launch_shape(model_class: int) -> tuple[int, int, int]:
+    b, d, u = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().pps_get_launch_shape(model_class, ctypes.byref(b), ctypes.byref(d), ctypes.byref(u)))
+    return b.value, d.value, u.value
+
+
+PATH_SHAPES = [(b, d, u) for b in (64, 128, 256) for d in (1, 2) for u in (1, 2)]
+GARCH_SHAPES = [(b, 1, 1) for b in (64, 128, 256)]
 
 
 def pps_n_summaries(model) -> int:

@@ -1,4 +1,6 @@
-// extern "C" entry points of libpps (declared in include/pps.h).
+// extern "C" entry points of libpps (declared in include/pps.h).  Every
+// synchronous call builds one epoch plan and runs it through the calling
+// device's epoch engine (one captured graph), then reads the staged results.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -6,11 +8,6 @@
 #include "pps.h"
 #include "pps_launch.hpp"
 #include "pps_runtime.hpp"
-
-namespace pps {
-const char *last_error();
-void clear_error();
-}  // namespace pps
 
 using namespace pps;
 
@@ -21,11 +18,34 @@ using namespace pps;
             return fail_hip(e_, what);                                                         \
     } while (0)
 
+#define PPS_TRY(expr)                                                                          \
+    do {                                                                                       \
+        int rc_ = (expr);                                                                      \
+        if (rc_ != PPS_OK)                                                                     \
+            return rc_;                                                                        \
+    } while (0)
+
 static hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+static void whole_job(const EpochEngine &eng, int cls, JobDev &row)
+{
+    row.tile_offset = 0;
+    row.n_tiles = eng.tiles_for(cls, row.n_draws);
+}
+
+// Runs one plan to completion on `stream` (context lock held by the caller).
+static int run_sync(Context &c, EpochPlan &plan, hipStream_t stream)
+{
+    PPS_TRY(c.engine->launch(0, plan, stream));
+    PPS_TRY(c.engine->wait(0));
+    if (g_timing)
+        c.last_kernel_ms = c.engine->sim_ms(0);
+    return PPS_OK;
+}
 
 extern "C" {
 
-const char *pps_version(void) { return "pps 0.1 (gfx950)"; }
+const char *pps_version(void) { return "pps 0.2 (gfx950)"; }
 
 const char *pps_last_error(void) { return last_error(); }
 
@@ -50,14 +70,16 @@ int pps_set_block_size(int model_class, int block)
     clear_error();
     if (model_class != CLASS_PATH && model_class != CLASS_GARCH)
         return fail(PPS_EINVAL, "unknown model class %d", model_class);
-    if (block != 64 && block != 128 && block != 256 && block != 512)
-        return fail(PPS_EINVAL, "block size %d not in {64, 128, 256, 512}", block);
     int rc;
     Context *c = current_context(&rc);
     if (!c)
         return rc;
     std::lock_guard<std::mutex> lk(c->mu);
-    c->shape[model_class].block = block;
+    SimShape sh = c->engine->shape(model_class);
+    sh.block = block;
+    if (!sim_shape_supported(model_class, sh))
+        return fail(PPS_EINVAL, "block size %d not supported for class %d", block, model_class);
+    c->engine->set_shape(model_class, sh);
     return PPS_OK;
 }
 
@@ -71,7 +93,48 @@ int pps_get_block_size(int model_class)
     if (!c)
         return rc;
     std::lock_guard<std::mutex> lk(c->mu);
-    return c->shape[model_class].block;
+    return c->engine->shape(model_class).block;
+}
+
+int pps_set_launch_shape(int model_class, int block, int draws_per_lane, int unroll)
+{
+    clear_error();
+    if (model_class != CLASS_PATH && model_class != CLASS_GARCH)
+        return fail(PPS_EINVAL, "unknown model class %d", model_class);
+    SimShape sh;
+    sh.block = block;
+    sh.dpl = draws_per_lane;
+    sh.unroll = unroll;
+    if (!sim_shape_supported(model_class, sh))
+        return fail(PPS_EINVAL, "launch shape (%d, %d, %d) not supported for class %d", block,
+                    draws_per_lane, unroll, model_class);
+    int rc;
+    Context *c = current_context(&rc);
+    if (!c)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->engine->set_shape(model_class, sh);
+    return PPS_OK;
+}
+
+int pps_get_launch_shape(int model_class, int *block, int *draws_per_lane, int *unroll)
+{
+    clear_error();
+    if (model_class != CLASS_PATH && model_class != CLASS_GARCH)
+        return fail(PPS_EINVAL, "unknown model class %d", model_class);
+    int rc;
+    Context *c = current_context(&rc);
+    if (!c)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    const SimShape &sh = c->engine->shape(model_class);
+    if (block)
+        *block = sh.block;
+    if (draws_per_lane)
+        *draws_per_lane = sh.dpl;
+    if (unroll)
+        *unroll = sh.unroll;
+    return PPS_OK;
 }
 
 const char *pps_strerror(int status)
@@ -126,19 +189,18 @@ int pps_simulate(const pps_model *model, const pps_sampling *sampling, const dou
 {
     clear_error();
     int ns = 0, rc;
-    if ((rc = validate_model(model, &ns)) != PPS_OK)
-        return rc;
-    if ((rc = validate_sampling(sampling)) != PPS_OK)
-        return rc;
+    PPS_TRY(validate_model(model, &ns));
+    PPS_TRY(validate_sampling(sampling));
     if (dist && !y_obs)
         return fail(PPS_EINVAL, "pps_simulate: dist requested without y_obs");
     Context *c = current_context(&rc);
     if (!c)
         return rc;
     std::lock_guard<std::mutex> lk(c->mu);
-    std::vector<JobDev> rows(1);
-    fill_job(rows[0], model, sampling, ns, JOB_DUMP);
-    JobDev &J = rows[0];
+    const int cls = model_class(model);
+    EpochPlan plan;
+    JobDev J;
+    fill_job(J, model, sampling, ns, JOB_DUMP);
     if (y_obs && model->model != PPS_GARCH11)
         for (int k = 0; k < ns; ++k)
             J.y_obs[k] = static_cast<float>(y_obs[k]);
@@ -146,12 +208,9 @@ int pps_simulate(const pps_model *model, const pps_sampling *sampling, const dou
     J.dump_summ = summ;
     J.dump_stat = model->model == PPS_GARCH11 ? nullptr : stat;
     J.dump_dist = model->model == PPS_GARCH11 ? nullptr : dist;
-    const hipStream_t s = as_stream(stream);
-    if ((rc = launch_rows(*c, model_class(model), rows, s)) != PPS_OK)
-        return rc;
-    PPS_TRY_HIP(hipStreamSynchronize(s), "pps_simulate");
-    collect_timing(*c);
-    return PPS_OK;
+    whole_job(*c->engine, cls, J);
+    plan.rows[cls].push_back(J);
+    return run_sync(*c, plan, as_stream(stream));
 }
 
 int abc_sample(const pps_model *model, const double *y_obs, const pps_sampling *sampling,
@@ -160,94 +219,44 @@ int abc_sample(const pps_model *model, const double *y_obs, const pps_sampling *
 {
     clear_error();
     int ns = 0, rc;
-    if ((rc = validate_model(model, &ns)) != PPS_OK)
-        return rc;
-    if ((rc = validate_sampling(sampling)) != PPS_OK)
-        return rc;
-    if (model->model == PPS_GARCH11)
-        return fail(PPS_EINVAL, "abc_sample: GARCH summaries have no observed-data distance here");
-    if (!y_obs || !stats)
-        return fail(PPS_EINVAL, "abc_sample: y_obs and stats are required");
-    if (eps_mode != PPS_EPS_FIXED && eps_mode != PPS_EPS_TOP_FRACTION)
-        return fail(PPS_EINVAL, "abc_sample: unknown eps_mode %d", eps_mode);
-    if (eps_mode == PPS_EPS_TOP_FRACTION && !(eps_or_frac > 0.0 && eps_or_frac <= 1.0))
-        return fail(PPS_EINVAL, "abc_sample: fraction must be in (0, 1]");
-    if (eps_mode == PPS_EPS_FIXED && std::isnan(eps_or_frac))
-        return fail(PPS_EINVAL, "abc_sample: eps is NaN");
+    PPS_TRY(validate_model(model, &ns));
+    PPS_TRY(validate_sampling(sampling));
+    if (!stats)
+        return fail(PPS_EINVAL, "abc_sample: stats is required");
+    PPS_TRY(validate_abc(model, y_obs, ns, sampling, eps_mode, eps_or_frac));
     if (capacity > 0 && (!acc_idx || !acc_theta || !acc_dist))
         return fail(PPS_EINVAL, "abc_sample: output buffers required when capacity > 0");
-    if (sampling->n_draws >= (1ull << 32))
-        return fail(PPS_EINVAL, "abc_sample: n_draws must be < 2^32");
-    for (int k = 0; k < ns; ++k)
-        if (!std::isfinite(y_obs[k]))
-            return fail(PPS_EINVAL, "abc_sample: y_obs[%d] is not finite", k);
     Context *c = current_context(&rc);
     if (!c)
         return rc;
     std::lock_guard<std::mutex> lk(c->mu);
     const uint64_t n = sampling->n_draws;
-    const uint64_t nb = (n + FIN_TILE - 1) / FIN_TILE;
-    PPS_TRY_HIP(c->dist.ensure(n * sizeof(float)), "distance buffer");
-    PPS_TRY_HIP(c->fins.ensure(sizeof(FinJob)), "finalisation table");
-    PPS_TRY_HIP(c->results.ensure(sizeof(FinResult)), "result row");
-    PPS_TRY_HIP(c->hist.ensure(SEL_BINS * sizeof(unsigned)), "select histogram");
-    PPS_TRY_HIP(c->block_counts.ensure(2 * nb * sizeof(unsigned long long)), "block counts");
-    PPS_TRY_HIP(c->partials.ensure(nb * (1 + 2 * PPS_MAX_PARAMS) * sizeof(double)), "partials");
-    PPS_TRY_HIP(c->h_fins.ensure(sizeof(FinJob)), "pinned staging");
-    PPS_TRY_HIP(c->h_results.ensure(sizeof(FinResult)), "pinned staging");
+    PPS_TRY_HIP(c->dist.ensure(abc_scratch_bytes(n)), "ABC scratch");
+    const AbcScratch scr = abc_scratch_at(c->dist.p, n);
 
-    std::vector<JobDev> rows(1);
-    fill_job(rows[0], model, sampling, ns, JOB_WRITE_DIST);
+    EpochPlan plan;
+    JobDev J;
+    fill_job(J, model, sampling, ns, JOB_WRITE_DIST);
     for (int k = 0; k < ns; ++k)
-        rows[0].y_obs[k] = static_cast<float>(y_obs[k]);
-    rows[0].dist = c->dist.as<float>();
-    const hipStream_t s = as_stream(stream);
-    if ((rc = launch_rows(*c, CLASS_PATH, rows, s)) != PPS_OK)
-        return rc;
-
+        J.y_obs[k] = static_cast<float>(y_obs[k]);
+    J.dist = scr.dist;
+    whole_job(*c->engine, CLASS_PATH, J);
+    plan.rows[CLASS_PATH].push_back(J);
     FinJob F;
-    std::memset(&F, 0, sizeof F);
-    F.dist = c->dist.as<float>();
-    F.n = n;
-    F.first_draw = sampling->first_draw;
-    F.seed = sampling->seed;
-    F.mode = eps_mode;
-    F.n_params = model->n_params;
-    F.constraint = model->constraint;
-    F.eps = eps_mode == PPS_EPS_FIXED ? eps_or_frac : 0.0;
-    F.k = eps_mode == PPS_EPS_TOP_FRACTION ? top_count(eps_or_frac, n) : 0;
-    F.capacity = capacity;
-    F.block_begin = 0;
-    F.n_blocks = nb;
-    std::memcpy(F.prior, rows[0].prior, sizeof F.prior);
-    F.acc_idx = acc_idx;
-    F.acc_theta = acc_theta;
-    F.acc_dist = acc_dist;
-    F.hist = c->hist.as<unsigned>();
-    F.block_counts = c->block_counts.as<unsigned long long>();
-    F.partials = c->partials.as<double>();
-    F.result = c->results.as<FinResult>();
-    std::memcpy(c->h_fins.p, &F, sizeof F);
-    PPS_TRY_HIP(hipMemcpyAsync(c->fins.p, c->h_fins.p, sizeof F, hipMemcpyHostToDevice, s),
-                "finalisation upload");
-    PPS_TRY_HIP(launch_abc_finalize(c->fins.as<FinJob>(), 1, nb,
-                                    eps_mode == PPS_EPS_TOP_FRACTION, s),
-                "finalisation launch");
-    PPS_TRY_HIP(hipMemcpyAsync(c->h_results.p, c->results.p, sizeof(FinResult),
-                               hipMemcpyDeviceToHost, s),
-                "result download");
-    PPS_TRY_HIP(hipStreamSynchronize(s), "abc_sample");
-    collect_timing(*c);
-    const FinResult *R = c->h_results.as<FinResult>();
-    stats->n_accepted = R->n_accepted;
-    stats->eps_used = R->eps_used;
+    fill_fin(F, J, eps_mode, eps_or_frac, capacity, acc_idx, acc_theta, acc_dist, scr);
+    plan.fins.push_back(F);
+    PPS_TRY(run_sync(*c, plan, as_stream(stream)));
+
+    const FinResult &R = c->engine->out_fin(0)[0];
+    stats->n_accepted = R.n_accepted;
+    stats->eps_used = R.eps_used;
     for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-        stats->mean[j] = R->mean[j];
-        stats->var[j] = R->var[j];
+        stats->mean[j] = R.mean[j];
+        stats->var[j] = R.var[j];
     }
-    if (R->n_accepted > capacity)
+    if (R.n_accepted > capacity)
         return fail(PPS_ETRUNC, "abc_sample: %llu accepted, capacity %llu",
-                    static_cast<unsigned long long>(R->n_accepted),
+                    static_cast<unsigned long long>(R.n_accepted),
                     static_cast<unsigned long long>(capacity));
     return PPS_OK;
 }
@@ -258,10 +267,8 @@ int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_famil
 {
     clear_error();
     int ns = 0, rc;
-    if ((rc = validate_model(model, &ns)) != PPS_OK)
-        return rc;
-    if ((rc = validate_sampling(sampling)) != PPS_OK)
-        return rc;
+    PPS_TRY(validate_model(model, &ns));
+    PPS_TRY(validate_sampling(sampling));
     if (model->model == PPS_GARCH11)
         return fail(PPS_EINVAL, "prior_pred_pvalue: use pps_summary_tally for GARCH");
     if (lambda_param < 0 || lambda_param >= model->n_params)
@@ -274,36 +281,32 @@ int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_famil
         return fail(PPS_EINVAL, "count_ge and pvalue are required");
     if (std::isnan(t_obs))
         return fail(PPS_EINVAL, "t_obs is NaN");
-    std::vector<JobDev> rows(n_lambda);
+    std::vector<pps_model> mk(n_lambda, *model);
     for (int k = 0; k < n_lambda; ++k) {
-        pps_model mk = *model;
-        mk.prior[lambda_param].family = lambda_family;
-        mk.prior[lambda_param].b = lambda[k];
+        mk[k].prior[lambda_param].family = lambda_family;
+        mk[k].prior[lambda_param].b = lambda[k];
         int ns2 = 0;
-        if ((rc = validate_model(&mk, &ns2)) != PPS_OK)
+        if (validate_model(&mk[k], &ns2) != PPS_OK)
             return fail(PPS_EINVAL, "lambda[%d] = %g gives an invalid prior", k, lambda[k]);
-        fill_job(rows[k], &mk, sampling, ns, JOB_TALLY_STAT);
-        rows[k].t_obs = t_obs;
-        rows[k].lambda_group = 0;
     }
     Context *c = current_context(&rc);
     if (!c)
         return rc;
     std::lock_guard<std::mutex> lk(c->mu);
     PPS_TRY_HIP(c->counts.ensure(n_lambda * sizeof(unsigned long long)), "tally buffer");
-    PPS_TRY_HIP(c->h_counts.ensure(n_lambda * sizeof(unsigned long long)), "pinned staging");
-    for (int k = 0; k < n_lambda; ++k)
-        rows[k].counts = c->counts.as<unsigned long long>() + k;
-    const hipStream_t s = as_stream(stream);
-    PPS_TRY_HIP(launch_fill_u64(c->counts.as<unsigned long long>(), n_lambda, 0ull, s), "tally reset");
-    if ((rc = launch_rows(*c, CLASS_PATH, rows, s)) != PPS_OK)
-        return rc;
-    PPS_TRY_HIP(hipMemcpyAsync(c->h_counts.p, c->counts.p, n_lambda * sizeof(unsigned long long),
-                               hipMemcpyDeviceToHost, s),
-                "tally download");
-    PPS_TRY_HIP(hipStreamSynchronize(s), "prior_pred_pvalue");
-    collect_timing(*c);
-    const unsigned long long *cnt = c->h_counts.as<unsigned long long>();
+    EpochPlan plan;
+    for (int k = 0; k < n_lambda; ++k) {
+        JobDev J;
+        fill_job(J, &mk[k], sampling, ns, JOB_TALLY_STAT);
+        J.t_obs = t_obs;
+        J.counts = c->counts.as<unsigned long long>() + k;
+        J.n_counts = 1;
+        J.row_flags = ROW_ZERO_COUNTS | ROW_COPY_COUNTS;
+        whole_job(*c->engine, CLASS_PATH, J);
+        plan.rows[CLASS_PATH].push_back(J);
+    }
+    PPS_TRY(run_sync(*c, plan, as_stream(stream)));
+    const unsigned long long *cnt = c->engine->out_counts(0);
     for (int k = 0; k < n_lambda; ++k) {
         count_ge[k] = cnt[k];
         pvalue[k] = static_cast<double>(cnt[k]) / static_cast<double>(sampling->n_draws);
@@ -316,10 +319,8 @@ int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
 {
     clear_error();
     int ns = 0, rc;
-    if ((rc = validate_model(model, &ns)) != PPS_OK)
-        return rc;
-    if ((rc = validate_sampling(sampling)) != PPS_OK)
-        return rc;
+    PPS_TRY(validate_model(model, &ns));
+    PPS_TRY(validate_sampling(sampling));
     if (model->model != PPS_GARCH11)
         return fail(PPS_EINVAL, "pps_summary_tally: GARCH models only");
     if (!obs_summ || !count_ge)
@@ -329,22 +330,18 @@ int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
         return rc;
     std::lock_guard<std::mutex> lk(c->mu);
     PPS_TRY_HIP(c->counts.ensure(ns * sizeof(unsigned long long)), "tally buffer");
-    PPS_TRY_HIP(c->h_counts.ensure(ns * sizeof(unsigned long long)), "pinned staging");
-    std::vector<JobDev> rows(1);
-    fill_job(rows[0], model, sampling, ns, JOB_TALLY_SUMM);
+    EpochPlan plan;
+    JobDev J;
+    fill_job(J, model, sampling, ns, JOB_TALLY_SUMM);
     for (int k = 0; k < ns; ++k)
-        rows[0].summ_obs[k] = obs_summ[k];
-    rows[0].counts = c->counts.as<unsigned long long>();
-    const hipStream_t s = as_stream(stream);
-    PPS_TRY_HIP(launch_fill_u64(c->counts.as<unsigned long long>(), ns, 0ull, s), "tally reset");
-    if ((rc = launch_rows(*c, CLASS_GARCH, rows, s)) != PPS_OK)
-        return rc;
-    PPS_TRY_HIP(hipMemcpyAsync(c->h_counts.p, c->counts.p, ns * sizeof(unsigned long long),
-                               hipMemcpyDeviceToHost, s),
-                "tally download");
-    PPS_TRY_HIP(hipStreamSynchronize(s), "pps_summary_tally");
-    collect_timing(*c);
-    std::memcpy(count_ge, c->h_counts.p, ns * sizeof(unsigned long long));
+        J.summ_obs[k] = obs_summ[k];
+    J.counts = c->counts.as<unsigned long long>();
+    J.n_counts = static_cast<uint32_t>(ns);
+    J.row_flags = ROW_ZERO_COUNTS | ROW_COPY_COUNTS;
+    whole_job(*c->engine, CLASS_GARCH, J);
+    plan.rows[CLASS_GARCH].push_back(J);
+    PPS_TRY(run_sync(*c, plan, as_stream(stream)));
+    std::memcpy(count_ge, c->engine->out_counts(0), ns * sizeof(unsigned long long));
     return PPS_OK;
 }
 

@@ -1,0 +1,234 @@
+// Epoch engine (see pps_engine.hpp).
+#include "pps_engine.hpp"
+
+#include <cstring>
+
+#include "pps_runtime.hpp"
+
+namespace pps {
+
+static hipError_t host_alloc(void **p, size_t bytes)
+{
+    // Coherent mapped host memory: the device reads the tables the host wrote
+    // for this epoch (never a cached copy of a previous epoch) and writes the
+    // results where the host reads them after the epoch's event.
+    hipError_t e = hipHostMalloc(p, bytes, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess)
+        std::memset(*p, 0, bytes);
+    return e;
+}
+
+template <class T> static T *dev_view(T *host)
+{
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, host, 0) != hipSuccess)
+        return nullptr;
+    return static_cast<T *>(d);
+}
+
+EpochEngine::~EpochEngine()
+{
+    // Staging memory, device tables and events are kept for the life of the
+    // process (engines are long-lived); only the graphs are released.
+    for (Slot &s : slots_) {
+        if (s.in_flight && s.done)
+            (void)hipEventSynchronize(s.done);
+        if (s.exec)
+            (void)hipGraphExecDestroy(s.exec);
+    }
+}
+
+int EpochEngine::init(int n_slots, int cu_count)
+{
+    cu_count_ = cu_count;
+    hipError_t e = hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return fail_hip(e, "capture stream");
+    slots_.resize(n_slots);
+    for (Slot &s : slots_) {
+        void *p;
+        if ((e = host_alloc(&p, sizeof(EpochHeader))) != hipSuccess)
+            return fail_hip(e, "epoch header staging");
+        s.h_hdr = static_cast<EpochHeader *>(p);
+        if ((e = host_alloc(&p, MAX_ROWS * sizeof(JobDev))) != hipSuccess)
+            return fail_hip(e, "row staging");
+        s.h_rows = static_cast<JobDev *>(p);
+        if ((e = host_alloc(&p, MAX_FINS * sizeof(FinJob))) != hipSuccess)
+            return fail_hip(e, "finalisation staging");
+        s.h_fins = static_cast<FinJob *>(p);
+        if ((e = host_alloc(&p, MAX_FINS * sizeof(FinResult))) != hipSuccess)
+            return fail_hip(e, "result staging");
+        s.h_out_fin = static_cast<FinResult *>(p);
+        if ((e = host_alloc(&p, MAX_OUT_COUNTS * sizeof(unsigned long long))) != hipSuccess)
+            return fail_hip(e, "count staging");
+        s.h_out_counts = static_cast<unsigned long long *>(p);
+        s.dev.h_hdr = dev_view(s.h_hdr);
+        s.dev.h_rows = dev_view(s.h_rows);
+        s.dev.h_fins = dev_view(s.h_fins);
+        s.dev.h_out_fin = dev_view(s.h_out_fin);
+        s.dev.h_out_counts = dev_view(s.h_out_counts);
+        if (!s.dev.h_hdr || !s.dev.h_rows || !s.dev.h_fins || !s.dev.h_out_fin || !s.dev.h_out_counts)
+            return fail(PPS_EDEVICE, "mapped staging has no device address");
+        if ((e = hipMalloc(&p, sizeof(EpochHeader))) != hipSuccess)
+            return fail_hip(e, "device epoch header");
+        s.dev.d_hdr = static_cast<EpochHeader *>(p);
+        if ((e = hipMalloc(&p, MAX_ROWS * sizeof(JobDev))) != hipSuccess)
+            return fail_hip(e, "device row table");
+        s.dev.d_rows = static_cast<JobDev *>(p);
+        if ((e = hipMalloc(&p, MAX_FINS * sizeof(FinJob))) != hipSuccess)
+            return fail_hip(e, "device finalisation table");
+        s.dev.d_fins = static_cast<FinJob *>(p);
+        if ((e = hipMalloc(&p, N_CLASSES * sizeof(LaunchState))) != hipSuccess)
+            return fail_hip(e, "launch state");
+        s.dev.states = static_cast<LaunchState *>(p);
+        if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreate(&s.dev.ev_sim_start)) != hipSuccess ||
+            (e = hipEventCreate(&s.dev.ev_sim_stop)) != hipSuccess)
+            return fail_hip(e, "epoch events");
+    }
+    return PPS_OK;
+}
+
+int EpochEngine::build_graph(Slot &s)
+{
+    EpochShape want = shape_;
+    for (int c = 0; c < N_CLASSES; ++c) {
+        if (!sim_shape_supported(c, want.sim[c]))
+            return fail(PPS_EINVAL, "unsupported launch shape for class %d", c);
+        int per_cu = 0;
+        hipError_t e = sim_occupancy(c, want.sim[c], &per_cu);
+        if (e != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        want.sim_grid[c] = static_cast<unsigned>(per_cu * cu_count_);
+    }
+    want.fin_grid = static_cast<unsigned>(8 * cu_count_);
+    if (s.exec && s.exec_shape == want)
+        return PPS_OK;
+    if (s.exec) {
+        (void)hipGraphExecDestroy(s.exec);
+        s.exec = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return fail_hip(e, "graph capture begin");
+    hipError_t ei = issue_epoch(s.dev, want, capture_stream_);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(capture_stream_, &graph);
+    if (ei != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return fail_hip(ei, "epoch capture");
+    }
+    if (e != hipSuccess)
+        return fail_hip(e, "graph capture end");
+    e = hipGraphInstantiate(&s.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        s.exec = nullptr;
+        return fail_hip(e, "graph instantiate");
+    }
+    s.exec_shape = want;
+    return PPS_OK;
+}
+
+int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
+{
+    Slot &s = slots_[slot];
+    if (s.in_flight)
+        return fail(PPS_EBUSY, "epoch slot %d still in flight", slot);
+    size_t n_rows = 0;
+    for (int c = 0; c < N_CLASSES; ++c)
+        n_rows += plan.rows[c].size();
+    if (n_rows > static_cast<size_t>(MAX_ROWS) || plan.fins.size() > static_cast<size_t>(MAX_FINS))
+        return fail(PPS_EINVAL, "epoch too large: %zu rows, %zu finalisations", n_rows,
+                    plan.fins.size());
+    int rc = build_graph(s);
+    if (rc != PPS_OK)
+        return rc;
+    EpochHeader &H = *s.h_hdr;
+    std::memset(&H, 0, sizeof H);
+    uint32_t r = 0;
+    uint32_t out_slot = 0;
+    for (int c = 0; c < N_CLASSES; ++c) {
+        H.class_first[c] = r;
+        H.class_rows[c] = static_cast<uint32_t>(plan.rows[c].size());
+        uint64_t tiles = 0;
+        const uint64_t ts = tile_size(c);
+        for (JobDev &row : plan.rows[c]) {
+            row.tile_size = static_cast<int32_t>(ts);
+            row.tile_begin = tiles;
+            tiles += row.n_tiles;
+            if (row.row_flags & ROW_COPY_COUNTS) {
+                if (out_slot + row.n_counts > static_cast<uint32_t>(MAX_OUT_COUNTS))
+                    return fail(PPS_EINVAL, "epoch has too many tallies");
+                row.out_slot = out_slot;
+                out_slot += row.n_counts;
+            }
+            s.h_rows[r++] = row;
+        }
+        H.class_tiles[c] = tiles;
+    }
+    H.n_rows = r;
+    uint64_t fb = 0;
+    for (size_t i = 0; i < plan.fins.size(); ++i) {
+        FinJob &F = plan.fins[i];
+        F.n_blocks = (F.n + FIN_TILE - 1) / FIN_TILE;
+        F.block_begin = fb;
+        fb += F.n_blocks;
+        if (F.mode == PPS_EPS_TOP_FRACTION)
+            H.any_top = 1;
+        s.h_fins[i] = F;
+    }
+    H.n_fins = static_cast<uint32_t>(plan.fins.size());
+    H.fin_blocks = fb;
+    hipError_t e = hipGraphLaunch(s.exec, stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "epoch graph launch");
+    e = hipEventRecord(s.done, stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "epoch event");
+    s.in_flight = true;
+    return PPS_OK;
+}
+
+int EpochEngine::finish(Slot &s)
+{
+    s.in_flight = false;
+    float ms = -1.0f;
+    if (hipEventElapsedTime(&ms, s.dev.ev_sim_start, s.dev.ev_sim_stop) != hipSuccess) {
+        (void)hipGetLastError();
+        ms = -1.0f;
+    }
+    s.sim_ms = ms;
+    return PPS_OK;
+}
+
+int EpochEngine::wait(int slot)
+{
+    Slot &s = slots_[slot];
+    if (!s.in_flight)
+        return PPS_OK;
+    hipError_t e = hipEventSynchronize(s.done);
+    if (e != hipSuccess) {
+        s.in_flight = false;
+        return fail_hip(e, "epoch");
+    }
+    return finish(s);
+}
+
+int EpochEngine::poll(int slot)
+{
+    Slot &s = slots_[slot];
+    if (!s.in_flight)
+        return PPS_OK;
+    hipError_t e = hipEventQuery(s.done);
+    if (e == hipErrorNotReady)
+        return PPS_PENDING;
+    if (e != hipSuccess) {
+        s.in_flight = false;
+        return fail_hip(e, "epoch");
+    }
+    return finish(s);
+}
+
+}  // namespace pps

@@ -18,7 +18,13 @@ enum : int32_t {
 };
 
 // Model classes compiled into separate simulation kernels.
-enum : int { CLASS_PATH = 0, CLASS_GARCH = 1 };
+enum : int { CLASS_PATH = 0, CLASS_GARCH = 1, N_CLASSES = 2 };
+
+// Row flags handled by the epoch stage-in / stage-out kernels.
+enum : uint32_t {
+    ROW_ZERO_COUNTS = 1u << 0,  // zero counts[0 .. n_counts) before simulating
+    ROW_COPY_COUNTS = 1u << 1,  // copy counts[0 .. n_counts) to the host after
+};
 
 struct PriorDev {
     int32_t family;
@@ -58,15 +64,37 @@ struct alignas(16) JobDev {
     float *dump_summ;
     float *dump_stat;
     float *dump_dist;
-    unsigned int *tiles_done;    // optional: incremented once per finished tile
-    uint32_t lambda_group;       // rows sharing draws under common random numbers
+    uint32_t row_flags;          // ROW_* above
+    uint32_t n_counts;           // tallies of this row (1, or 14 for GARCH)
+    uint32_t out_slot;           // ROW_COPY_COUNTS: first host slot
     uint32_t pad2;
 };
 
-// Device-side launch state (reset by a kernel before each launch).
+// Device-side launch state of one simulation class (reset by the stage-in
+// kernel of each epoch).
 struct alignas(64) LaunchState {
     unsigned long long next_tile;
     unsigned long long pad[7];
+};
+
+// Capacities of one epoch.
+constexpr int MAX_ROWS = 4096;
+constexpr int MAX_FINS = 1024;
+constexpr int MAX_OUT_COUNTS = 16384;
+
+// Epoch descriptor: staged from pinned host memory to the device at the start
+// of every epoch.  Rows of class c are rows [class_first[c], class_first[c] +
+// class_rows[c]) and their tiles are numbered 0 .. class_tiles[c] - 1.
+struct alignas(64) EpochHeader {
+    uint32_t class_first[N_CLASSES];
+    uint32_t class_rows[N_CLASSES];
+    uint64_t class_tiles[N_CLASSES];
+    uint32_t n_rows;
+    uint32_t n_fins;
+    uint64_t fin_blocks;
+    uint32_t any_top;
+    uint32_t pad;
+    uint64_t epoch_id;
 };
 
 // ---- ABC finalisation (select / compaction / moments) -------------------

@@ -200,22 +200,122 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
     }
 }
 
+// The same logistic simulation for DPL independent draws per lane, with
+// UNROLL Philox blocks generated per loop trip: the draws' (and blocks')
+// random streams are independent, which gives the scheduler instruction-level
+// parallelism without changing any draw's arithmetic.
+template <int DPL, int UNROLL>
+__device__ __forceinline__ void sim_logistic_ilp(const JobDev *__restrict__ J, StreamKey key,
+                                                 const uint64_t (&draw)[DPL],
+                                                 const double (&theta)[DPL][PPS_MAX_PARAMS],
+                                                 Kahan (&d2)[DPL], Kahan (&sum)[DPL])
+{
+    const double dt = J->dt;
+    const double sdt = sqrt(dt);
+    float a[DPL], b[DPL], c[DPL], x[DPL];
+#pragma unroll
+    for (int d = 0; d < DPL; ++d) {
+        a[d] = static_cast<float>(theta[d][0] * dt);
+        b[d] = static_cast<float>(theta[d][0] * dt / theta[d][1]);
+        c[d] = static_cast<float>(theta[d][2] * sdt);
+        x[d] = static_cast<float>(J->x0);
+    }
+    const int steps = J->steps;
+    const int stride = J->obs_stride;
+    const int nblk = (steps + 3) >> 2;
+    int next_obs = stride;
+    int k = 0;
+    int blk = 0;
+    for (; blk + UNROLL <= nblk; blk += UNROLL) {
+        float z[UNROLL][DPL][4];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+            for (int d = 0; d < DPL; ++d)
+                path_normals4(key, draw[d], static_cast<uint32_t>(blk + u), z[u][d][0], z[u][d][1],
+                              z[u][d][2], z[u][d][3]);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int step = 4 * (blk + u) + j + 1;
+                if (step > steps)
+                    break;
+#pragma unroll
+                for (int d = 0; d < DPL; ++d) {
+                    float g = __builtin_fmaf(-b[d], x[d], a[d]);
+                    g = __builtin_fmaf(c[d], z[u][d][j], g);
+                    x[d] = __builtin_fmaxf(__builtin_fmaf(x[d], g, x[d]), 0.0f);
+                }
+                if (step == next_obs) {
+                    const float y = J->y_obs[k];
+#pragma unroll
+                    for (int d = 0; d < DPL; ++d) {
+                        const float diff = x[d] - y;
+                        d2[d].add(diff * diff);
+                        sum[d].add(x[d]);
+                    }
+                    ++k;
+                    next_obs += stride;
+                }
+            }
+        }
+    }
+    for (; blk < nblk; ++blk) {
+        float z[DPL][4];
+#pragma unroll
+        for (int d = 0; d < DPL; ++d)
+            path_normals4(key, draw[d], static_cast<uint32_t>(blk), z[d][0], z[d][1], z[d][2], z[d][3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int step = 4 * blk + j + 1;
+            if (step > steps)
+                break;
+#pragma unroll
+            for (int d = 0; d < DPL; ++d) {
+                float g = __builtin_fmaf(-b[d], x[d], a[d]);
+                g = __builtin_fmaf(c[d], z[d][j], g);
+                x[d] = __builtin_fmaxf(__builtin_fmaf(x[d], g, x[d]), 0.0f);
+            }
+            if (step == next_obs) {
+                const float y = J->y_obs[k];
+#pragma unroll
+                for (int d = 0; d < DPL; ++d) {
+                    const float diff = x[d] - y;
+                    d2[d].add(diff * diff);
+                    sum[d].add(x[d]);
+                }
+                ++k;
+                next_obs += stride;
+            }
+        }
+    }
+}
+
 // ===========================================================================
 // Persistent simulation kernel.
-// ===========================================================================
+//
 // CLASS selects the model family compiled into this instance, so that each
 // family gets its own register allocation: CLASS_PATH = logistic SDE and
 // normal-mean (short per-draw state), CLASS_GARCH = GARCH(1,1) (summary ring).
-template <int BLOCK, int CLASS>
-__global__ __launch_bounds__(BLOCK) void k_simulate(const JobDev *__restrict__ jobs, int n_jobs,
-                                                    uint64_t total_tiles,
-                                                    LaunchState *__restrict__ state)
+// A tile is BLOCK * DPL draws of one job row; lane t handles draws
+// q0 + t + d * BLOCK, d < DPL.  Workgroups pull tiles from an atomic counter
+// until the class's tiles of the epoch are exhausted.
+// ===========================================================================
+template <int BLOCK, int CLASS, int DPL, int UNROLL>
+__global__ __launch_bounds__(BLOCK) void k_simulate(const EpochHeader *__restrict__ hdr,
+                                                    const JobDev *__restrict__ rows,
+                                                    LaunchState *__restrict__ states)
 {
     constexpr int NW = BLOCK / 64;
     __shared__ unsigned long long s_tile;
     __shared__ unsigned s_cnt[PPS_GARCH_NSUMM][NW];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
+    const int n_jobs = static_cast<int>(hdr->class_rows[CLASS]);
+    const uint64_t total_tiles = hdr->class_tiles[CLASS];
+    const JobDev *__restrict__ jobs = rows + hdr->class_first[CLASS];
+    LaunchState *__restrict__ state = states + CLASS;
     for (;;) {
         if (tid == 0)
             s_tile = atomicAdd(&state->next_tile, 1ull);
@@ -236,59 +336,84 @@ __global__ __launch_bounds__(BLOCK) void k_simulate(const JobDev *__restrict__ j
         const int flags = J->flags;
         const uint64_t n = J->n_draws;
         const uint64_t q0 = (t - J->tile_begin + J->tile_offset) * static_cast<uint64_t>(J->tile_size);
-        const uint64_t q = q0 + static_cast<uint64_t>(tid);
-        const bool valid = q < n;
-        const bool wave_live = q0 + static_cast<uint64_t>(wave) * 64 < n;
-        const uint64_t draw = J->first_draw + q;
         const StreamKey key = make_key(J->seed);
-
-        double theta[PPS_MAX_PARAMS] = {0.0, 0.0, 0.0, 0.0};
+        const bool wave_live = q0 + static_cast<uint64_t>(wave) * 64 < n;
+        uint64_t q[DPL], draw[DPL];
+        bool valid[DPL];
+#pragma unroll
+        for (int d = 0; d < DPL; ++d) {
+            q[d] = q0 + static_cast<uint64_t>(tid + d * BLOCK);
+            valid[d] = q[d] < n;
+            draw[d] = J->first_draw + q[d];
+        }
+        double theta[DPL][PPS_MAX_PARAMS];
         double summ[PPS_GARCH_NSUMM];
-        Kahan d2, sum;
+        Kahan d2[DPL], sum[DPL];
+#pragma unroll
+        for (int d = 0; d < DPL; ++d)
+#pragma unroll
+            for (int j = 0; j < PPS_MAX_PARAMS; ++j)
+                theta[d][j] = 0.0;
         const int model = J->model;
         if (wave_live) {
-            prior_draw(J->prior, J->n_params, J->constraint, key, draw, theta);
+#pragma unroll
+            for (int d = 0; d < DPL; ++d)
+                prior_draw(J->prior, J->n_params, J->constraint, key, draw[d], theta[d]);
             if constexpr (CLASS == CLASS_GARCH) {
-                sim_garch(J, key, draw, theta, summ);
-            } else if (model == PPS_LOGISTIC_SDE) {
-                if (flags & JOB_DUMP)
-                    sim_logistic<true>(J, key, draw, theta, q, valid, d2, sum);
-                else
-                    sim_logistic<false>(J, key, draw, theta, q, valid, d2, sum);
+                sim_garch(J, key, draw[0], theta[0], summ);
             } else {
-                if (flags & JOB_DUMP)
-                    sim_normal_mean<true>(J, key, draw, theta, q, valid, d2, sum);
-                else
-                    sim_normal_mean<false>(J, key, draw, theta, q, valid, d2, sum);
+                if (model == PPS_LOGISTIC_SDE && !(flags & JOB_DUMP)) {
+                    sim_logistic_ilp<DPL, UNROLL>(J, key, draw, theta, d2, sum);
+                } else {
+#pragma unroll
+                    for (int d = 0; d < DPL; ++d) {
+                        if (model == PPS_LOGISTIC_SDE)
+                            sim_logistic<true>(J, key, draw[d], theta[d], q[d], valid[d], d2[d], sum[d]);
+                        else if (flags & JOB_DUMP)
+                            sim_normal_mean<true>(J, key, draw[d], theta[d], q[d], valid[d], d2[d], sum[d]);
+                        else
+                            sim_normal_mean<false>(J, key, draw[d], theta[d], q[d], valid[d], d2[d], sum[d]);
+                    }
+                }
             }
         }
         constexpr bool garch = CLASS == CLASS_GARCH;
-        (void)model;
-        const float dist = garch ? 0.0f : static_cast<float>(sqrt(d2.value()));
-        const double stat = garch ? 0.0 : sum.value() / static_cast<double>(J->n_summ);
-
-        if ((flags & JOB_WRITE_DIST) && valid)
-            J->dist[q] = dist;
-        if ((flags & JOB_DUMP) && valid) {
-            if (J->dump_theta)
-                for (int j = 0; j < J->n_params; ++j)
-                    J->dump_theta[static_cast<uint64_t>(j) * n + q] = static_cast<float>(theta[j]);
-            if (garch && J->dump_summ)
-                for (int s = 0; s < PPS_GARCH_NSUMM; ++s)
-                    J->dump_summ[static_cast<uint64_t>(s) * n + q] = static_cast<float>(summ[s]);
-            if (!garch && J->dump_stat)
-                J->dump_stat[q] = static_cast<float>(stat);
-            if (!garch && J->dump_dist)
-                J->dump_dist[q] = dist;
+        float dist[DPL];
+        double stat[DPL];
+#pragma unroll
+        for (int d = 0; d < DPL; ++d) {
+            dist[d] = garch ? 0.0f : static_cast<float>(sqrt(d2[d].value()));
+            stat[d] = garch ? 0.0 : sum[d].value() / static_cast<double>(J->n_summ);
+        }
+#pragma unroll
+        for (int d = 0; d < DPL; ++d) {
+            if ((flags & JOB_WRITE_DIST) && valid[d])
+                J->dist[q[d]] = dist[d];
+            if ((flags & JOB_DUMP) && valid[d]) {
+                if (J->dump_theta)
+                    for (int j = 0; j < J->n_params; ++j)
+                        J->dump_theta[static_cast<uint64_t>(j) * n + q[d]] = static_cast<float>(theta[d][j]);
+                if (garch && J->dump_summ)
+                    for (int s = 0; s < PPS_GARCH_NSUMM; ++s)
+                        J->dump_summ[static_cast<uint64_t>(s) * n + q[d]] = static_cast<float>(summ[s]);
+                if (!garch && J->dump_stat)
+                    J->dump_stat[q[d]] = static_cast<float>(stat[d]);
+                if (!garch && J->dump_dist)
+                    J->dump_dist[q[d]] = dist[d];
+            }
         }
         if (flags & (JOB_TALLY_STAT | JOB_TALLY_SUMM)) {
             const int ns = (flags & JOB_TALLY_SUMM) ? (garch ? PPS_GARCH_NSUMM : 0) : 1;
             for (int s = 0; s < ns; ++s) {
-                const double v = (flags & JOB_TALLY_SUMM) ? summ[s] : stat;
-                const double ref = (flags & JOB_TALLY_SUMM) ? J->summ_obs[s] : J->t_obs;
-                const uint64_t m = __ballot(valid && v >= ref);
+                unsigned cnt = 0;
+#pragma unroll
+                for (int d = 0; d < DPL; ++d) {
+                    const double v = (flags & JOB_TALLY_SUMM) ? summ[s] : stat[d];
+                    const double ref = (flags & JOB_TALLY_SUMM) ? J->summ_obs[s] : J->t_obs;
+                    cnt += static_cast<unsigned>(__popcll(__ballot(valid[d] && v >= ref)));
+                }
                 if (lane_id() == 0)
-                    s_cnt[s][wave] = static_cast<unsigned>(__popcll(m));
+                    s_cnt[s][wave] = cnt;
             }
             __syncthreads();
             if (tid < ns) {
@@ -303,17 +428,58 @@ __global__ __launch_bounds__(BLOCK) void k_simulate(const JobDev *__restrict__ j
     }
 }
 
-__global__ void k_reset_state(LaunchState *state)
+// ===========================================================================
+// Epoch staging: tables in, results out (mapped pinned host memory).
+// ===========================================================================
+__global__ void k_stage_in(const EpochHeader *__restrict__ h_hdr, const JobDev *__restrict__ h_rows,
+                           const FinJob *__restrict__ h_fins, EpochHeader *__restrict__ d_hdr,
+                           JobDev *__restrict__ d_rows, FinJob *__restrict__ d_fins,
+                           LaunchState *__restrict__ states)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        state->next_tile = 0;
+    const uint32_t n_rows = h_hdr->n_rows;
+    const uint32_t n_fins = h_hdr->n_fins;
+    const uint64_t gtid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t gsize = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    const uint64_t row_words = n_rows * (sizeof(JobDev) / sizeof(uint4));
+    const uint64_t fin_words = n_fins * (sizeof(FinJob) / sizeof(uint4));
+    const uint4 *src_r = reinterpret_cast<const uint4 *>(h_rows);
+    uint4 *dst_r = reinterpret_cast<uint4 *>(d_rows);
+    for (uint64_t i = gtid; i < row_words; i += gsize)
+        dst_r[i] = src_r[i];
+    const uint4 *src_f = reinterpret_cast<const uint4 *>(h_fins);
+    uint4 *dst_f = reinterpret_cast<uint4 *>(d_fins);
+    for (uint64_t i = gtid; i < fin_words; i += gsize)
+        dst_f[i] = src_f[i];
+    for (uint64_t r = gtid; r < n_rows; r += gsize) {
+        if (h_rows[r].row_flags & ROW_ZERO_COUNTS) {
+            unsigned long long *c = h_rows[r].counts;
+            for (uint32_t s = 0; s < h_rows[r].n_counts; ++s)
+                c[s] = 0ull;
+        }
+    }
+    if (gtid == 0) {
+        *d_hdr = *h_hdr;
+        for (int c = 0; c < N_CLASSES; ++c)
+            states[c].next_tile = 0ull;
+    }
 }
 
-__global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v)
+__global__ void k_stage_out(const EpochHeader *__restrict__ d_hdr, const JobDev *__restrict__ d_rows,
+                            const FinJob *__restrict__ d_fins, FinResult *__restrict__ h_out_fin,
+                            unsigned long long *__restrict__ h_out_counts)
 {
-    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-        p[i] = v;
+    const uint32_t n_rows = d_hdr->n_rows;
+    const uint32_t n_fins = d_hdr->n_fins;
+    const uint64_t gtid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t gsize = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = gtid; i < n_fins; i += gsize)
+        h_out_fin[i] = *d_fins[i].result;
+    for (uint64_t r = gtid; r < n_rows; r += gsize) {
+        const JobDev &R = d_rows[r];
+        if (R.row_flags & ROW_COPY_COUNTS)
+            for (uint32_t s = 0; s < R.n_counts; ++s)
+                h_out_counts[R.out_slot + s] = R.counts[s];
+    }
 }
 
 // ===========================================================================
@@ -351,7 +517,10 @@ __global__ void k_normals(uint64_t seed, uint64_t first, uint64_t n, uint32_t m,
 }
 
 // ===========================================================================
-// ABC finalisation.
+// ABC finalisation.  Per-element kernels loop over the epoch's finalisation
+// blocks with a fixed grid; per-job kernels run one workgroup per job with
+// grid MAX_FINS (surplus workgroups exit).  Fixed grids keep the epoch
+// graph's shape independent of the jobs it carries.
 // ===========================================================================
 __device__ __forceinline__ int fin_locate(const FinJob *__restrict__ fins, int n_fins, uint64_t b)
 {
@@ -380,9 +549,12 @@ __device__ __forceinline__ void sel_digit(int pass, int &shift, int &bits)
     }
 }
 
-// One block per job: reset the select state and zero the histogram.
-__global__ __launch_bounds__(FIN_BLOCK) void k_fin_init(const FinJob *__restrict__ fins)
+// One workgroup per job: reset the select state and zero the histogram.
+__global__ __launch_bounds__(FIN_BLOCK) void k_fin_init(const EpochHeader *__restrict__ hdr,
+                                                         const FinJob *__restrict__ fins)
 {
+    if (blockIdx.x >= hdr->n_fins)
+        return;
     const FinJob *F = fins + blockIdx.x;
     for (int i = threadIdx.x; i < SEL_BINS; i += FIN_BLOCK)
         F->hist[i] = 0;
@@ -399,43 +571,52 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_fin_init(const FinJob *__restrict
     }
 }
 
-__global__ __launch_bounds__(FIN_BLOCK) void k_sel_hist(const FinJob *__restrict__ fins,
-                                                         int n_fins, int pass)
+__global__ __launch_bounds__(FIN_BLOCK) void k_sel_hist(const EpochHeader *__restrict__ hdr,
+                                                         const FinJob *__restrict__ fins, int pass)
 {
     __shared__ unsigned h[SEL_BINS];
-    const int jb = fin_locate(fins, n_fins, blockIdx.x);
-    const FinJob *F = fins + jb;
-    if (F->mode != PPS_EPS_TOP_FRACTION)
+    if (!hdr->any_top)
         return;
+    const int n_fins = static_cast<int>(hdr->n_fins);
+    const uint64_t total = hdr->fin_blocks;
     int shift, bits;
     sel_digit(pass, shift, bits);
     const uint32_t dmask = (1u << bits) - 1u;
-    const uint32_t prefix = F->result->sel_prefix;
-    const uint32_t pmask = F->result->sel_mask;
-    for (int i = threadIdx.x; i < SEL_BINS; i += FIN_BLOCK)
-        h[i] = 0;
-    __syncthreads();
-    const uint64_t base = (blockIdx.x - F->block_begin) * static_cast<uint64_t>(FIN_TILE);
-    const uint32_t *d = reinterpret_cast<const uint32_t *>(F->dist);
+    for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const FinJob *F = fins + fin_locate(fins, n_fins, b);
+        if (F->mode != PPS_EPS_TOP_FRACTION)
+            continue;  // uniform across the workgroup
+        const uint32_t prefix = F->result->sel_prefix;
+        const uint32_t pmask = F->result->sel_mask;
+        for (int i = threadIdx.x; i < SEL_BINS; i += FIN_BLOCK)
+            h[i] = 0;
+        __syncthreads();
+        const uint64_t base = (b - F->block_begin) * static_cast<uint64_t>(FIN_TILE);
+        const uint32_t *d = reinterpret_cast<const uint32_t *>(F->dist);
 #pragma unroll 4
-    for (int r = 0; r < FIN_ROWS; ++r) {
-        const uint64_t e = base + static_cast<uint64_t>(r) * FIN_BLOCK + threadIdx.x;
-        if (e < F->n) {
-            const uint32_t v = d[e];
-            if ((v & pmask) == prefix)
-                atomicAdd(&h[(v >> shift) & dmask], 1u);
+        for (int r = 0; r < FIN_ROWS; ++r) {
+            const uint64_t e = base + static_cast<uint64_t>(r) * FIN_BLOCK + threadIdx.x;
+            if (e < F->n) {
+                const uint32_t v = d[e];
+                if ((v & pmask) == prefix)
+                    atomicAdd(&h[(v >> shift) & dmask], 1u);
+            }
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i <= static_cast<int>(dmask); i += FIN_BLOCK)
+            if (h[i])
+                atomicAdd(&F->hist[i], h[i]);
+        __syncthreads();
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= static_cast<int>(dmask); i += FIN_BLOCK)
-        if (h[i])
-            atomicAdd(&F->hist[i], h[i]);
 }
 
-// One block per job: find the digit holding the rank still sought.
-__global__ __launch_bounds__(FIN_BLOCK) void k_sel_pick(const FinJob *__restrict__ fins, int pass)
+// One workgroup per job: find the digit holding the rank still sought.
+__global__ __launch_bounds__(FIN_BLOCK) void k_sel_pick(const EpochHeader *__restrict__ hdr,
+                                                         const FinJob *__restrict__ fins, int pass)
 {
     __shared__ unsigned long long s_sum[FIN_BLOCK];
+    if (!hdr->any_top || blockIdx.x >= hdr->n_fins)
+        return;
     const FinJob *F = fins + blockIdx.x;
     if (F->mode != PPS_EPS_TOP_FRACTION)
         return;
@@ -450,7 +631,6 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_sel_pick(const FinJob *__restrict
         local += F->hist[b0 + i];
     s_sum[threadIdx.x] = local;
     __syncthreads();
-    // inclusive Hillis-Steele scan over the per-thread sums
     for (int off = 1; off < FIN_BLOCK; off <<= 1) {
         const unsigned long long v = threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0ull;
         __syncthreads();
@@ -503,45 +683,52 @@ __device__ __forceinline__ void fin_pred(const FinJob *F, uint32_t thresh, uint6
 }
 
 // Per block: (count rho "below", count "tied") over its FIN_TILE elements.
-__global__ __launch_bounds__(FIN_BLOCK) void k_compact_count(const FinJob *__restrict__ fins,
-                                                              int n_fins)
+__global__ __launch_bounds__(FIN_BLOCK) void k_compact_count(const EpochHeader *__restrict__ hdr,
+                                                              const FinJob *__restrict__ fins)
 {
     __shared__ unsigned s_lt[FIN_BLOCK / 64], s_eq[FIN_BLOCK / 64];
-    const int jb = fin_locate(fins, n_fins, blockIdx.x);
-    const FinJob *F = fins + jb;
-    const uint64_t lb = blockIdx.x - F->block_begin;
+    const int n_fins = static_cast<int>(hdr->n_fins);
+    const uint64_t total = hdr->fin_blocks;
     const int wave = threadIdx.x >> 6;
-    const uint32_t thresh = F->result->thresh_bits;
-    const uint64_t wbase = lb * FIN_TILE + static_cast<uint64_t>(wave) * (FIN_ROWS * 64);
-    unsigned clt = 0, ceq = 0;
+    for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const FinJob *F = fins + fin_locate(fins, n_fins, b);
+        const uint64_t lb = b - F->block_begin;
+        const uint32_t thresh = F->result->thresh_bits;
+        const uint64_t wbase = lb * FIN_TILE + static_cast<uint64_t>(wave) * (FIN_ROWS * 64);
+        unsigned clt = 0, ceq = 0;
 #pragma unroll 4
-    for (int r = 0; r < FIN_ROWS; ++r) {
-        bool lt, eq;
-        float d;
-        fin_pred(F, thresh, wbase + r * 64 + lane_id(), lt, eq, d);
-        clt += __popcll(__ballot(lt));
-        ceq += __popcll(__ballot(eq));
-    }
-    if (lane_id() == 0) {
-        s_lt[wave] = clt;
-        s_eq[wave] = ceq;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long a = 0, b = 0;
-        for (int w = 0; w < FIN_BLOCK / 64; ++w) {
-            a += s_lt[w];
-            b += s_eq[w];
+        for (int r = 0; r < FIN_ROWS; ++r) {
+            bool lt, eq;
+            float d;
+            fin_pred(F, thresh, wbase + r * 64 + lane_id(), lt, eq, d);
+            clt += __popcll(__ballot(lt));
+            ceq += __popcll(__ballot(eq));
         }
-        F->block_counts[2 * lb] = a;
-        F->block_counts[2 * lb + 1] = b;
+        if (lane_id() == 0) {
+            s_lt[wave] = clt;
+            s_eq[wave] = ceq;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long a = 0, c = 0;
+            for (int w = 0; w < FIN_BLOCK / 64; ++w) {
+                a += s_lt[w];
+                c += s_eq[w];
+            }
+            F->block_counts[2 * lb] = a;
+            F->block_counts[2 * lb + 1] = c;
+        }
+        __syncthreads();
     }
 }
 
-// One block per job: exclusive scan of the per-block (lt, eq) counts.
-__global__ __launch_bounds__(FIN_BLOCK) void k_compact_scan(const FinJob *__restrict__ fins)
+// One workgroup per job: exclusive scan of the per-block (lt, eq) counts.
+__global__ __launch_bounds__(FIN_BLOCK) void k_compact_scan(const EpochHeader *__restrict__ hdr,
+                                                             const FinJob *__restrict__ fins)
 {
     __shared__ unsigned long long s_a[FIN_BLOCK], s_b[FIN_BLOCK];
+    if (blockIdx.x >= hdr->n_fins)
+        return;
     const FinJob *F = fins + blockIdx.x;
     FinResult *R = F->result;
     unsigned long long carry_a = 0, carry_b = 0;
@@ -620,118 +807,126 @@ __device__ __forceinline__ Moments moments_shfl_down(const Moments &m, int off)
 constexpr int PARTIAL_STRIDE = 1 + 2 * PPS_MAX_PARAMS;
 
 // Writes accepted records in draw-index order and per-block moment partials.
-__global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const FinJob *__restrict__ fins,
-                                                              int n_fins)
+__global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *__restrict__ hdr,
+                                                              const FinJob *__restrict__ fins)
 {
     constexpr int NW = FIN_BLOCK / 64;
     __shared__ unsigned s_lt[NW], s_eq[NW];
     __shared__ Moments s_mom[NW];
-    const int jb = fin_locate(fins, n_fins, blockIdx.x);
-    const FinJob *F = fins + jb;
-    const FinResult *R = F->result;
-    const uint64_t lb = blockIdx.x - F->block_begin;
+    const int n_fins = static_cast<int>(hdr->n_fins);
+    const uint64_t total = hdr->fin_blocks;
     const int wave = threadIdx.x >> 6;
     const uint32_t lane = lane_id();
-    const uint32_t thresh = R->thresh_bits;
-    const uint64_t quota = F->mode == PPS_EPS_FIXED ? 0 : R->quota;
-    const uint64_t wbase = lb * FIN_TILE + static_cast<uint64_t>(wave) * (FIN_ROWS * 64);
-    const int np = F->n_params;
-    // pass 1: this wave's totals, for the prefix over the block's waves
-    unsigned clt = 0, ceq = 0;
-    for (int r = 0; r < FIN_ROWS; ++r) {
-        bool lt, eq;
-        float d;
-        fin_pred(F, thresh, wbase + r * 64 + lane, lt, eq, d);
-        clt += __popcll(__ballot(lt));
-        ceq += __popcll(__ballot(eq));
-    }
-    if (lane == 0) {
-        s_lt[wave] = clt;
-        s_eq[wave] = ceq;
-    }
-    __syncthreads();
-    uint64_t lt_before = F->block_counts[2 * lb];
-    uint64_t eq_before = F->block_counts[2 * lb + 1];
-    for (int w = 0; w < wave; ++w) {
-        lt_before += s_lt[w];
-        eq_before += s_eq[w];
-    }
-    Moments mom;
-    mom.n = 0.0;
-#pragma unroll
-    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-        mom.mean[j] = 0.0;
-        mom.m2[j] = 0.0;
-    }
-    const StreamKey key = make_key(F->seed);
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // pass 2: ranks and writes
-    for (int r = 0; r < FIN_ROWS; ++r) {
-        const uint64_t e = wbase + r * 64 + lane;
-        bool lt, eq;
-        float d;
-        fin_pred(F, thresh, e, lt, eq, d);
-        const uint64_t mlt = __ballot(lt);
-        const uint64_t meq = __ballot(eq);
-        if (mlt | meq) {
-            const uint64_t my_lt = lt_before + __popcll(mlt & below);
-            const uint64_t my_eq = eq_before + __popcll(meq & below);
-            const bool acc = lt || (eq && my_eq < quota);
-            if (acc) {
-                const uint64_t pos = my_lt + (my_eq < quota ? my_eq : quota);
-                double theta[PPS_MAX_PARAMS];
-                prior_draw(F->prior, np, F->constraint, key, F->first_draw + e, theta);
-                if (pos < F->capacity) {
-                    F->acc_idx[pos] = F->first_draw + e;
-                    F->acc_dist[pos] = d;
+    for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const FinJob *F = fins + fin_locate(fins, n_fins, b);
+        const FinResult *R = F->result;
+        const uint64_t lb = b - F->block_begin;
+        const uint32_t thresh = R->thresh_bits;
+        const uint64_t quota = F->mode == PPS_EPS_FIXED ? 0 : R->quota;
+        const uint64_t wbase = lb * FIN_TILE + static_cast<uint64_t>(wave) * (FIN_ROWS * 64);
+        const int np = F->n_params;
+        // pass 1: this wave's totals, for the prefix over the block's waves
+        unsigned clt = 0, ceq = 0;
+        for (int r = 0; r < FIN_ROWS; ++r) {
+            bool lt, eq;
+            float d;
+            fin_pred(F, thresh, wbase + r * 64 + lane, lt, eq, d);
+            clt += __popcll(__ballot(lt));
+            ceq += __popcll(__ballot(eq));
+        }
+        if (lane == 0) {
+            s_lt[wave] = clt;
+            s_eq[wave] = ceq;
+        }
+        __syncthreads();
+        uint64_t lt_before = F->block_counts[2 * lb];
+        uint64_t eq_before = F->block_counts[2 * lb + 1];
+        for (int w = 0; w < wave; ++w) {
+            lt_before += s_lt[w];
+            eq_before += s_eq[w];
+        }
+        Moments mom;
+        mom.n = 0.0;
 #pragma unroll
-                    for (int j = 0; j < PPS_MAX_PARAMS; ++j)
-                        if (j < np)
-                            F->acc_theta[static_cast<uint64_t>(j) * F->capacity + pos] =
-                                static_cast<float>(theta[j]);
-                }
-                // Welford update in index order
-                mom.n += 1.0;
-                const double inv_n = 1.0 / mom.n;
+        for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+            mom.mean[j] = 0.0;
+            mom.m2[j] = 0.0;
+        }
+        const StreamKey key = make_key(F->seed);
+        // pass 2: ranks and writes
+        for (int r = 0; r < FIN_ROWS; ++r) {
+            const uint64_t e = wbase + r * 64 + lane;
+            bool lt, eq;
+            float d;
+            fin_pred(F, thresh, e, lt, eq, d);
+            const uint64_t mlt = __ballot(lt);
+            const uint64_t meq = __ballot(eq);
+            if (mlt | meq) {
+                const uint64_t my_lt = lt_before + __popcll(mlt & below);
+                const uint64_t my_eq = eq_before + __popcll(meq & below);
+                const bool acc = lt || (eq && my_eq < quota);
+                if (acc) {
+                    const uint64_t pos = my_lt + (my_eq < quota ? my_eq : quota);
+                    double theta[PPS_MAX_PARAMS];
+                    prior_draw(F->prior, np, F->constraint, key, F->first_draw + e, theta);
+                    if (pos < F->capacity) {
+                        F->acc_idx[pos] = F->first_draw + e;
+                        F->acc_dist[pos] = d;
 #pragma unroll
-                for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-                    if (j < np) {
-                        const double delta = theta[j] - mom.mean[j];
-                        mom.mean[j] += delta * inv_n;
-                        mom.m2[j] += delta * (theta[j] - mom.mean[j]);
+                        for (int j = 0; j < PPS_MAX_PARAMS; ++j)
+                            if (j < np)
+                                F->acc_theta[static_cast<uint64_t>(j) * F->capacity + pos] =
+                                    static_cast<float>(theta[j]);
+                    }
+                    // Welford update in index order
+                    mom.n += 1.0;
+                    const double inv_n = 1.0 / mom.n;
+#pragma unroll
+                    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+                        if (j < np) {
+                            const double delta = theta[j] - mom.mean[j];
+                            mom.mean[j] += delta * inv_n;
+                            mom.m2[j] += delta * (theta[j] - mom.mean[j]);
+                        }
                     }
                 }
+                lt_before += __popcll(mlt);
+                eq_before += __popcll(meq);
             }
-            lt_before += __popcll(mlt);
-            eq_before += __popcll(meq);
         }
-    }
-    // lanes -> wave (fixed tree order), waves -> block
-    for (int off = 1; off < 64; off <<= 1) {
-        const Moments other = moments_shfl_down(mom, off);
-        if ((lane & (2 * off - 1)) == 0)
-            moments_merge(mom, other, np);
-    }
-    if (lane == 0)
-        s_mom[wave] = mom;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Moments acc = s_mom[0];
-        for (int w = 1; w < NW; ++w)
-            moments_merge(acc, s_mom[w], np);
-        double *p = F->partials + lb * PARTIAL_STRIDE;
-        p[0] = acc.n;
-        for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-            p[1 + j] = acc.mean[j];
-            p[1 + PPS_MAX_PARAMS + j] = acc.m2[j];
+        // lanes -> wave (fixed tree order), waves -> block
+        for (int off = 1; off < 64; off <<= 1) {
+            const Moments other = moments_shfl_down(mom, off);
+            if ((lane & (2 * off - 1)) == 0)
+                moments_merge(mom, other, np);
         }
+        if (lane == 0)
+            s_mom[wave] = mom;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Moments acc = s_mom[0];
+            for (int w = 1; w < NW; ++w)
+                moments_merge(acc, s_mom[w], np);
+            double *p = F->partials + lb * PARTIAL_STRIDE;
+            p[0] = acc.n;
+#pragma unroll
+            for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+                p[1 + j] = acc.mean[j];
+                p[1 + PPS_MAX_PARAMS + j] = acc.m2[j];
+            }
+        }
+        __syncthreads();
     }
 }
 
-// One block per job: fold the per-block partials in block order.
-__global__ __launch_bounds__(FIN_BLOCK) void k_moments_final(const FinJob *__restrict__ fins)
+// One workgroup per job: fold the per-block partials in block order.
+__global__ __launch_bounds__(FIN_BLOCK) void k_moments_final(const EpochHeader *__restrict__ hdr,
+                                                              const FinJob *__restrict__ fins)
 {
     __shared__ Moments s_m[FIN_BLOCK];
+    if (blockIdx.x >= hdr->n_fins)
+        return;
     const FinJob *F = fins + blockIdx.x;
     FinResult *R = F->result;
     const int np = F->n_params;
@@ -739,6 +934,7 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_moments_final(const FinJob *__res
     const uint64_t chunk = (nb + FIN_BLOCK - 1) / FIN_BLOCK;
     Moments m;
     m.n = 0.0;
+#pragma unroll
     for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
         m.mean[j] = 0.0;
         m.m2[j] = 0.0;
@@ -747,6 +943,7 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_moments_final(const FinJob *__res
         const double *p = F->partials + b * PARTIAL_STRIDE;
         Moments o;
         o.n = p[0];
+#pragma unroll
         for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
             o.mean[j] = p[1 + j];
             o.m2[j] = p[1 + PPS_MAX_PARAMS + j];
@@ -783,71 +980,84 @@ static inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap)
     return static_cast<unsigned>(g);
 }
 
-template <int BLOCK, int CLASS>
-static hipError_t launch_sim_t(const JobDev *jobs, int n_jobs, uint64_t total_tiles,
-                               LaunchState *state, unsigned grid, hipStream_t s, hipEvent_t e0,
-                               hipEvent_t e1)
+using SimKernel = void (*)(const EpochHeader *, const JobDev *, LaunchState *);
+
+template <int BLOCK, int CLASS, int DPL, int UNROLL>
+static SimKernel sim_ptr()
 {
-    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, state);
-    if (e0) {
-        hipError_t e = hipEventRecord(e0, s);
-        if (e != hipSuccess)
+    return k_simulate<BLOCK, CLASS, DPL, UNROLL>;
+}
+
+// Kernel instance for a launch shape; null for an unsupported shape.
+static SimKernel sim_kernel(int cls, const SimShape &sh)
+{
+    if (cls == CLASS_GARCH) {
+        if (sh.dpl != 1 || sh.unroll != 1)
+            return nullptr;
+        switch (sh.block) {
+        case 64: return sim_ptr<64, CLASS_GARCH, 1, 1>();
+        case 128: return sim_ptr<128, CLASS_GARCH, 1, 1>();
+        case 256: return sim_ptr<256, CLASS_GARCH, 1, 1>();
+        default: return nullptr;
+        }
+    }
+#define PPS_PATH_SHAPES(B)                                                                         \
+    if (sh.block == B) {                                                                           \
+        if (sh.dpl == 1 && sh.unroll == 1) return sim_ptr<B, CLASS_PATH, 1, 1>();                  \
+        if (sh.dpl == 1 && sh.unroll == 2) return sim_ptr<B, CLASS_PATH, 1, 2>();                  \
+        if (sh.dpl == 2 && sh.unroll == 1) return sim_ptr<B, CLASS_PATH, 2, 1>();                  \
+        if (sh.dpl == 2 && sh.unroll == 2) return sim_ptr<B, CLASS_PATH, 2, 2>();                  \
+        return nullptr;                                                                            \
+    }
+    PPS_PATH_SHAPES(64)
+    PPS_PATH_SHAPES(128)
+    PPS_PATH_SHAPES(256)
+#undef PPS_PATH_SHAPES
+    return nullptr;
+}
+
+bool sim_shape_supported(int cls, const SimShape &sh) { return sim_kernel(cls, sh) != nullptr; }
+
+hipError_t sim_occupancy(int cls, const SimShape &sh, int *blocks_per_cu)
+{
+    SimKernel k = sim_kernel(cls, sh);
+    if (!k)
+        return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, sh.block, 0);
+}
+
+hipError_t issue_epoch(const EpochDevPtrs &p, const EpochShape &shape, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage_in, dim3(STAGE_GRID), dim3(256), 0, s, p.h_hdr, p.h_rows, p.h_fins,
+                       p.d_hdr, p.d_rows, p.d_fins, p.states);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    if (p.ev_sim_start && (e = hipEventRecord(p.ev_sim_start, s)) != hipSuccess)
+        return e;
+    for (int c = 0; c < N_CLASSES; ++c) {
+        SimKernel k = sim_kernel(c, shape.sim[c]);
+        if (!k)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k, dim3(shape.sim_grid[c]), dim3(shape.sim[c].block), 0, s, p.d_hdr,
+                           p.d_rows, p.states);
+        if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL((k_simulate<BLOCK, CLASS>), dim3(grid), dim3(BLOCK), 0, s, jobs, n_jobs,
-                       total_tiles, state);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && e1)
-        e = hipEventRecord(e1, s);
-    return e;
-}
-
-template <int CLASS>
-static hipError_t launch_sim_c(int block, const JobDev *jobs, int n_jobs, uint64_t total_tiles,
-                               LaunchState *state, unsigned grid, hipStream_t s, hipEvent_t e0,
-                               hipEvent_t e1)
-{
-    switch (block) {
-    case 64: return launch_sim_t<64, CLASS>(jobs, n_jobs, total_tiles, state, grid, s, e0, e1);
-    case 128: return launch_sim_t<128, CLASS>(jobs, n_jobs, total_tiles, state, grid, s, e0, e1);
-    case 512: return launch_sim_t<512, CLASS>(jobs, n_jobs, total_tiles, state, grid, s, e0, e1);
-    case 256:
-    default: return launch_sim_t<256, CLASS>(jobs, n_jobs, total_tiles, state, grid, s, e0, e1);
+    if (p.ev_sim_stop && (e = hipEventRecord(p.ev_sim_stop, s)) != hipSuccess)
+        return e;
+    const dim3 fb(FIN_BLOCK);
+    hipLaunchKernelGGL(k_fin_init, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(k_sel_hist, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins, pass);
+        hipLaunchKernelGGL(k_sel_pick, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins, pass);
     }
-}
-
-hipError_t launch_simulate(int cls, int block, const JobDev *jobs, int n_jobs, uint64_t total_tiles,
-                           LaunchState *state, unsigned grid, hipStream_t s, hipEvent_t ev_start,
-                           hipEvent_t ev_stop)
-{
-    if (cls == CLASS_GARCH)
-        return launch_sim_c<CLASS_GARCH>(block, jobs, n_jobs, total_tiles, state, grid, s,
-                                         ev_start, ev_stop);
-    return launch_sim_c<CLASS_PATH>(block, jobs, n_jobs, total_tiles, state, grid, s, ev_start,
-                                    ev_stop);
-}
-
-template <int CLASS>
-static hipError_t occ_c(int block, int *blocks_per_cu)
-{
-    switch (block) {
-    case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_simulate<64, CLASS>, 64, 0);
-    case 128: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_simulate<128, CLASS>, 128, 0);
-    case 512: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_simulate<512, CLASS>, 512, 0);
-    case 256:
-    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_simulate<256, CLASS>, 256, 0);
-    }
-}
-
-hipError_t simulate_occupancy(int cls, int block, int *blocks_per_cu)
-{
-    return cls == CLASS_GARCH ? occ_c<CLASS_GARCH>(block, blocks_per_cu)
-                              : occ_c<CLASS_PATH>(block, blocks_per_cu);
-}
-
-hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(k_compact_count, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins);
+    hipLaunchKernelGGL(k_compact_scan, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
+    hipLaunchKernelGGL(k_compact_write, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins);
+    hipLaunchKernelGGL(k_moments_final, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
+    hipLaunchKernelGGL(k_stage_out, dim3(STAGE_GRID), dim3(256), 0, s, p.d_hdr, p.d_rows, p.d_fins,
+                       p.h_out_fin, p.h_out_counts);
     return hipGetLastError();
 }
 
@@ -864,24 +1074,6 @@ hipError_t launch_normals(uint64_t seed, uint64_t first, uint64_t n, uint32_t m,
 {
     hipLaunchKernelGGL(k_normals, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, seed, first, n,
                        m, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_abc_finalize(const FinJob *fins, int n_fins, uint64_t total_blocks,
-                               bool any_top, hipStream_t s)
-{
-    const unsigned tb = static_cast<unsigned>(total_blocks);
-    hipLaunchKernelGGL(k_fin_init, dim3(n_fins), dim3(FIN_BLOCK), 0, s, fins);
-    if (any_top) {
-        for (int pass = 0; pass < 3; ++pass) {
-            hipLaunchKernelGGL(k_sel_hist, dim3(tb), dim3(FIN_BLOCK), 0, s, fins, n_fins, pass);
-            hipLaunchKernelGGL(k_sel_pick, dim3(n_fins), dim3(FIN_BLOCK), 0, s, fins, pass);
-        }
-    }
-    hipLaunchKernelGGL(k_compact_count, dim3(tb), dim3(FIN_BLOCK), 0, s, fins, n_fins);
-    hipLaunchKernelGGL(k_compact_scan, dim3(n_fins), dim3(FIN_BLOCK), 0, s, fins);
-    hipLaunchKernelGGL(k_compact_write, dim3(tb), dim3(FIN_BLOCK), 0, s, fins, n_fins);
-    hipLaunchKernelGGL(k_moments_final, dim3(n_fins), dim3(FIN_BLOCK), 0, s, fins);
     return hipGetLastError();
 }
 

@@ -8,26 +8,64 @@
 
 namespace pps {
 
-// Resets the launch state, then runs the persistent simulation kernel over
-// tiles [0, total_tiles) of the job table with `grid` workgroups of `block`.
-// cls: CLASS_PATH (logistic, normal-mean) or CLASS_GARCH; every job in the
-// table must belong to that class.
-// When ev_start / ev_stop are not null they are recorded on `s` right
-// before and after the simulation kernel (after the state reset).
-hipError_t launch_simulate(int cls, int block, const JobDev *jobs, int n_jobs, uint64_t total_tiles,
-                           LaunchState *state, unsigned grid, hipStream_t s,
-                           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
-hipError_t simulate_occupancy(int cls, int block, int *blocks_per_cu);
+// Launch shape of one simulation class: workgroup size, draws per lane (the
+// draws of a lane are simulated interleaved) and Philox blocks generated per
+// loop trip.  Results never depend on the shape.
+struct SimShape {
+    int block = 256;
+    int dpl = 1;
+    int unroll = 1;
+    bool operator==(const SimShape &o) const
+    {
+        return block == o.block && dpl == o.dpl && unroll == o.unroll;
+    }
+};
 
-hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
+// Shape of one epoch: a simulation shape and resident grid per class, and the
+// grid of the per-element finalisation kernels.
+struct EpochShape {
+    SimShape sim[N_CLASSES];
+    unsigned sim_grid[N_CLASSES] = {0, 0};
+    unsigned fin_grid = 0;
+    bool operator==(const EpochShape &o) const
+    {
+        for (int c = 0; c < N_CLASSES; ++c)
+            if (!(sim[c] == o.sim[c]) || sim_grid[c] != o.sim_grid[c])
+                return false;
+        return fin_grid == o.fin_grid;
+    }
+};
+
+constexpr unsigned STAGE_GRID = 64;
+
+// Device-visible addresses used by one epoch slot.  h_* point into mapped
+// pinned host memory; d_* into device memory.
+struct EpochDevPtrs {
+    const EpochHeader *h_hdr = nullptr;
+    const JobDev *h_rows = nullptr;
+    const FinJob *h_fins = nullptr;
+    FinResult *h_out_fin = nullptr;
+    unsigned long long *h_out_counts = nullptr;
+    EpochHeader *d_hdr = nullptr;
+    JobDev *d_rows = nullptr;
+    FinJob *d_fins = nullptr;
+    LaunchState *states = nullptr;  // N_CLASSES
+    hipEvent_t ev_sim_start = nullptr;
+    hipEvent_t ev_sim_stop = nullptr;
+};
+
+bool sim_shape_supported(int cls, const SimShape &sh);
+hipError_t sim_occupancy(int cls, const SimShape &sh, int *blocks_per_cu);
+
+// Issues one whole epoch on `s`: stage-in, the simulation kernel of every
+// class, the ABC finalisation kernels, stage-out.  Every launch shape is fixed
+// by `shape`, so the sequence can be captured once into a graph and replayed
+// with new table contents.
+hipError_t issue_epoch(const EpochDevPtrs &p, const EpochShape &shape, hipStream_t s);
+
 hipError_t launch_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t block,
                          uint32_t purpose, uint32_t *out, hipStream_t s);
 hipError_t launch_normals(uint64_t seed, uint64_t first, uint64_t n, uint32_t m, float *out,
                           hipStream_t s);
-
-// Select (top-fraction jobs), ordered compaction and moments for n_fins
-// ABC jobs whose finalisation blocks span [0, total_blocks).
-hipError_t launch_abc_finalize(const FinJob *fins, int n_fins, uint64_t total_blocks,
-                               bool any_top, hipStream_t s);
 
 }  // namespace pps

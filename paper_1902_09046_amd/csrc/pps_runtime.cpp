@@ -55,28 +55,6 @@ hipError_t DevBuf::ensure(size_t need)
     return hipSuccess;
 }
 
-hipError_t HostBuf::ensure(size_t need)
-{
-    if (need <= bytes && p)
-        return hipSuccess;
-    if (p) {
-        hipError_t e = hipHostFree(p);
-        p = nullptr;
-        bytes = 0;
-        if (e != hipSuccess)
-            return e;
-    }
-    size_t grow = need < 4096 ? 4096 : need + need / 4;
-    hipError_t e = hipHostMalloc(&p, grow, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        p = nullptr;
-        return e;
-    }
-    bytes = grow;
-    return hipSuccess;
-}
-
 static constexpr int kMaxDevices = 64;
 static Context *g_contexts[kMaxDevices];
 static std::mutex g_contexts_mu;
@@ -104,32 +82,16 @@ Context *current_context(int *status)
         Context *c = new Context();
         c->device = dev;
         c->cu_count = prop.multiProcessorCount;
+        c->engine.reset(new EpochEngine());
+        int rc = c->engine->init(1, c->cu_count);
+        if (rc != PPS_OK) {
+            *status = rc;
+            return nullptr;  // the partially built context is leaked on purpose
+        }
         g_contexts[dev] = c;
     }
     *status = PPS_OK;
     return g_contexts[dev];
-}
-
-static int block_index(int block)
-{
-    switch (block) {
-    case 64: return 0;
-    case 128: return 1;
-    case 512: return 3;
-    default: return 2;
-    }
-}
-
-int blocks_per_cu(Context &c, int cls, int block)
-{
-    int &occ = c.occupancy[cls][block_index(block)];
-    if (occ == 0) {
-        int v = 0;
-        if (simulate_occupancy(cls, block, &v) != hipSuccess || v < 1)
-            v = 1;
-        occ = v;
-    }
-    return occ;
 }
 
 int model_class(const pps_model *m) { return m->model == PPS_GARCH11 ? CLASS_GARCH : CLASS_PATH; }
@@ -243,65 +205,78 @@ void fill_job(JobDev &J, const pps_model *m, const pps_sampling *s, int n_summ, 
     J.noise_sd = m->noise_sd;
 }
 
-int launch_rows(Context &c, int cls, std::vector<JobDev> &rows, hipStream_t stream)
+bool g_timing = false;
+
+static size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+size_t abc_scratch_bytes(uint64_t n)
 {
-    const int block = c.shape[cls].block;
-    uint64_t tiles = 0;
-    for (JobDev &r : rows) {
-        r.tile_size = block;
-        r.tile_offset = 0;
-        r.n_tiles = (r.n_draws + block - 1) / block;
-        r.tile_begin = tiles;
-        tiles += r.n_tiles;
-    }
-    const size_t bytes = rows.size() * sizeof(JobDev);
-    hipError_t e = c.h_jobs.ensure(bytes);
-    if (e != hipSuccess)
-        return fail_hip(e, "pinned job staging");
-    e = c.jobs.ensure(bytes);
-    if (e != hipSuccess)
-        return fail_hip(e, "device job table");
-    e = c.state.ensure(sizeof(LaunchState));
-    if (e != hipSuccess)
-        return fail_hip(e, "device launch state");
-    std::memcpy(c.h_jobs.p, rows.data(), bytes);
-    e = hipMemcpyAsync(c.jobs.p, c.h_jobs.p, bytes, hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess)
-        return fail_hip(e, "job table upload");
-    const uint64_t resident = static_cast<uint64_t>(blocks_per_cu(c, cls, block)) * c.cu_count;
-    const unsigned grid = static_cast<unsigned>(tiles < resident ? tiles : resident);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (g_timing) {
-        if (!c.ev_start) {
-            e = hipEventCreate(&c.ev_start);
-            if (e == hipSuccess)
-                e = hipEventCreate(&c.ev_stop);
-            if (e != hipSuccess)
-                return fail_hip(e, "timing events");
-        }
-        e0 = c.ev_start;
-        e1 = c.ev_stop;
-        c.ev_pending = true;
-    }
-    e = launch_simulate(cls, block, c.jobs.as<JobDev>(), static_cast<int>(rows.size()), tiles,
-                        c.state.as<LaunchState>(), grid, stream, e0, e1);
-    if (e != hipSuccess)
-        return fail_hip(e, "simulation launch");
+    const uint64_t nb = (n + FIN_TILE - 1) / FIN_TILE;
+    return align256(n * sizeof(float)) + align256(2 * nb * sizeof(unsigned long long)) +
+           align256(nb * (1 + 2 * PPS_MAX_PARAMS) * sizeof(double)) +
+           align256(SEL_BINS * sizeof(unsigned)) + align256(sizeof(FinResult));
+}
+
+AbcScratch abc_scratch_at(void *base, uint64_t n)
+{
+    const uint64_t nb = (n + FIN_TILE - 1) / FIN_TILE;
+    char *p = static_cast<char *>(base);
+    AbcScratch s;
+    s.dist = reinterpret_cast<float *>(p);
+    p += align256(n * sizeof(float));
+    s.block_counts = reinterpret_cast<unsigned long long *>(p);
+    p += align256(2 * nb * sizeof(unsigned long long));
+    s.partials = reinterpret_cast<double *>(p);
+    p += align256(nb * (1 + 2 * PPS_MAX_PARAMS) * sizeof(double));
+    s.hist = reinterpret_cast<unsigned *>(p);
+    p += align256(SEL_BINS * sizeof(unsigned));
+    s.result = reinterpret_cast<FinResult *>(p);
+    return s;
+}
+
+int validate_abc(const pps_model *m, const double *y_obs, int n_summ, const pps_sampling *s,
+                 int eps_mode, double eps_or_frac)
+{
+    if (m->model == PPS_GARCH11)
+        return fail(PPS_EINVAL, "ABC: GARCH summaries have no observed-data distance here");
+    if (!y_obs)
+        return fail(PPS_EINVAL, "ABC: y_obs is required");
+    if (eps_mode != PPS_EPS_FIXED && eps_mode != PPS_EPS_TOP_FRACTION)
+        return fail(PPS_EINVAL, "ABC: unknown eps_mode %d", eps_mode);
+    if (eps_mode == PPS_EPS_TOP_FRACTION && !(eps_or_frac > 0.0 && eps_or_frac <= 1.0))
+        return fail(PPS_EINVAL, "ABC: fraction must be in (0, 1]");
+    if (eps_mode == PPS_EPS_FIXED && std::isnan(eps_or_frac))
+        return fail(PPS_EINVAL, "ABC: eps is NaN");
+    if (s->n_draws >= (1ull << 32))
+        return fail(PPS_EINVAL, "ABC: n_draws must be < 2^32");
+    for (int k = 0; k < n_summ; ++k)
+        if (!std::isfinite(y_obs[k]))
+            return fail(PPS_EINVAL, "ABC: y_obs[%d] is not finite", k);
     return PPS_OK;
 }
 
-bool g_timing = false;
-
-void collect_timing(Context &c)
+void fill_fin(FinJob &F, const JobDev &row, int eps_mode, double eps_or_frac, uint64_t capacity,
+              uint64_t *acc_idx, float *acc_theta, float *acc_dist, const AbcScratch &scr)
 {
-    if (!c.ev_pending)
-        return;
-    c.ev_pending = false;
-    float ms = -1.0f;
-    if (hipEventElapsedTime(&ms, c.ev_start, c.ev_stop) == hipSuccess)
-        c.last_kernel_ms = ms;
-    else
-        (void)hipGetLastError();
+    std::memset(&F, 0, sizeof F);
+    F.dist = scr.dist;
+    F.n = row.n_draws;
+    F.first_draw = row.first_draw;
+    F.seed = row.seed;
+    F.mode = eps_mode;
+    F.n_params = row.n_params;
+    F.constraint = row.constraint;
+    F.eps = eps_mode == PPS_EPS_FIXED ? eps_or_frac : 0.0;
+    F.k = eps_mode == PPS_EPS_TOP_FRACTION ? top_count(eps_or_frac, row.n_draws) : 0;
+    F.capacity = capacity;
+    std::memcpy(F.prior, row.prior, sizeof F.prior);
+    F.acc_idx = acc_idx;
+    F.acc_theta = acc_theta;
+    F.acc_dist = acc_dist;
+    F.hist = scr.hist;
+    F.block_counts = scr.block_counts;
+    F.partials = scr.partials;
+    F.result = scr.result;
 }
 
 uint64_t top_count(double frac, uint64_t n)

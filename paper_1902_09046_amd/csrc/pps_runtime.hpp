@@ -1,14 +1,17 @@
-// Host runtime of libpps: per-device context, buffers, job-table launches.
+// Host runtime of libpps: errors, buffers, per-device context, validation,
+// job-row and finalisation-row construction.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "pps.h"
+#include "pps_engine.hpp"
 #include "pps_internal.hpp"
 
 namespace pps {
@@ -16,6 +19,8 @@ namespace pps {
 // Records a message for pps_last_error() and returns `code`.
 int fail(int code, const char *fmt, ...);
 int fail_hip(hipError_t e, const char *what);
+const char *last_error();
+void clear_error();
 
 struct DevBuf {
     void *p = nullptr;
@@ -24,40 +29,20 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
-struct HostBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    hipError_t ensure(size_t need);
-    template <class T> T *as() const { return static_cast<T *>(p); }
-};
-
-// Launch shape of the simulation kernel for one model class.
-struct LaunchShape {
-    int block = 256;
-};
-
+// Per-device state of the synchronous entry points: their epoch engine (one
+// slot) and the scratch their jobs use.
 struct Context {
     int device = -1;
     int cu_count = 0;
     std::mutex mu;
-    LaunchShape shape[2];
-    int occupancy[2][4] = {{0}};  // blocks per CU for block sizes 64,128,256,512
-    // device scratch
-    DevBuf jobs, state, fins, results, dist, block_counts, partials, hist, counts;
-    // pinned staging
-    HostBuf h_jobs, h_fins, h_results, h_counts;
-    // kernel timing (see pps_set_timing)
-    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
-    bool ev_pending = false;
+    std::unique_ptr<EpochEngine> engine;
+    DevBuf dist, block_counts, partials, hist, results, counts;
     double last_kernel_ms = -1.0;
 };
 
 extern bool g_timing;
-// After a synchronous call's final stream synchronisation: reads the event
-// pair recorded around the simulation kernel, if any.
-void collect_timing(Context &c);
 
-// Context of the current HIP device (created on first use).
+// Context of the current HIP device (created on first use, engine included).
 Context *current_context(int *status);
 
 int model_class(const pps_model *m);
@@ -65,14 +50,26 @@ int model_class(const pps_model *m);
 int validate_model(const pps_model *m, int *n_summ);
 int validate_sampling(const pps_sampling *s);
 
-// Fills a job row (no tiling, no outputs).
+// Fills a job row for the whole job (tiles assigned by the engine).
 void fill_job(JobDev &J, const pps_model *m, const pps_sampling *s, int n_summ, int flags);
 
-// Assigns tiles to rows (tile size = block), stages the table and launches
-// the persistent simulation kernel of class `cls` on `stream`.
-int launch_rows(Context &c, int cls, std::vector<JobDev> &rows, hipStream_t stream);
+// Per-job device scratch of an ABC finalisation.
+struct AbcScratch {
+    float *dist = nullptr;                    // n floats
+    unsigned long long *block_counts = nullptr;  // 2 * blocks
+    double *partials = nullptr;               // blocks * (1 + 2 * PPS_MAX_PARAMS)
+    unsigned *hist = nullptr;                 // SEL_BINS
+    FinResult *result = nullptr;              // 1
+};
+size_t abc_scratch_bytes(uint64_t n);
+// Carves an AbcScratch out of `base` (abc_scratch_bytes(n) bytes, 256-aligned).
+AbcScratch abc_scratch_at(void *base, uint64_t n);
 
-int blocks_per_cu(Context &c, int cls, int block);
+// Validates the ABC arguments shared by abc_sample and the server.
+int validate_abc(const pps_model *m, const double *y_obs, int n_summ, const pps_sampling *s,
+                 int eps_mode, double eps_or_frac);
+void fill_fin(FinJob &F, const JobDev &row, int eps_mode, double eps_or_frac, uint64_t capacity,
+              uint64_t *acc_idx, float *acc_theta, float *acc_dist, const AbcScratch &scr);
 
 uint64_t top_count(double frac, uint64_t n);
 

@@ -266,6 +266,44 @@ def test_sharding_invariance(P, torch):
                                       np.concatenate([b[key].cpu().numpy(), c[key].cpu().numpy()]))
 
 
+def test_launch_shape_invariance(P, torch):
+    """Every supported launch shape (workgroup size, draws per lane, Philox
+    blocks per loop trip) gives bit-identical per-draw results and ABC output."""
+    y = np.array(observed()["logistic_S1000"]["y_obs"])
+    spec = W.logistic_spec(steps=200)
+    n = 3001
+    keep = P.pps_get_launch_shape(0)
+    try:
+        ref = None
+        for shape in P.PATH_SHAPES:
+            P.pps_set_launch_shape(0, *shape)
+            g = P.simulate(spec, 8, 5, n, y_obs=y)
+            a = P.abc(spec, y, 8, 5, n, P.PPS_EPS_TOP_FRACTION, 0.02)
+            cur = [g[k].cpu().numpy() for k in ("theta", "summ", "stat", "dist")] + \
+                  [a["idx"].cpu().numpy(), a["theta"].cpu().numpy(), a["dist"].cpu().numpy(),
+                   np.array([a["eps_used"]]), a["mean"], a["var"]]
+            if ref is None:
+                ref = cur
+            else:
+                for x, r in zip(cur, ref):
+                    np.testing.assert_array_equal(x, r, err_msg=str(shape))
+    finally:
+        P.pps_set_launch_shape(0, *keep)
+    keep = P.pps_get_launch_shape(1)
+    try:
+        gs = W.garch_spec(series_len=200)
+        ref = None
+        for shape in P.GARCH_SHAPES:
+            P.pps_set_launch_shape(1, *shape)
+            cur = P.simulate(gs, 2, 0, 1500)["summ"].cpu().numpy()
+            if ref is None:
+                ref = cur
+            else:
+                np.testing.assert_array_equal(cur, ref, err_msg=str(shape))
+    finally:
+        P.pps_set_launch_shape(1, *keep)
+
+
 def test_invalid_arguments_raise(P, torch):
     spec = W.logistic_spec(steps=999)
     with pytest.raises(P.PPSError):
