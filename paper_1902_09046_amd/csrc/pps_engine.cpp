@@ -33,8 +33,9 @@ EpochEngine::~EpochEngine()
     for (Slot &s : slots_) {
         if (s.in_flight && s.done)
             (void)hipEventSynchronize(s.done);
-        if (s.exec)
-            (void)hipGraphExecDestroy(s.exec);
+        for (hipGraphExec_t &x : s.exec)
+            if (x)
+                (void)hipGraphExecDestroy(x);
     }
 }
 
@@ -82,8 +83,8 @@ int EpochEngine::init(int n_slots, int cu_count)
             return fail_hip(e, "launch state");
         s.dev.states = static_cast<LaunchState *>(p);
         if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess ||
-            (e = hipEventCreate(&s.dev.ev_sim_start)) != hipSuccess ||
-            (e = hipEventCreate(&s.dev.ev_sim_stop)) != hipSuccess)
+            (e = hipEventCreate(&s.sim_start)) != hipSuccess ||
+            (e = hipEventCreate(&s.sim_stop)) != hipSuccess)
             return fail_hip(e, "epoch events");
     }
     return PPS_OK;
@@ -102,32 +103,37 @@ int EpochEngine::build_graph(Slot &s)
         want.sim_grid[c] = static_cast<unsigned>(per_cu * cu_count_);
     }
     want.fin_grid = static_cast<unsigned>(8 * cu_count_);
-    if (s.exec && s.exec_shape == want)
+    if (s.have_exec && s.exec_shape == want)
         return PPS_OK;
-    if (s.exec) {
-        (void)hipGraphExecDestroy(s.exec);
-        s.exec = nullptr;
+    for (hipGraphExec_t &x : s.exec) {
+        if (x)
+            (void)hipGraphExecDestroy(x);
+        x = nullptr;
     }
-    hipError_t e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess)
-        return fail_hip(e, "graph capture begin");
-    hipError_t ei = issue_epoch(s.dev, want, capture_stream_);
-    hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(capture_stream_, &graph);
-    if (ei != hipSuccess) {
-        if (graph)
-            (void)hipGraphDestroy(graph);
-        return fail_hip(ei, "epoch capture");
-    }
-    if (e != hipSuccess)
-        return fail_hip(e, "graph capture end");
-    e = hipGraphInstantiate(&s.exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-        s.exec = nullptr;
-        return fail_hip(e, "graph instantiate");
+    s.have_exec = false;
+    for (int part = 0; part < EPOCH_PARTS; ++part) {
+        hipError_t e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess)
+            return fail_hip(e, "graph capture begin");
+        hipError_t ei = issue_epoch_part(part, s.dev, want, capture_stream_);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(capture_stream_, &graph);
+        if (ei != hipSuccess) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return fail_hip(ei, "epoch capture");
+        }
+        if (e != hipSuccess)
+            return fail_hip(e, "graph capture end");
+        e = hipGraphInstantiate(&s.exec[part], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            s.exec[part] = nullptr;
+            return fail_hip(e, "graph instantiate");
+        }
     }
     s.exec_shape = want;
+    s.have_exec = true;
     return PPS_OK;
 }
 
@@ -181,7 +187,15 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
     }
     H.n_fins = static_cast<uint32_t>(plan.fins.size());
     H.fin_blocks = fb;
-    hipError_t e = hipGraphLaunch(s.exec, stream);
+    hipError_t e = hipGraphLaunch(s.exec[EPOCH_STAGE_IN], stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(s.sim_start, stream);
+    if (e == hipSuccess)
+        e = hipGraphLaunch(s.exec[EPOCH_SIMULATE], stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(s.sim_stop, stream);
+    if (e == hipSuccess)
+        e = hipGraphLaunch(s.exec[EPOCH_FINALIZE], stream);
     if (e != hipSuccess)
         return fail_hip(e, "epoch graph launch");
     e = hipEventRecord(s.done, stream);
@@ -195,7 +209,7 @@ int EpochEngine::finish(Slot &s)
 {
     s.in_flight = false;
     float ms = -1.0f;
-    if (hipEventElapsedTime(&ms, s.dev.ev_sim_start, s.dev.ev_sim_stop) != hipSuccess) {
+    if (hipEventElapsedTime(&ms, s.sim_start, s.sim_stop) != hipSuccess) {
         (void)hipGetLastError();
         ms = -1.0f;
     }

@@ -74,9 +74,10 @@ class EpochEngine {
         FinResult *h_out_fin = nullptr;
         unsigned long long *h_out_counts = nullptr;
         EpochDevPtrs dev;
-        hipGraphExec_t exec = nullptr;
+        hipGraphExec_t exec[EPOCH_PARTS] = {nullptr, nullptr, nullptr};
+        bool have_exec = false;
         EpochShape exec_shape;
-        hipEvent_t done = nullptr;
+        hipEvent_t sim_start = nullptr, sim_stop = nullptr, done = nullptr;
         bool in_flight = false;
         float sim_ms = -1.0f;
     };

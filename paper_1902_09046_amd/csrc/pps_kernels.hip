@@ -1026,26 +1026,26 @@ hipError_t sim_occupancy(int cls, const SimShape &sh, int *blocks_per_cu)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, sh.block, 0);
 }
 
-hipError_t issue_epoch(const EpochDevPtrs &p, const EpochShape &shape, hipStream_t s)
+hipError_t issue_epoch_part(int part, const EpochDevPtrs &p, const EpochShape &shape, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stage_in, dim3(STAGE_GRID), dim3(256), 0, s, p.h_hdr, p.h_rows, p.h_fins,
-                       p.d_hdr, p.d_rows, p.d_fins, p.states);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    if (p.ev_sim_start && (e = hipEventRecord(p.ev_sim_start, s)) != hipSuccess)
-        return e;
-    for (int c = 0; c < N_CLASSES; ++c) {
-        SimKernel k = sim_kernel(c, shape.sim[c]);
-        if (!k)
-            return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k, dim3(shape.sim_grid[c]), dim3(shape.sim[c].block), 0, s, p.d_hdr,
-                           p.d_rows, p.states);
-        if ((e = hipGetLastError()) != hipSuccess)
-            return e;
+    if (part == EPOCH_STAGE_IN) {
+        hipLaunchKernelGGL(k_stage_in, dim3(STAGE_GRID), dim3(256), 0, s, p.h_hdr, p.h_rows,
+                           p.h_fins, p.d_hdr, p.d_rows, p.d_fins, p.states);
+        return hipGetLastError();
     }
-    if (p.ev_sim_stop && (e = hipEventRecord(p.ev_sim_stop, s)) != hipSuccess)
-        return e;
+    if (part == EPOCH_SIMULATE) {
+        for (int c = 0; c < N_CLASSES; ++c) {
+            SimKernel k = sim_kernel(c, shape.sim[c]);
+            if (!k)
+                return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k, dim3(shape.sim_grid[c]), dim3(shape.sim[c].block), 0, s, p.d_hdr,
+                               p.d_rows, p.states);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    }
     const dim3 fb(FIN_BLOCK);
     hipLaunchKernelGGL(k_fin_init, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
     for (int pass = 0; pass < 3; ++pass) {

@@ -50,18 +50,18 @@ struct EpochDevPtrs {
     JobDev *d_rows = nullptr;
     FinJob *d_fins = nullptr;
     LaunchState *states = nullptr;  // N_CLASSES
-    hipEvent_t ev_sim_start = nullptr;
-    hipEvent_t ev_sim_stop = nullptr;
 };
 
 bool sim_shape_supported(int cls, const SimShape &sh);
 hipError_t sim_occupancy(int cls, const SimShape &sh, int *blocks_per_cu);
 
-// Issues one whole epoch on `s`: stage-in, the simulation kernel of every
-// class, the ABC finalisation kernels, stage-out.  Every launch shape is fixed
-// by `shape`, so the sequence can be captured once into a graph and replayed
-// with new table contents.
-hipError_t issue_epoch(const EpochDevPtrs &p, const EpochShape &shape, hipStream_t s);
+// An epoch is three parts issued in order on one stream: stage-in; the
+// simulation kernel of every class; the ABC finalisation kernels and
+// stage-out.  Every launch shape is fixed by `shape`, so each part is captured
+// once into a graph and replayed with new table contents; timing events are
+// recorded between the parts.
+enum { EPOCH_STAGE_IN = 0, EPOCH_SIMULATE = 1, EPOCH_FINALIZE = 2, EPOCH_PARTS = 3 };
+hipError_t issue_epoch_part(int part, const EpochDevPtrs &p, const EpochShape &shape, hipStream_t s);
 
 hipError_t launch_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t block,
                          uint32_t purpose, uint32_t *out, hipStream_t s);
