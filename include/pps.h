@@ -191,6 +191,107 @@ int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_famil
 int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
                       const double *obs_summ, uint64_t *count_ge, void *stream);
 
+/* ---- jobs, batches and serving ------------------------------------------ */
+/* A job is one ABC run (Alg. 1, fixed-N form) or one prior-predictive p-value
+ * at one lambda (Eq. pppvhype).  Jobs of different N, step count, lambda and
+ * kind are run together: their tiles share persistent launches ("epochs"),
+ * each job's result being identical to the one it gets alone (every draw is
+ * keyed by (seed, i); tallies are integers; moments are reduced in a fixed
+ * order per job). */
+enum pps_job_kind { PPS_JOB_ABC = 0, PPS_JOB_PVALUE = 1 };
+
+typedef struct {
+    int32_t kind;           /* enum pps_job_kind */
+    pps_model model;        /* logistic SDE or normal-mean */
+    pps_sampling sampling;
+    /* ABC */
+    double y_obs[PPS_MAX_OBS]; /* observed summaries (n_summaries values) */
+    int32_t eps_mode;       /* enum pps_eps_mode */
+    double eps_or_frac;
+    uint64_t capacity;      /* FIXED: records kept (later ones only counted);
+                               TOP_FRACTION: ignored (all k records are kept) */
+    /* p-value: parameter lambda_param gets (lambda_family, a = model's a,
+       b = lambda); count of T_i >= t_obs */
+    int32_t lambda_param;
+    int32_t lambda_family;
+    double lambda;
+    double t_obs;
+} pps_job;
+
+typedef struct {
+    int32_t status;         /* PPS_OK, PPS_ETRUNC (ABC records truncated) or an error */
+    int32_t kind;
+    pps_abc_stats abc;      /* ABC statistics */
+    uint64_t count_ge;      /* p-value tally */
+    double pvalue;
+    /* ABC records (device pointers into the arena, increasing draw index;
+       valid until the job is released / the arena is reused):
+       acc_idx[r], acc_theta[j * record_stride + r], acc_dist[r], r < n_records. */
+    const uint64_t *acc_idx;
+    const float *acc_theta;
+    const float *acc_dist;
+    uint64_t n_records;
+    uint64_t record_stride;
+    /* steady-clock seconds: submitted, admitted (memory reserved), result visible */
+    double t_submit, t_admit, t_done;
+} pps_job_result;
+
+enum pps_policy {
+    PPS_POLICY_BATCHED = 0, /* continuous batching: many jobs' tiles per epoch,
+                               jobs admitted while others run */
+    PPS_POLICY_PLAIN = 1    /* one job per epoch, each epoch waited for before
+                               the next is launched (the one-job-per-launch path) */
+};
+
+typedef struct {
+    void *arena;            /* device memory for per-job scratch and ABC records
+                               (caller-owned, >= 256-byte aligned) */
+    uint64_t arena_bytes;
+    int32_t max_active;     /* jobs admitted at once (1..1024) */
+    int32_t queue_capacity; /* submissions waiting for admission (pps_submit
+                               returns PPS_EBUSY beyond this) */
+    double epoch_ms;        /* target GPU time of one epoch (planning budget) */
+    int32_t policy;         /* enum pps_policy */
+    void *stream;           /* HIP stream of the epochs; NULL: a stream of the
+                               server's own (default priority) */
+} pps_server_config;
+
+/* Bytes of arena a job needs while admitted (ABC: distances, finalisation
+ * scratch and records; p-value: its tally), or a negative status. */
+int64_t pps_job_arena_bytes(const pps_job *job);
+
+/* Runs n_jobs jobs to completion with the same scheduler as the server (no
+ * thread): jobs are admitted in order as arena memory allows.  results[i]
+ * gets job i's result; the records stay in the arena until it is reused.
+ * Returns PPS_OK when every job ran (per-job status in results[i].status).
+ * config->queue_capacity is ignored. */
+int pps_run_batch(const pps_job *jobs, int n_jobs, const pps_server_config *config,
+                  pps_job_result *results);
+
+typedef struct pps_server pps_server;
+int pps_server_create(const pps_server_config *config, pps_server **server);
+/* Queues a copy of *job; never blocks.  PPS_EBUSY when the queue is full,
+ * PPS_EINVAL for an invalid job (message in pps_last_error). */
+int pps_submit(pps_server *server, const pps_job *job, uint64_t *job_id);
+/* PPS_PENDING while the job runs; PPS_OK (or the job's error status) with
+ * *out filled once its result is visible; PPS_ENOTFOUND for unknown or
+ * released ids. */
+int pps_poll(pps_server *server, uint64_t job_id, pps_job_result *out);
+/* Frees a finished job's arena memory.  PPS_EBUSY if it has not finished,
+ * PPS_ENOTFOUND if unknown or already released. */
+int pps_release(pps_server *server, uint64_t job_id);
+
+typedef struct {
+    uint64_t submitted, completed, epochs;
+    uint64_t queued, active;   /* right now */
+    double busy_s;             /* sum of epoch simulation-kernel times */
+    double latency_p50_s, latency_p99_s; /* submit -> visible, completed jobs */
+} pps_server_stats;
+int pps_server_stats_get(pps_server *server, pps_server_stats *stats);
+/* Stops the server thread after the epochs in flight finish; pending jobs
+ * are dropped.  The arena is not freed (it belongs to the caller). */
+int pps_server_destroy(pps_server *server);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Kernel timing.  While enabled (process-wide; off by default) every call

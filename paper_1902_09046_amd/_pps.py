@@ -65,6 +65,64 @@ class pps_abc_stats(ctypes.Structure):
                 ("mean", ctypes.c_double * PPS_MAX_PARAMS), ("var", ctypes.c_double * PPS_MAX_PARAMS)]
 
 
+PPS_JOB_ABC, PPS_JOB_PVALUE = 0, 1
+PPS_POLICY_BATCHED, PPS_POLICY_PLAIN = 0, 1
+
+
+class pps_job(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("model", pps_model),
+        ("sampling", pps_sampling),
+        ("y_obs", ctypes.c_double * PPS_MAX_OBS),
+        ("eps_mode", ctypes.c_int32),
+        ("eps_or_frac", ctypes.c_double),
+        ("capacity", ctypes.c_uint64),
+        ("lambda_param", ctypes.c_int32),
+        ("lambda_family", ctypes.c_int32),
+        ("lambda_", ctypes.c_double),
+        ("t_obs", ctypes.c_double),
+    ]
+
+
+class pps_job_result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("kind", ctypes.c_int32),
+        ("abc", pps_abc_stats),
+        ("count_ge", ctypes.c_uint64),
+        ("pvalue", ctypes.c_double),
+        ("acc_idx", ctypes.c_void_p),
+        ("acc_theta", ctypes.c_void_p),
+        ("acc_dist", ctypes.c_void_p),
+        ("n_records", ctypes.c_uint64),
+        ("record_stride", ctypes.c_uint64),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
+class pps_server_config(ctypes.Structure):
+    _fields_ = [
+        ("arena", ctypes.c_void_p),
+        ("arena_bytes", ctypes.c_uint64),
+        ("max_active", ctypes.c_int32),
+        ("queue_capacity", ctypes.c_int32),
+        ("epoch_ms", ctypes.c_double),
+        ("policy", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class pps_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("epochs", ctypes.c_uint64),
+        ("queued", ctypes.c_uint64), ("active", ctypes.c_uint64), ("busy_s", ctypes.c_double),
+        ("latency_p50_s", ctypes.c_double), ("latency_p99_s", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -102,8 +160,20 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         L.pps_get_launch_shape.argtypes = [ctypes.c_int, ip, ip, ip]
         L.pps_get_launch_shape.restype = ctypes.c_int
+        jp, rp, cp = ctypes.POINTER(pps_job), ctypes.POINTER(pps_job_result), ctypes.POINTER(pps_server_config)
+        L.pps_job_arena_bytes.argtypes = [jp]
+        L.pps_job_arena_bytes.restype = ctypes.c_int64
+        L.pps_run_batch.argtypes = [jp, ctypes.c_int, cp, rp]
+        L.pps_server_create.argtypes = [cp, ctypes.POINTER(ctypes.c_void_p)]
+        L.pps_submit.argtypes = [vp, jp, ctypes.POINTER(ctypes.c_uint64)]
+        L.pps_poll.argtypes = [vp, u64, rp]
+        L.pps_release.argtypes = [vp, u64]
+        L.pps_server_stats_get.argtypes = [vp, ctypes.POINTER(pps_server_stats)]
+        L.pps_server_destroy.argtypes = [vp]
         for name in ("pps_philox", "pps_normals", "pps_simulate", "pps_n_summaries", "abc_sample",
-                     "prior_pred_pvalue", "pps_summary_tally"):
+                     "prior_pred_pvalue", "pps_summary_tally", "pps_run_batch", "pps_server_create",
+                     "pps_submit", "pps_poll", "pps_release", "pps_server_stats_get",
+                     "pps_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -281,3 +351,130 @@ def abc(spec: Mapping, y_obs, seed: int, first: int, n: int, eps_mode: int, eps_
     k = min(st["n_accepted"], capacity)
     st.update({"status": rc, "idx": idx[:k], "theta": th[:, :k], "dist": d[:k]})
     return st
+
+
+# --------------------------------------------------------------------------
+# Jobs, batches and serving.
+# --------------------------------------------------------------------------
+def make_abc_job(spec: Mapping, y_obs, sampling: pps_sampling, eps_mode: int, eps_or_frac: float,
+                 capacity: int = 0) -> pps_job:
+    j = pps_job()
+    j.kind = PPS_JOB_ABC
+    j.model = make_model(spec)
+    j.sampling = sampling
+    for k, v in enumerate(y_obs):
+        j.y_obs[k] = float(v)
+    j.eps_mode = eps_mode
+    j.eps_or_frac = float(eps_or_frac)
+    j.capacity = int(capacity)
+    return j
+
+
+def make_pvalue_job(spec: Mapping, lambda_param: int, lambda_family: int, lam: float,
+                    sampling: pps_sampling, t_obs: float) -> pps_job:
+    j = pps_job()
+    j.kind = PPS_JOB_PVALUE
+    j.model = make_model(spec)
+    j.sampling = sampling
+    j.lambda_param = lambda_param
+    j.lambda_family = lambda_family
+    j.lambda_ = float(lam)
+    j.t_obs = float(t_obs)
+    return j
+
+
+def make_server_config(arena, arena_bytes: int | None = None, max_active: int = 256,
+                       queue_capacity: int = 0, epoch_ms: float = 4.0,
+                       policy: int = PPS_POLICY_BATCHED, stream=None) -> pps_server_config:
+    c = pps_server_config()
+    c.arena = int(arena.data_ptr())
+    c.arena_bytes = int(arena_bytes if arena_bytes is not None else arena.numel() * arena.element_size())
+    c.max_active = max_active
+    c.queue_capacity = queue_capacity
+    c.epoch_ms = epoch_ms
+    c.policy = policy
+    c.stream = None if stream is None else int(stream)
+    return c
+
+
+def pps_job_arena_bytes(job: pps_job) -> int:
+    return _check_count(lib().pps_job_arena_bytes(ctypes.byref(job)))
+
+
+def pps_run_batch(jobs, config: pps_server_config):
+    arr = (pps_job * len(jobs))(*jobs)
+    res = (pps_job_result * len(jobs))()
+    _check(lib().pps_run_batch(arr, len(jobs), ctypes.byref(config), res))
+    return list(res)
+
+
+class Server:
+    """pps_server_create / pps_submit / pps_poll / pps_release / pps_server_destroy."""
+
+    def __init__(self, config: pps_server_config):
+        self._cfg = config
+        h = ctypes.c_void_p()
+        _check(lib().pps_server_create(ctypes.byref(config), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, job: pps_job) -> int:
+        jid = ctypes.c_uint64()
+        _check(lib().pps_submit(self._h, ctypes.byref(job), ctypes.byref(jid)))
+        return int(jid.value)
+
+    def try_submit(self, job: pps_job):
+        """Returns the job id, or None when the queue is full."""
+        jid = ctypes.c_uint64()
+        rc = lib().pps_submit(self._h, ctypes.byref(job), ctypes.byref(jid))
+        if rc == PPS_EBUSY:
+            return None
+        _check(rc)
+        return int(jid.value)
+
+    def poll(self, job_id: int):
+        """(status, result): status PPS_PENDING while running."""
+        r = pps_job_result()
+        rc = lib().pps_poll(self._h, job_id, ctypes.byref(r))
+        if rc == PPS_ENOTFOUND:
+            _check(rc)
+        return rc, r
+
+    def release(self, job_id: int) -> int:
+        return lib().pps_release(self._h, job_id)
+
+    def stats(self) -> pps_server_stats:
+        s = pps_server_stats()
+        _check(lib().pps_server_stats_get(self._h, ctypes.byref(s)))
+        return s
+
+    def close(self):
+        if self._h:
+            _check(lib().pps_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def records(result: pps_job_result, arena, n_params: int):
+    """A finished ABC job's records (index, theta (n_params, n), dist) as
+    numpy arrays, read from the arena tensor the results point into."""
+    n = int(result.n_records)
+    base = int(arena.data_ptr())
+    raw = arena.view(-1).view(__import__("torch").uint8)
+
+    def span(ptr, nbytes):
+        off = int(ptr) - base
+        return raw[off:off + nbytes]
+
+    if n == 0:
+        return np.zeros(0, np.uint64), np.zeros((n_params, 0), np.float32), np.zeros(0, np.float32)
+    stride = int(result.record_stride)
+    idx = span(result.acc_idx, 8 * n).cpu().numpy().view(np.uint64).copy()
+    th = np.stack([span(result.acc_theta + 4 * j * stride, 4 * n).cpu().numpy().view(np.float32)
+                   for j in range(n_params)])
+    d = span(result.acc_dist, 4 * n).cpu().numpy().view(np.float32).copy()
+    return idx, th, d

@@ -28,15 +28,27 @@ template <class T> static T *dev_view(T *host)
 
 EpochEngine::~EpochEngine()
 {
-    // Staging memory, device tables and events are kept for the life of the
-    // process (engines are long-lived); only the graphs are released.
     for (Slot &s : slots_) {
         if (s.in_flight && s.done)
             (void)hipEventSynchronize(s.done);
         for (hipGraphExec_t &x : s.exec)
             if (x)
                 (void)hipGraphExecDestroy(x);
+        for (void *h : {static_cast<void *>(s.h_hdr), static_cast<void *>(s.h_rows),
+                        static_cast<void *>(s.h_fins), static_cast<void *>(s.h_out_fin),
+                        static_cast<void *>(s.h_out_counts)})
+            if (h)
+                (void)hipHostFree(h);
+        for (void *d : {static_cast<void *>(s.dev.d_hdr), static_cast<void *>(s.dev.d_rows),
+                        static_cast<void *>(s.dev.d_fins), static_cast<void *>(s.dev.states)})
+            if (d)
+                (void)hipFree(d);
+        for (hipEvent_t ev : {s.sim_start, s.sim_stop, s.done})
+            if (ev)
+                (void)hipEventDestroy(ev);
     }
+    if (capture_stream_)
+        (void)hipStreamDestroy(capture_stream_);
 }
 
 int EpochEngine::init(int n_slots, int cu_count)

@@ -35,7 +35,8 @@ struct Context {
     int device = -1;
     int cu_count = 0;
     std::mutex mu;
-    std::unique_ptr<EpochEngine> engine;
+    std::unique_ptr<EpochEngine> engine;        // synchronous calls (one slot)
+    std::unique_ptr<EpochEngine> batch_engine;  // pps_run_batch (two slots)
     DevBuf dist, block_counts, partials, hist, results, counts;
     double last_kernel_ms = -1.0;
 };

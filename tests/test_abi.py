@@ -59,6 +59,13 @@ int main(void) {
          offsetof(pps_model, x0), offsetof(pps_model, t_end), offsetof(pps_model, steps),
          offsetof(pps_model, n_obs), offsetof(pps_model, noise_sd));
   printf("%zu %zu %zu\n", offsetof(pps_abc_stats, eps_used), offsetof(pps_abc_stats, mean), offsetof(pps_abc_stats, var));
+  printf("%zu %zu %zu %zu\n", sizeof(pps_job), sizeof(pps_job_result), sizeof(pps_server_config), sizeof(pps_server_stats));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", offsetof(pps_job, model), offsetof(pps_job, sampling), offsetof(pps_job, y_obs),
+         offsetof(pps_job, eps_mode), offsetof(pps_job, capacity), offsetof(pps_job, lambda_param), offsetof(pps_job, lambda), offsetof(pps_job, t_obs));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(pps_job_result, abc), offsetof(pps_job_result, count_ge), offsetof(pps_job_result, acc_idx),
+         offsetof(pps_job_result, n_records), offsetof(pps_job_result, record_stride), offsetof(pps_job_result, t_done));
+  printf("%zu %zu %zu %zu\n", offsetof(pps_server_config, max_active), offsetof(pps_server_config, epoch_ms), offsetof(pps_server_config, policy),
+         offsetof(pps_server_config, stream));
   return 0;
 }
 """
@@ -80,6 +87,15 @@ def test_struct_layout_matches_binding(P):
                     ("prior", "constraint", "x0", "t_end", "steps", "n_obs", "noise_sd")]
     offs2 = [int(v) for v in lines[2].split()]
     assert offs2 == [getattr(B.pps_abc_stats, f).offset for f in ("eps_used", "mean", "var")]
+    assert [int(v) for v in lines[3].split()] == [ctypes.sizeof(B.pps_job), ctypes.sizeof(B.pps_job_result),
+                                                  ctypes.sizeof(B.pps_server_config),
+                                                  ctypes.sizeof(B.pps_server_stats)]
+    assert [int(v) for v in lines[4].split()] == [getattr(B.pps_job, f).offset for f in (
+        "model", "sampling", "y_obs", "eps_mode", "capacity", "lambda_param", "lambda_", "t_obs")]
+    assert [int(v) for v in lines[5].split()] == [getattr(B.pps_job_result, f).offset for f in (
+        "abc", "count_ge", "acc_idx", "n_records", "record_stride", "t_done")]
+    assert [int(v) for v in lines[6].split()] == [getattr(B.pps_server_config, f).offset for f in (
+        "max_active", "epoch_ms", "policy", "stream")]
 
 
 def test_validation_without_device(P):
@@ -137,6 +153,37 @@ def test_validation_without_device(P):
                                None) == P.PPS_EINVAL
     assert L.pps_philox(1, 0, 0, 0, 0, None, None) == P.PPS_EINVAL
     assert L.pps_normals(1, 0, 10, 0, None, None) == P.PPS_EINVAL
+
+
+def test_job_arena_bytes_and_server_validation(P):
+    """Arena sizing and argument checks that answer without a device."""
+    import pps_workloads as W
+    L = P.lib()
+    spec = W.logistic_spec()
+    s = P.make_sampling(100_000, 0, 1)
+    j = P.make_abc_job(spec, np.zeros(20), s, P.PPS_EPS_TOP_FRACTION, 0.01)
+    need = P.pps_job_arena_bytes(j)
+    assert need >= 100_000 * 4 + 1000 * (8 + 16 + 4)  # distances + 1000 records
+    pj = P.make_pvalue_job(W.pvalue_spec(), 0, P.PPS_LOGNORMAL, 0.5, s, 70.0)
+    assert P.pps_job_arena_bytes(pj) == 256
+    bad = P.make_pvalue_job(W.pvalue_spec(), 5, P.PPS_LOGNORMAL, 0.5, s, 70.0)
+    assert L.pps_job_arena_bytes(ctypes.byref(bad)) == P.PPS_EINVAL
+    bad2 = P.make_abc_job(spec, np.zeros(20), s, P.PPS_EPS_TOP_FRACTION, 2.0)
+    assert L.pps_job_arena_bytes(ctypes.byref(bad2)) == P.PPS_EINVAL
+    cfg = P._pps.pps_server_config()
+    h = ctypes.c_void_p()
+    assert L.pps_server_create(ctypes.byref(cfg), ctypes.byref(h)) == P.PPS_EINVAL  # no arena
+    cfg.arena, cfg.arena_bytes, cfg.max_active, cfg.epoch_ms = 4096, 1 << 20, 0, 1.0
+    assert L.pps_server_create(ctypes.byref(cfg), ctypes.byref(h)) == P.PPS_EINVAL  # max_active
+    cfg.max_active, cfg.epoch_ms = 8, 0.0
+    assert L.pps_server_create(ctypes.byref(cfg), ctypes.byref(h)) == P.PPS_EINVAL  # epoch_ms
+    cfg.epoch_ms, cfg.arena = 1.0, 4097
+    assert L.pps_server_create(ctypes.byref(cfg), ctypes.byref(h)) == P.PPS_EINVAL  # alignment
+    cfg.arena = 4096
+    res = (P._pps.pps_job_result * 1)()
+    arr = (P._pps.pps_job * 1)(bad)
+    assert L.pps_run_batch(arr, 1, ctypes.byref(cfg), res) == P.PPS_EINVAL  # invalid job
+    assert L.pps_submit(None, ctypes.byref(j), ctypes.byref(ctypes.c_uint64())) == P.PPS_EINVAL
 
 
 def test_strerror(P):
