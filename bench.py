@@ -95,6 +95,78 @@ def time_calls(P, torch, fn, warmup: int, reps: int):
     return (time.perf_counter() - t0) / reps, sum(ks) / len(ks)
 
 
+def serving_bench(P, torch, W, golden, n_jobs: int, rate_hz: float):
+    """The serving mix: open-loop Poisson arrivals through the server (latency
+    percentiles), then every job submitted at once, batched vs plain."""
+    import numpy as np
+    jobs_spec = W.serving_jobs(n_jobs=n_jobs, rate_hz=rate_hz, seed=W.SERVING_MIX["seed"])
+    ob = golden["logistic_S1000"]
+    lam = W.lambda_grid(64)
+    jobs = []
+    draw_steps = 0
+    for js in jobs_spec:
+        s = P.make_sampling(js["n"], 0, js["seed"])
+        if js["kind"] == "abc":
+            jobs.append(P.make_abc_job(W.logistic_spec(steps=js["steps"]), ob["y_obs"], s,
+                                       P.PPS_EPS_TOP_FRACTION, 0.01))
+        else:
+            jobs.append(P.make_pvalue_job(W.pvalue_spec(steps=js["steps"]), 0, P.PPS_LOGNORMAL,
+                                          float(lam[js["lambda_index"]]), s, ob["t_obs"]))
+        draw_steps += js["n"] * js["steps"]
+    need = sum(P.pps_job_arena_bytes(j) for j in jobs)
+    arena = torch.empty(need + (64 << 20), dtype=torch.uint8, device="cuda")
+    total_draws = sum(js["n"] for js in jobs_spec)
+    out = {"jobs": n_jobs, "rate_hz": rate_hz, "draws": total_draws, "sde_steps": draw_steps}
+
+    # open loop: arrivals at their Poisson times; latency = submit -> visible
+    print(f"bench: serving open loop {n_jobs} jobs at {rate_hz}/s", file=sys.stderr, flush=True)
+    cfg = P.make_server_config(arena, epoch_ms=2.0, max_active=1024)
+    with P.Server(cfg) as srv:
+        t0 = time.perf_counter()
+        ids = []
+        for js, j in zip(jobs_spec, jobs):
+            delay = js["arrival_s"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(j))
+        lat = []
+        for jid in ids:
+            while True:
+                rc, r = srv.poll(jid)
+                if rc != P.PPS_PENDING:
+                    break
+                time.sleep(0.0005)
+            if rc not in (P.PPS_OK, P.PPS_ETRUNC):
+                raise RuntimeError(f"serving job failed with status {rc}")
+            lat.append(r.t_done - r.t_submit)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    lat = np.array(lat)
+    out["open_loop"] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                        "mean_ms": round(float(lat.mean()) * 1e3, 3), "wall_s": round(wall, 3),
+                        "epochs": int(st.epochs), "gpu_busy_s": round(st.busy_s, 3)}
+
+    # saturated: all jobs at t = 0, continuous batching vs one job per launch
+    sat = {}
+    for name, pol in (("batched", P.PPS_POLICY_BATCHED), ("plain", P.PPS_POLICY_PLAIN)):
+        print(f"bench: serving saturated {name}", file=sys.stderr, flush=True)
+        cfg = P.make_server_config(arena, epoch_ms=8.0, max_active=1024, policy=pol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = P.pps_run_batch(jobs, cfg)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bad = [r.status for r in res if r.status not in (P.PPS_OK, P.PPS_ETRUNC)]
+        if bad:
+            raise RuntimeError(f"saturated {name}: job status {bad[0]}")
+        sat[name] = {"wall_s": round(dt, 4), "sims_per_s": round(total_draws / dt, 1),
+                     "sde_steps_per_s": round(draw_steps / dt, 1)}
+    sat["batched_over_plain"] = round(sat["plain"]["wall_s"] / sat["batched"]["wall_s"], 3)
+    out["saturated"] = sat
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,7 +176,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="draws of the oracle's timed sample (0 disables the CPU baseline)")
     ap.add_argument("--only-main", action="store_true",
-                    help="skip the p-value batch and GARCH workloads")
+                    help="skip the p-value batch, GARCH and serving workloads")
+    ap.add_argument("--serving-jobs", type=int, default=2000,
+                    help="jobs of the serving mix (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -212,6 +286,9 @@ def main():
         workloads["garch11_L2000_n1e6_summaries"] = {
             "sims_per_s": round(gn / wall, 1), "ms": round(wall * 1e3, 3), "kernel_ms": round(kms, 3),
             "valu_frac": round(gops / (kms * 1e-3) / VALU_PEAK_OPS, 4)}
+        if args.serving_jobs > 0:
+            workloads["serving_mix"] = serving_bench(P, torch, W, golden, args.serving_jobs,
+                                                     W.SERVING_MIX["rate_hz"])
 
     cpu = None
     if args.cpu_sample > 0:

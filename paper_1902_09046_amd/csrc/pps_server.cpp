@@ -717,8 +717,13 @@ int pps_release(pps_server *server, uint64_t job_id)
         return fail(PPS_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(server->mu);
     Job *j = server->sched.find(job_id);
-    if (!j)
+    if (!j) {
+        for (const auto &p : server->inbox)
+            if (p->id == job_id)
+                return fail(PPS_EBUSY, "job %llu has not started",
+                            static_cast<unsigned long long>(job_id));
         return fail(PPS_ENOTFOUND, "unknown job %llu", static_cast<unsigned long long>(job_id));
+    }
     if (j->state != JobState::DONE)
         return fail(PPS_EBUSY, "job %llu has not finished", static_cast<unsigned long long>(job_id));
     server->sched.erase(job_id);
