@@ -232,6 +232,9 @@ def main():
     stream = torch.cuda.current_stream()
 
     P.pps_set_timing(True)
+    tune = P.pps_autotune(model, 1 << 21, use_cache=True)
+    print(f"bench: autotuned launch shape {tune['best']} (cache: {tune['from_cache']})",
+          file=sys.stderr, flush=True)
     print(f"bench: warmup {args.warmup} x abc_sample N={n}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         P.abc_sample(model, y_obs, sampling, P.PPS_EPS_FIXED, eps, capacity, idx, th, dd)
@@ -256,7 +259,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "TOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic("k_simulate_path_abc_n1e7"),
-                "kernel": "k_simulate<256,path>", "kernel_ms": round(k_ms, 4),
+                "kernel": "k_simulate<block=%d,path,dpl=%d,unroll=%d>" % tuple(tune["best"]),
+                "kernel_ms": round(k_ms, 4),
                 "ops_per_draw": ops_per_draw(steps_em, n_obs)}
 
     workloads = {}
@@ -309,7 +313,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "abc_logistic_sde_n1e7_S1000_fixed_eps", "n_draws": n,
                    "em_steps": steps_em, "n_obs": n_obs, "eps": eps,
-                   "accepted": stats["n_accepted"]},
+                   "accepted": stats["n_accepted"], "launch_shape": list(tune["best"])},
         "sde_steps_per_s": round(value * steps_em, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,

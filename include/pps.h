@@ -320,6 +320,31 @@ int pps_get_block_size(int model_class);
 int pps_set_launch_shape(int model_class, int block, int draws_per_lane, int unroll);
 int pps_get_launch_shape(int model_class, int *block, int *draws_per_lane, int *unroll);
 
+/* ---- autotuning --------------------------------------------------------- */
+typedef struct {
+    int32_t block, draws_per_lane, unroll;
+    double ms; /* simulation-kernel time of the probe (best of the timed runs) */
+} pps_tune_entry;
+
+typedef struct {
+    int32_t model_class;
+    int32_t n_entries;
+    pps_tune_entry entries[16];
+    int32_t best;       /* index of the chosen shape in entries (or -1) */
+    int32_t from_cache; /* 1 when the choice was read from the cache file */
+} pps_tune_report;
+
+/* Chooses the launch shape of the model's class on the current device: times
+ * every supported shape (pps_set_launch_shape) on a probe of n_draws draws of
+ * `model` (p-value tally, no per-draw output; results never depend on the
+ * shape), keeps the fastest for all later calls, batches and servers created
+ * afterwards, and appends it to the cache file named by the environment
+ * variable PPS_TUNE_CACHE, if set, keyed by (GPU architecture, class, steps
+ * rounded up to a power of two).  With use_cache != 0 and a matching cache
+ * line, the cached shape is applied without timing.  report may be NULL. */
+int pps_autotune(const pps_model *model, uint64_t n_draws, int use_cache, pps_tune_report *report,
+                 void *stream);
+
 /* ---- errors ------------------------------------------------------------- */
 const char *pps_strerror(int status);
 const char *pps_last_error(void); /* thread-local; "" when none */

@@ -20,5 +20,5 @@ from ._pps import (  # noqa: F401
     PPS_JOB_ABC, PPS_JOB_PVALUE, PPS_POLICY_BATCHED, PPS_POLICY_PLAIN,
     pps_job, pps_job_result, pps_server_config, pps_server_stats,
     make_abc_job, make_pvalue_job, make_server_config, pps_job_arena_bytes, pps_run_batch,
-    Server, records,
+    Server, records, pps_autotune,
 )

@@ -123,6 +123,17 @@ class pps_server_stats(ctypes.Structure):
     ]
 
 
+class pps_tune_entry(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("draws_per_lane", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
+class pps_tune_report(ctypes.Structure):
+    _fields_ = [("model_class", ctypes.c_int32), ("n_entries", ctypes.c_int32),
+                ("entries", pps_tune_entry * 16), ("best", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -170,6 +181,8 @@ def lib():
         L.pps_release.argtypes = [vp, u64]
         L.pps_server_stats_get.argtypes = [vp, ctypes.POINTER(pps_server_stats)]
         L.pps_server_destroy.argtypes = [vp]
+        L.pps_autotune.argtypes = [mp, u64, ctypes.c_int, ctypes.POINTER(pps_tune_report), vp]
+        L.pps_autotune.restype = ctypes.c_int
         for name in ("pps_philox", "pps_normals", "pps_simulate", "pps_n_summaries", "abc_sample",
                      "prior_pred_pvalue", "pps_summary_tally", "pps_run_batch", "pps_server_create",
                      "pps_submit", "pps_poll", "pps_release", "pps_server_stats_get",
@@ -261,6 +274,17 @@ def pps_get_launch_shape(model_class: int) -> tuple[int, int, int]:
 
 PATH_SHAPES = [(b, d, u) for b in (64, 128, 256) for d in (1, 2) for u in (1, 2)]
 GARCH_SHAPES = [(b, 1, 1) for b in (64, 128, 256)]
+
+
+def pps_autotune(model, n_draws: int, use_cache: bool = True, stream=None) -> dict:
+    """Times the launch shapes of the model's class and keeps the fastest."""
+    r = pps_tune_report()
+    _check(lib().pps_autotune(ctypes.byref(_model_arg(model)), n_draws, 1 if use_cache else 0,
+                              ctypes.byref(r), _stream(stream)))
+    entries = [(e.block, e.draws_per_lane, e.unroll, e.ms) for e in r.entries[: r.n_entries]]
+    best = entries[r.best][:3] if r.best >= 0 else None
+    return {"model_class": r.model_class, "entries": entries, "best": best,
+            "from_cache": bool(r.from_cache)}
 
 
 def pps_n_summaries(model) -> int:

@@ -304,6 +304,31 @@ def test_launch_shape_invariance(P, torch):
         P.pps_set_launch_shape(1, *keep)
 
 
+def test_autotune_and_cache(P, torch, tmp_path, monkeypatch):
+    """The autotuner times every supported shape, applies the fastest, and a
+    cache hit applies the recorded shape without timing."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PPS_TUNE_CACHE", str(cache))
+    keep = P.pps_get_launch_shape(0)
+    try:
+        spec = W.logistic_spec(steps=200)
+        rep = P.pps_autotune(spec, 1 << 18, use_cache=True)
+        assert not rep["from_cache"] and len(rep["entries"]) == len(P.PATH_SHAPES)
+        assert all(e[3] > 0 for e in rep["entries"])
+        assert rep["best"] in [tuple(s) for s in P.PATH_SHAPES]
+        assert P.pps_get_launch_shape(0) == rep["best"]
+        line = cache.read_text().split()
+        assert line[1] == "0" and line[2] == "256"  # class 0, steps bucket 256
+        P.pps_set_launch_shape(0, 64, 2, 2)
+        rep2 = P.pps_autotune(spec, 1 << 18, use_cache=True)
+        assert rep2["from_cache"] and rep2["best"] == rep["best"]
+        assert P.pps_get_launch_shape(0) == rep["best"]
+        g = P.pps_autotune(W.garch_spec(series_len=200), 1 << 15, use_cache=False)
+        assert len(g["entries"]) == len(P.GARCH_SHAPES)
+    finally:
+        P.pps_set_launch_shape(0, *keep)
+
+
 def test_invalid_arguments_raise(P, torch):
     spec = W.logistic_spec(steps=999)
     with pytest.raises(P.PPSError):
