@@ -34,13 +34,13 @@ CUS, LANES_PER_CU, CLOCK = 256, 128, 2.4e9
 VALU_PEAK_OPS = CUS * LANES_PER_CU * CLOCK  # 7.86e13 lane-ops/s
 
 # Algorithmic VALU lane-operations of the logistic path (see the design notes):
-#   Philox4x32-10 call: 10 rounds x (2 mul_hi + 2 mul_lo + 4 xor) = 80
+#   Philox4x32-10 call: 10 rounds x (2 widening 32x32->64 multiplies + 4 xor) = 60
 #   Box-Muller pair: 2 x (shift, convert, fma) + log2, scale, sqrt, cos, sin,
 #                    2 multiplies = 12   -> 24 per call (4 normals)
 #   Euler-Maruyama step: 3 fma + max = 4
 #   observation: difference, Kahan (4) for rho^2, Kahan (4) for the sum = 9
 #   prior draw: 3 Philox calls + 3 uniform transforms ~ 250 per draw
-OPS_PHILOX = 80
+OPS_PHILOX = 60
 OPS_BM_PAIR = 12
 OPS_EM = 4
 OPS_OBS = 9
@@ -52,10 +52,10 @@ def ops_per_draw(steps: int, n_obs: int) -> float:
     return steps * per_step + n_obs * OPS_OBS + OPS_PRIOR
 
 
-# GARCH(1,1) step: the shared normal (26) + sqrt, 2 multiplies, 2 fma for the
-# variance, 4 moment sums, b_t, 10 lag products = 46, plus 14 Kahan folds
+# GARCH(1,1) step: the normal (21) + sqrt, 2 multiplies, 2 fma for the
+# variance, 4 moment sums, b_t, 10 lag products = 41, plus 14 Kahan folds
 # (4 ops) every 20 steps = 2.8; closing algebra and prior ~ 600 per draw.
-GARCH_OPS_PER_STEP = 48.8
+GARCH_OPS_PER_STEP = 43.8
 GARCH_OPS_PER_DRAW_FIXED = 600
 
 
