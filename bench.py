@@ -52,6 +52,19 @@ def ops_per_draw(steps: int, n_obs: int) -> float:
     return steps * per_step + n_obs * OPS_OBS + OPS_PRIOR
 
 
+# A lambda group (p-value grids): 8 lambda values of one draw per lane share
+# the normal; each member adds its EM update, its Kahan mean (4 per
+# observation) and its lambda'd prior value (one Philox call + FP64 transform).
+GROUP_LPL = 8
+OPS_PRIOR_MEMBER = 160
+
+
+def ops_per_group_draw(steps: int, n_obs: int) -> float:
+    per_step = (OPS_PHILOX + 2 * OPS_BM_PAIR) / 4.0 + GROUP_LPL * OPS_EM
+    return (steps * per_step + n_obs * GROUP_LPL * 4 + OPS_PRIOR
+            + (GROUP_LPL - 1) * OPS_PRIOR_MEMBER)
+
+
 # GARCH(1,1) step: the normal (21) + sqrt, 2 multiplies, 2 fma for the
 # variance, 4 moment sums, b_t, 10 lag products = 41, plus 14 Kahan folds
 # (4 ops) every 20 steps = 2.8; closing algebra and prior ~ 600 per draw.
@@ -273,7 +286,7 @@ def main():
         print("bench: p-value batch 64 x 1e6", file=sys.stderr, flush=True)
         wall, kms = time_calls(P, torch, lambda: P.prior_pred_pvalue(
             pspec, 0, P.PPS_LOGNORMAL, lam, P.make_sampling(pn, 0, W.SAMPLING_SEED), t_obs), 1, 3)
-        pops = ops_per_draw(steps_em, n_obs) * pn * 64
+        pops = ops_per_group_draw(steps_em, n_obs) * pn * (64 // GROUP_LPL)
         workloads["pvalue_logistic_64lambda_n1e6"] = {
             "sims_per_s": round(64 * pn / wall, 1), "ms_per_batch": round(wall * 1e3, 3),
             "kernel_ms": round(kms, 3), "valu_frac": round(pops / (kms * 1e-3) / VALU_PEAK_OPS, 4)}

@@ -178,7 +178,9 @@ int abc_sample(const pps_model *model, const double *y_obs, const pps_sampling *
  * priors are unchanged.  Every lambda_k uses the same draws and random
  * numbers (common random numbers).  count_ge[k] = #{i : T_i >= t_obs} with
  * T_i the mean of draw i's observations (compared in FP64) and
- * pvalue[k] = count_ge[k] / N.  All lambda values run in one launch.
+ * pvalue[k] = count_ge[k] / N.  All lambda values run in one launch; for the
+ * logistic SDE, lambda values are simulated in groups of 8 per lane from one
+ * random stream (the common random numbers make their normals identical).
  * lambda, count_ge, pvalue: host arrays of n_lambda (1..4096).
  * Not for GARCH (use pps_summary_tally). */
 int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_family,
@@ -312,11 +314,14 @@ double pps_last_kernel_ms(void);
 int pps_set_block_size(int model_class, int block);
 int pps_get_block_size(int model_class);
 
-/* Full launch shape of a model class: workgroup size, draws simulated
+/* Full launch shape of a kernel class: workgroup size, draws simulated
  * interleaved per lane (1 or 2) and Philox blocks generated per loop trip
- * (1 or 2; logistic SDE).  Supported shapes: class 0 block {64, 128, 256} x
- * draws_per_lane {1, 2} x unroll {1, 2}; class 1 block {64, 128, 256} with
- * (1, 1).  Results do not depend on the shape.  PPS_EINVAL otherwise. */
+ * (1 or 2; logistic SDE).  Classes: 0 logistic SDE / normal-mean, 1 GARCH,
+ * 2 lambda groups of a p-value grid (8 lambda values of one draw per lane,
+ * sharing its random numbers).  Supported shapes: class 0 block
+ * {64, 128, 256} x draws_per_lane {1, 2} x unroll {1, 2}; classes 1 and 2
+ * block {64, 128, 256} with (1, 1).  Results do not depend on the shape.
+ * PPS_EINVAL otherwise. */
 int pps_set_launch_shape(int model_class, int block, int draws_per_lane, int unroll);
 int pps_get_launch_shape(int model_class, int *block, int *draws_per_lane, int *unroll);
 

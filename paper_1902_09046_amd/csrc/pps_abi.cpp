@@ -68,7 +68,7 @@ double pps_last_kernel_ms(void)
 int pps_set_block_size(int model_class, int block)
 {
     clear_error();
-    if (model_class != CLASS_PATH && model_class != CLASS_GARCH)
+    if (model_class < 0 || model_class >= N_CLASSES)
         return fail(PPS_EINVAL, "unknown model class %d", model_class);
     int rc;
     Context *c = current_context(&rc);
@@ -86,7 +86,7 @@ int pps_set_block_size(int model_class, int block)
 int pps_get_block_size(int model_class)
 {
     clear_error();
-    if (model_class != CLASS_PATH && model_class != CLASS_GARCH)
+    if (model_class < 0 || model_class >= N_CLASSES)
         return fail(PPS_EINVAL, "unknown model class %d", model_class);
     int rc;
     Context *c = current_context(&rc);
@@ -99,7 +99,7 @@ int pps_get_block_size(int model_class)
 int pps_set_launch_shape(int model_class, int block, int draws_per_lane, int unroll)
 {
     clear_error();
-    if (model_class != CLASS_PATH && model_class != CLASS_GARCH)
+    if (model_class < 0 || model_class >= N_CLASSES)
         return fail(PPS_EINVAL, "unknown model class %d", model_class);
     SimShape sh;
     sh.block = block;
@@ -120,7 +120,7 @@ int pps_set_launch_shape(int model_class, int block, int draws_per_lane, int unr
 int pps_get_launch_shape(int model_class, int *block, int *draws_per_lane, int *unroll)
 {
     clear_error();
-    if (model_class != CLASS_PATH && model_class != CLASS_GARCH)
+    if (model_class < 0 || model_class >= N_CLASSES)
         return fail(PPS_EINVAL, "unknown model class %d", model_class);
     int rc;
     Context *c = current_context(&rc);
@@ -294,22 +294,30 @@ int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_famil
         return rc;
     std::lock_guard<std::mutex> lk(c->mu);
     PPS_TRY_HIP(c->counts.ensure(n_lambda * sizeof(unsigned long long)), "tally buffer");
+    // Logistic grids run in groups of GROUP_LPL lambda values sharing each
+    // draw's random numbers; the rest (and other models) one row per lambda.
+    const int grouped = model->model == PPS_LOGISTIC_SDE ? (n_lambda / GROUP_LPL) * GROUP_LPL : 0;
     EpochPlan plan;
+    std::vector<std::pair<int, size_t>> where(n_lambda);  // (class, row index)
     for (int k = 0; k < n_lambda; ++k) {
+        const int cls = k < grouped ? CLASS_GROUP : CLASS_PATH;
         JobDev J;
         fill_job(J, &mk[k], sampling, ns, JOB_TALLY_STAT);
         J.t_obs = t_obs;
         J.counts = c->counts.as<unsigned long long>() + k;
         J.n_counts = 1;
         J.row_flags = ROW_ZERO_COUNTS | ROW_COPY_COUNTS;
-        whole_job(*c->engine, CLASS_PATH, J);
-        plan.rows[CLASS_PATH].push_back(J);
+        J.lambda_param = lambda_param;
+        whole_job(*c->engine, cls, J);
+        where[k] = {cls, plan.rows[cls].size()};
+        plan.rows[cls].push_back(J);
     }
     PPS_TRY(run_sync(*c, plan, as_stream(stream)));
     const unsigned long long *cnt = c->engine->out_counts(0);
     for (int k = 0; k < n_lambda; ++k) {
-        count_ge[k] = cnt[k];
-        pvalue[k] = static_cast<double>(cnt[k]) / static_cast<double>(sampling->n_draws);
+        const JobDev &R = plan.rows[where[k].first][where[k].second];
+        count_ge[k] = cnt[R.out_slot];
+        pvalue[k] = static_cast<double>(count_ge[k]) / static_cast<double>(sampling->n_draws);
     }
     return PPS_OK;
 }

@@ -172,10 +172,15 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
         H.class_rows[c] = static_cast<uint32_t>(plan.rows[c].size());
         uint64_t tiles = 0;
         const uint64_t ts = tile_size(c);
-        for (JobDev &row : plan.rows[c]) {
+        if (c == CLASS_GROUP && plan.rows[c].size() % GROUP_LPL != 0)
+            return fail(PPS_EINVAL, "lambda-group rows must come in groups of %d", GROUP_LPL);
+        for (size_t i = 0; i < plan.rows[c].size(); ++i) {
+            JobDev &row = plan.rows[c][i];
             row.tile_size = static_cast<int32_t>(ts);
             row.tile_begin = tiles;
-            tiles += row.n_tiles;
+            // the members of a lambda group share the group's tiles
+            if (c != CLASS_GROUP || i % GROUP_LPL == GROUP_LPL - 1)
+                tiles += row.n_tiles;
             if (row.row_flags & ROW_COPY_COUNTS) {
                 if (out_slot + row.n_counts > static_cast<uint32_t>(MAX_OUT_COUNTS))
                     return fail(PPS_EINVAL, "epoch has too many tallies");

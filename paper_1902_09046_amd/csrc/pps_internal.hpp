@@ -17,8 +17,13 @@ enum : int32_t {
     JOB_DUMP = 1 << 3,        // write theta / summaries / stat / dist per draw
 };
 
-// Model classes compiled into separate simulation kernels.
-enum : int { CLASS_PATH = 0, CLASS_GARCH = 1, N_CLASSES = 2 };
+// Model classes compiled into separate simulation kernels.  CLASS_GROUP
+// holds p-value rows of one lambda grid in groups of GROUP_LPL consecutive
+// rows that differ only in the prior of parameter `lambda_param`: one lane
+// simulates a draw under every lambda of its group from one random stream
+// (common random numbers).
+enum : int { CLASS_PATH = 0, CLASS_GARCH = 1, CLASS_GROUP = 2, N_CLASSES = 3 };
+constexpr int GROUP_LPL = 8;
 
 // Row flags handled by the epoch stage-in / stage-out kernels.
 enum : uint32_t {
@@ -67,7 +72,7 @@ struct alignas(16) JobDev {
     uint32_t row_flags;          // ROW_* above
     uint32_t n_counts;           // tallies of this row (1, or 14 for GARCH)
     uint32_t out_slot;           // ROW_COPY_COUNTS: first host slot
-    uint32_t pad2;
+    int32_t lambda_param;        // CLASS_GROUP: the parameter whose prior varies
 };
 
 // Device-side launch state of one simulation class (reset by the stage-in

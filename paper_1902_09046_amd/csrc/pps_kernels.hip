@@ -429,6 +429,121 @@ __global__ __launch_bounds__(BLOCK) void k_simulate(const EpochHeader *__restric
 }
 
 // ===========================================================================
+// Lambda-group kernel (p-value grids, logistic SDE).  One lane simulates draw
+// i under the LPL lambda values of its group: the path normals and every
+// prior parameter except `lambda_param` are shared (common random numbers),
+// each member keeps its own state, EM constants and compensated mean, and
+// tallies its own statistic.  The member arithmetic is the same sequence of
+// operations as in k_simulate, so counts equal those of one row per lambda.
+// ===========================================================================
+template <int BLOCK, int LPL>
+__global__ __launch_bounds__(BLOCK) void k_simulate_group(const EpochHeader *__restrict__ hdr,
+                                                          const JobDev *__restrict__ rows,
+                                                          LaunchState *__restrict__ states)
+{
+    constexpr int NW = BLOCK / 64;
+    __shared__ unsigned long long s_tile;
+    __shared__ unsigned s_cnt[LPL][NW];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int n_groups = static_cast<int>(hdr->class_rows[CLASS_GROUP] / LPL);
+    const uint64_t total_tiles = hdr->class_tiles[CLASS_GROUP];
+    const JobDev *__restrict__ grp = rows + hdr->class_first[CLASS_GROUP];
+    LaunchState *__restrict__ state = states + CLASS_GROUP;
+    for (;;) {
+        if (tid == 0)
+            s_tile = atomicAdd(&state->next_tile, 1ull);
+        __syncthreads();
+        const uint64_t t = uniform_u64(s_tile);
+        __syncthreads();
+        if (t >= total_tiles)
+            break;
+        int lo = 0, hi = n_groups - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (grp[mid * LPL].tile_begin <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const JobDev *__restrict__ J = grp + lo * LPL;
+        const uint64_t n = J->n_draws;
+        const uint64_t q0 = (t - J->tile_begin + J->tile_offset) * static_cast<uint64_t>(J->tile_size);
+        const uint64_t q = q0 + static_cast<uint64_t>(tid);
+        const bool valid = q < n;
+        const bool wave_live = q0 + static_cast<uint64_t>(wave) * 64 < n;
+        const uint64_t draw = J->first_draw + q;
+        const StreamKey key = make_key(J->seed);
+        Kahan sum[LPL];
+        if (wave_live) {
+            double theta[PPS_MAX_PARAMS] = {0.0, 0.0, 0.0, 0.0};
+            prior_draw(J->prior, J->n_params, J->constraint, key, draw, theta);
+            const int lp = J->lambda_param;
+            const double dt = J->dt;
+            float a[LPL], b[LPL], c[LPL], x[LPL];
+            const double sdt = sqrt(dt);
+#pragma unroll
+            for (int k = 0; k < LPL; ++k) {
+                double th[3] = {theta[0], theta[1], theta[2]};
+                if (k > 0) {
+                    const double v = prior_value(J[k].prior[lp], key, draw, lp, 0);
+                    th[0] = lp == 0 ? v : th[0];
+                    th[1] = lp == 1 ? v : th[1];
+                    th[2] = lp == 2 ? v : th[2];
+                }
+                a[k] = static_cast<float>(th[0] * dt);
+                b[k] = static_cast<float>(th[0] * dt / th[1]);
+                c[k] = static_cast<float>(th[2] * sdt);
+                x[k] = static_cast<float>(J->x0);
+            }
+            const int steps = J->steps;
+            const int stride = J->obs_stride;
+            const int nblk = (steps + 3) >> 2;
+            int next_obs = stride;
+            for (int blk = 0; blk < nblk; ++blk) {
+                float z[4];
+                path_normals4(key, draw, static_cast<uint32_t>(blk), z[0], z[1], z[2], z[3]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int step = 4 * blk + j + 1;
+                    if (step > steps)
+                        break;
+#pragma unroll
+                    for (int k = 0; k < LPL; ++k) {
+                        float g = __builtin_fmaf(-b[k], x[k], a[k]);
+                        g = __builtin_fmaf(c[k], z[j], g);
+                        x[k] = __builtin_fmaxf(__builtin_fmaf(x[k], g, x[k]), 0.0f);
+                    }
+                    if (step == next_obs) {
+#pragma unroll
+                        for (int k = 0; k < LPL; ++k)
+                            sum[k].add(x[k]);
+                        next_obs += stride;
+                    }
+                }
+            }
+        }
+        const double inv = 1.0 / static_cast<double>(J->n_summ);
+#pragma unroll
+        for (int k = 0; k < LPL; ++k) {
+            const bool hit = valid && sum[k].value() * inv >= J[k].t_obs;
+            const uint64_t m = __ballot(hit);
+            if (lane_id() == 0)
+                s_cnt[k][wave] = static_cast<unsigned>(__popcll(m));
+        }
+        __syncthreads();
+        if (tid < LPL) {
+            unsigned tot = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                tot += s_cnt[tid][w];
+            if (tot)
+                atomicAdd(&J[tid].counts[0], static_cast<unsigned long long>(tot));
+        }
+    }
+}
+
+// ===========================================================================
 // Epoch staging: tables in, results out (mapped pinned host memory).
 // ===========================================================================
 __global__ void k_stage_in(const EpochHeader *__restrict__ h_hdr, const JobDev *__restrict__ h_rows,
@@ -998,6 +1113,16 @@ static SimKernel sim_kernel(int cls, const SimShape &sh)
         case 64: return sim_ptr<64, CLASS_GARCH, 1, 1>();
         case 128: return sim_ptr<128, CLASS_GARCH, 1, 1>();
         case 256: return sim_ptr<256, CLASS_GARCH, 1, 1>();
+        default: return nullptr;
+        }
+    }
+    if (cls == CLASS_GROUP) {
+        if (sh.dpl != 1 || sh.unroll != 1)
+            return nullptr;
+        switch (sh.block) {
+        case 64: return k_simulate_group<64, GROUP_LPL>;
+        case 128: return k_simulate_group<128, GROUP_LPL>;
+        case 256: return k_simulate_group<256, GROUP_LPL>;
         default: return nullptr;
         }
     }

@@ -199,6 +199,25 @@ def test_pvalue_lambda_grid_parity(P, torch):
     assert diff.max() <= max(3, int(2e-3 * n))
 
 
+@pytest.mark.parametrize("lp,family,lams", [
+    (0, "lognormal", list(W.lambda_grid(13))),
+    (1, "uniform", [60.0 + 7.0 * k for k in range(9)]),        # th2 ~ U(50, lambda)
+    (2, "uniform", [0.05 + 0.03 * k for k in range(16)]),      # th3 ~ U(0, lambda)
+])
+def test_pvalue_lambda_groups_equal_single_rows(P, torch, lp, family, lams):
+    """Grids run in groups of 8 lambda values per lane (shared random numbers);
+    every count equals the one-lambda-per-row result, remainder rows included."""
+    spec = W.pvalue_spec(steps=400)
+    fam = {"lognormal": P.PPS_LOGNORMAL, "uniform": P.PPS_UNIFORM}[family]
+    t_obs = observed()["logistic_S1000"]["t_obs"]
+    s = P.make_sampling(5003, 17, 4)
+    counts, _ = P.prior_pred_pvalue(spec, lp, fam, lams, s, t_obs)
+    single = [int(P.prior_pred_pvalue(spec, lp, fam, [l], s, t_obs)[0][0]) for l in lams]
+    np.testing.assert_array_equal(counts.astype(np.int64), np.array(single))
+    ref = oracle.pvalue(spec, lp, family, lams, 4, 17, 5003, t_obs)
+    assert np.abs(counts.astype(np.int64) - ref["count_ge"].astype(np.int64)).max() <= 3
+
+
 def test_conjugate_normal_pvalue_gpu(P, torch):
     spec = W.normal_mean_spec(n_obs=20, noise_sd=1.0)
     n, t_obs = 200000, 0.4
