@@ -207,12 +207,15 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
     hipError_t e = hipGraphLaunch(s.exec[EPOCH_STAGE_IN], stream);
     if (e == hipSuccess)
         e = hipEventRecord(s.sim_start, stream);
-    if (e == hipSuccess)
-        e = hipGraphLaunch(s.exec[EPOCH_SIMULATE], stream);
+    for (int c = 0; c < N_CLASSES && e == hipSuccess; ++c)
+        if (H.class_tiles[c] > 0)
+            e = hipGraphLaunch(s.exec[EPOCH_SIMULATE + c], stream);
     if (e == hipSuccess)
         e = hipEventRecord(s.sim_stop, stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess && H.n_fins > 0)
         e = hipGraphLaunch(s.exec[EPOCH_FINALIZE], stream);
+    if (e == hipSuccess)
+        e = hipGraphLaunch(s.exec[EPOCH_STAGE_OUT], stream);
     if (e != hipSuccess)
         return fail_hip(e, "epoch graph launch");
     e = hipEventRecord(s.done, stream);

@@ -74,7 +74,7 @@ class EpochEngine {
         FinResult *h_out_fin = nullptr;
         unsigned long long *h_out_counts = nullptr;
         EpochDevPtrs dev;
-        hipGraphExec_t exec[EPOCH_PARTS] = {nullptr, nullptr, nullptr};
+        hipGraphExec_t exec[EPOCH_PARTS] = {};
         bool have_exec = false;
         EpochShape exec_shape;
         hipEvent_t sim_start = nullptr, sim_stop = nullptr, done = nullptr;

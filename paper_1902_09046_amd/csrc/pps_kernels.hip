@@ -1158,18 +1158,19 @@ hipError_t issue_epoch_part(int part, const EpochDevPtrs &p, const EpochShape &s
                            p.h_fins, p.d_hdr, p.d_rows, p.d_fins, p.states);
         return hipGetLastError();
     }
-    if (part == EPOCH_SIMULATE) {
-        for (int c = 0; c < N_CLASSES; ++c) {
-            SimKernel k = sim_kernel(c, shape.sim[c]);
-            if (!k)
-                return hipErrorInvalidValue;
-            hipLaunchKernelGGL(k, dim3(shape.sim_grid[c]), dim3(shape.sim[c].block), 0, s, p.d_hdr,
-                               p.d_rows, p.states);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess)
-                return e;
-        }
-        return hipSuccess;
+    if (part >= EPOCH_SIMULATE && part < EPOCH_SIMULATE + N_CLASSES) {
+        const int c = part - EPOCH_SIMULATE;
+        SimKernel k = sim_kernel(c, shape.sim[c]);
+        if (!k)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k, dim3(shape.sim_grid[c]), dim3(shape.sim[c].block), 0, s, p.d_hdr,
+                           p.d_rows, p.states);
+        return hipGetLastError();
+    }
+    if (part == EPOCH_STAGE_OUT) {
+        hipLaunchKernelGGL(k_stage_out, dim3(STAGE_GRID), dim3(256), 0, s, p.d_hdr, p.d_rows,
+                           p.d_fins, p.h_out_fin, p.h_out_counts);
+        return hipGetLastError();
     }
     const dim3 fb(FIN_BLOCK);
     hipLaunchKernelGGL(k_fin_init, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
@@ -1181,8 +1182,6 @@ hipError_t issue_epoch_part(int part, const EpochDevPtrs &p, const EpochShape &s
     hipLaunchKernelGGL(k_compact_scan, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
     hipLaunchKernelGGL(k_compact_write, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins);
     hipLaunchKernelGGL(k_moments_final, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
-    hipLaunchKernelGGL(k_stage_out, dim3(STAGE_GRID), dim3(256), 0, s, p.d_hdr, p.d_rows, p.d_fins,
-                       p.h_out_fin, p.h_out_counts);
     return hipGetLastError();
 }
 

@@ -55,12 +55,18 @@ struct EpochDevPtrs {
 bool sim_shape_supported(int cls, const SimShape &sh);
 hipError_t sim_occupancy(int cls, const SimShape &sh, int *blocks_per_cu);
 
-// An epoch is three parts issued in order on one stream: stage-in; the
-// simulation kernel of every class; the ABC finalisation kernels and
-// stage-out.  Every launch shape is fixed by `shape`, so each part is captured
-// once into a graph and replayed with new table contents; timing events are
-// recorded between the parts.
-enum { EPOCH_STAGE_IN = 0, EPOCH_SIMULATE = 1, EPOCH_FINALIZE = 2, EPOCH_PARTS = 3 };
+// An epoch is issued as parts, in order, on one stream: stage-in; the
+// simulation kernel of each class that has tiles; the ABC finalisation kernels
+// (when the epoch finishes ABC jobs); stage-out.  Every launch shape is fixed
+// by `shape`, so each part is captured once into a graph and replayed with new
+// table contents; timing events bracket the simulation parts.
+enum {
+    EPOCH_STAGE_IN = 0,
+    EPOCH_SIMULATE = 1,  // + class
+    EPOCH_FINALIZE = EPOCH_SIMULATE + N_CLASSES,
+    EPOCH_STAGE_OUT,
+    EPOCH_PARTS
+};
 hipError_t issue_epoch_part(int part, const EpochDevPtrs &p, const EpochShape &shape, hipStream_t s);
 
 hipError_t launch_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t block,
