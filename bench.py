@@ -192,6 +192,9 @@ def parse():
                     help="skip the p-value batch, GARCH and serving workloads")
     ap.add_argument("--serving-jobs", type=int, default=2000,
                     help="jobs of the serving mix (0 skips it)")
+    ap.add_argument("--launch-shape", default="",
+                    help="block,draws_per_lane,unroll of the simulation kernel instead of autotuning "
+                         "(profiling runs pin the shape so that every run times the same kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -245,9 +248,15 @@ def main():
     stream = torch.cuda.current_stream()
 
     P.pps_set_timing(True)
-    tune = P.pps_autotune(model, 1 << 21, use_cache=True)
-    print(f"bench: autotuned launch shape {tune['best']} (cache: {tune['from_cache']})",
-          file=sys.stderr, flush=True)
+    if args.launch_shape:
+        shape = tuple(int(v) for v in args.launch_shape.split(","))
+        P.pps_set_launch_shape(0, *shape)
+        tune = {"best": shape, "from_cache": False}
+        print(f"bench: launch shape {shape} (given)", file=sys.stderr, flush=True)
+    else:
+        tune = P.pps_autotune(model, 1 << 21, use_cache=True)
+        print(f"bench: autotuned launch shape {tune['best']} (cache: {tune['from_cache']})",
+              file=sys.stderr, flush=True)
     print(f"bench: warmup {args.warmup} x abc_sample N={n}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         P.abc_sample(model, y_obs, sampling, P.PPS_EPS_FIXED, eps, capacity, idx, th, dd)
