@@ -298,7 +298,9 @@ def main():
         pops = ops_per_group_draw(steps_em, n_obs) * pn * (64 // GROUP_LPL)
         workloads["pvalue_logistic_64lambda_n1e6"] = {
             "sims_per_s": round(64 * pn / wall, 1), "ms_per_batch": round(wall * 1e3, 3),
-            "kernel_ms": round(kms, 3), "valu_frac": round(pops / (kms * 1e-3) / VALU_PEAK_OPS, 4)}
+            "kernel_ms": round(kms, 3), "valu_frac": round(pops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
+            "kernel": "k_simulate_group<256,8>",
+            "traffic": measured_traffic("k_simulate_group_pvalue_64x1e6")}
         # GARCH(1,1) prior-predictive check: 1e6 series of length 2000,
         # 14 summaries per draw written out, then tail-area tallies.
         gspec = W.garch_spec(series_len=2000)
@@ -311,7 +313,9 @@ def main():
         gops = (GARCH_OPS_PER_STEP * 2000 + GARCH_OPS_PER_DRAW_FIXED) * gn
         workloads["garch11_L2000_n1e6_summaries"] = {
             "sims_per_s": round(gn / wall, 1), "ms": round(wall * 1e3, 3), "kernel_ms": round(kms, 3),
-            "valu_frac": round(gops / (kms * 1e-3) / VALU_PEAK_OPS, 4)}
+            "valu_frac": round(gops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
+            "kernel": "k_simulate<256,garch>",
+            "traffic": measured_traffic("k_simulate_garch_L2000_n1e6")}
         if args.serving_jobs > 0:
             workloads["serving_mix"] = serving_bench(P, torch, W, golden, args.serving_jobs,
                                                      W.SERVING_MIX["rate_hz"])
