@@ -108,31 +108,40 @@ __device__ __forceinline__ void sim_normal_mean(const JobDev *__restrict__ J, St
     }
 }
 
-// GARCH(1,1) in scaled form: with sbar^2 = omega/(1-alpha-beta) and
-// s_t = r_t / sbar, h_t = sigma2_t / sbar^2:
-//   h_1 = 1,  s_t = sqrt(h_t) z_t,  h_{t+1} = (1-alpha-beta) + alpha s_t^2 + beta h_t.
+// GARCH(1,1) in scaled deviation form.  With sbar^2 = omega/(1-alpha-beta),
+// s_t = r_t / sbar and h_t = sigma2_t / sbar^2 = 1 + g_t, the recursion
+// sigma2_{t+1} = omega + alpha r_t^2 + beta sigma2_t becomes
+//   g_1 = 0,  s_t = sqrt(1 + g_t) z_t,  g_{t+1} = alpha (s_t^2 - 1) + beta g_t,
+// exactly; the stationary level of g is 0 whatever the FP32 rounding of alpha
+// and beta (the level of 1-alpha-beta+alpha s^2+beta h in FP32 would drift by
+// ~1e-7/(1-alpha-beta) for near-integrated draws).
 // Streaming summaries: plain FP32 sums over 20-step blocks folded into Kahan
 // totals; b_t = s_t^2 - 1 kept in a 10-deep register ring for the lag
-// products; the first and last 10 b_t give the ACF centring terms.  The
-// closing algebra is FP64.  Requires the length to be a multiple of 20.
+// products; the first 10 b_t are recomputed from the stream at the end for
+// the ACF centring terms.  The closing algebra is FP64.  Requires the length
+// to be a multiple of 20.
+__device__ __forceinline__ float garch_step(float &g, float z, float al, float be)
+{
+    const float s = __builtin_amdgcn_sqrtf(1.0f + g) * z;
+    const float bt = s * s - 1.0f;
+    g = __builtin_fmaf(al, bt, be * g);
+    return s;
+}
+
 __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKey key,
                                           uint64_t draw, const double *theta, double *summ)
 {
     const double alpha_d = theta[1], beta_d = theta[2];
     const double oab = 1.0 - alpha_d - beta_d;
-    const float om = static_cast<float>(oab);
     const float al = static_cast<float>(alpha_d);
     const float be = static_cast<float>(beta_d);
     const int len = J->steps;
-    float h = 1.0f;
+    float g = 0.0f;
     Kahan K1, K2, K3, K4, KL[PPS_GARCH_LAGS];
     float ring[PPS_GARCH_LAGS];
-    float head[PPS_GARCH_LAGS];
 #pragma unroll
-    for (int k = 0; k < PPS_GARCH_LAGS; ++k) {
+    for (int k = 0; k < PPS_GARCH_LAGS; ++k)
         ring[k] = 0.0f;
-        head[k] = 0.0f;
-    }
     const int nblk20 = len / 20;
     for (int blk = 0; blk < nblk20; ++blk) {
         float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, s4 = 0.0f;
@@ -147,9 +156,8 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int jj = 4 * p + j;  // position in the 20-step block
-                const float s = __builtin_amdgcn_sqrtf(h) * z[j];
+                const float s = garch_step(g, z[j], al, be);
                 const float sq = s * s;
-                h = __builtin_fmaf(al, sq, __builtin_fmaf(be, h, om));
                 s1 += s;
                 s2 += sq;
                 s3 = __builtin_fmaf(sq, s, s3);
@@ -159,8 +167,6 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
                 for (int k = 1; k <= PPS_GARCH_LAGS; ++k)
                     lag[k - 1] = __builtin_fmaf(bt, ring[(jj - k + 20) % 10], lag[k - 1]);
                 ring[jj % 10] = bt;
-                if (jj < 10 && blk == 0)
-                    head[jj] = bt;
             }
         }
         K1.add(s1);
@@ -170,6 +176,23 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
 #pragma unroll
         for (int k = 0; k < PPS_GARCH_LAGS; ++k)
             KL[k].add(lag[k]);
+    }
+    // The first 10 b_t again (same operations, so the same values).
+    float head[PPS_GARCH_LAGS];
+    {
+        float g0 = 0.0f;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            float z[4];
+            path_normals4(key, draw, static_cast<uint32_t>(p), z[0], z[1], z[2], z[3]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (4 * p + j < PPS_GARCH_LAGS) {
+                    const float s = garch_step(g0, z[j], al, be);
+                    head[4 * p + j] = s * s - 1.0f;
+                }
+            }
+        }
     }
     // Closing algebra in FP64.
     const double T = static_cast<double>(len);
