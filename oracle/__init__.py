@@ -19,7 +19,11 @@ Each function follows one passage of the paper:
   it): accept rho <= eps, or the closest fraction with eps chosen a posteriori.
 * ``pvalue`` -- the prior-predictive p-value under each lambda of a
   hyperparameter grid (Eqs. pppv, pppvhype), using a tail-area statistic.
-* ``summary_tally`` -- per-summary tail areas (the GARCH check).
+* ``summary_tally`` -- per-summary tail areas (the GARCH and toggle-switch
+  checks).
+* ``toggle_cells`` -- every cell of one draw of the genetic toggle switch
+  (Sec. 3.2, Eqs. gene_uv_SDE, gene_uv_SDE_EM and gene_u_obs), for checks of
+  its dynamics, measurement model and quantile summaries.
 """
 from __future__ import annotations
 
@@ -35,12 +39,14 @@ _SRC = os.path.join(_HERE, "pps_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 UNIFORM, NORMAL, LOGNORMAL, POINT = 0, 1, 2, 3
-LOGISTIC, GARCH11, NORMAL_MEAN = 0, 1, 2
+LOGISTIC, GARCH11, NORMAL_MEAN, TOGGLE_SWITCH = 0, 1, 2, 3
+MAX_PARAMS = 8
 EPS_FIXED, EPS_TOP_FRACTION = 0, 1
 GARCH_NSUMM = 14
 
 _FAMILY = {"uniform": UNIFORM, "normal": NORMAL, "lognormal": LOGNORMAL, "point": POINT}
-_MODEL = {"logistic": LOGISTIC, "garch11": GARCH11, "normal_mean": NORMAL_MEAN}
+_MODEL = {"logistic": LOGISTIC, "garch11": GARCH11, "normal_mean": NORMAL_MEAN,
+          "toggle_switch": TOGGLE_SWITCH}
 
 
 def build(force: bool = True) -> str:
@@ -64,13 +70,14 @@ class _Model(ctypes.Structure):
     _fields_ = [
         ("model", ctypes.c_int32),
         ("n_params", ctypes.c_int32),
-        ("prior", _Prior * 4),
+        ("prior", _Prior * MAX_PARAMS),
         ("constraint", ctypes.c_int32),
         ("x0", ctypes.c_double),
         ("t_end", ctypes.c_double),
         ("steps", ctypes.c_int32),
         ("n_obs", ctypes.c_int32),
         ("noise_sd", ctypes.c_double),
+        ("n_cells", ctypes.c_int32),
     ]
 
 
@@ -96,6 +103,10 @@ def _load():
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         lib.or_path_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
         lib.or_path_normal.restype = ctypes.c_double
+        lib.or_cell_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64]
+        lib.or_cell_normal.restype = ctypes.c_double
+        lib.or_toggle_cells.argtypes = [mp, f64p, ctypes.c_uint64, ctypes.c_uint64, f64p, f64p, f64p]
+        lib.or_toggle_cells.restype = ctypes.c_int
         lib.or_prior_draw.argtypes = [mp, ctypes.c_uint64, ctypes.c_uint64, f64p]
         lib.or_prior_draw.restype = ctypes.c_int
         lib.or_n_summaries.argtypes = [mp]
@@ -142,6 +153,7 @@ def _model(spec: Mapping) -> _Model:
     m.steps = int(spec.get("steps", 0))
     m.n_obs = int(spec.get("n_obs", 0))
     m.noise_sd = float(spec.get("noise_sd", 0.0))
+    m.n_cells = int(spec.get("n_cells", 0))
     return m
 
 
@@ -174,6 +186,24 @@ def box_muller(w0: int, w1: int) -> tuple[float, float]:
 
 def path_normal(seed: int, draw: int, n: int) -> float:
     return float(_load().or_path_normal(seed, draw, n))
+
+
+def cell_normal(seed: int, draw: int, cell: int, n: int) -> float:
+    """Normal n of cell `cell` of a draw (multi-cell models)."""
+    return float(_load().or_cell_normal(seed, draw, cell, n))
+
+
+def toggle_cells(spec: Mapping, theta, seed: int, draw: int) -> dict:
+    """Final levels u, v and measurement y of every cell of one toggle-switch
+    draw at the given theta (cell order)."""
+    m = _model(spec)
+    c = m.n_cells
+    u, v, y = (np.zeros(c, np.float64) for _ in range(3))
+    rc = _load().or_toggle_cells(ctypes.byref(m), np.ascontiguousarray(theta, np.float64), seed,
+                                 draw, u, v, y)
+    if rc != 0:
+        raise ValueError("oracle: not a valid toggle-switch model")
+    return {"u": u, "v": v, "y": y}
 
 
 def n_summaries(spec: Mapping) -> int:
@@ -221,8 +251,8 @@ def abc(spec: Mapping, y_obs, seed: int, first: int, n: int, mode: int, eps_or_f
     d = np.zeros(max(cap, 1), np.float64)
     nacc = ctypes.c_uint64()
     eps = ctypes.c_double()
-    mean = np.zeros(4, np.float64)
-    var = np.zeros(4, np.float64)
+    mean = np.zeros(MAX_PARAMS, np.float64)
+    var = np.zeros(MAX_PARAMS, np.float64)
     rc = _load().or_abc(ctypes.byref(m), np.ascontiguousarray(y_obs, np.float64), seed, first, n,
                         mode, eps_or_frac, cap, idx, th, d, ctypes.byref(nacc), ctypes.byref(eps),
                         mean, var)

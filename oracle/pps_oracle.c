@@ -19,8 +19,10 @@
  *   - the prior-predictive p-value under a family of priors pi(theta|lambda)
  *     (Sec. 4.1, Eqs. pppv and pppvhype), with a tail-area statistic in place
  *     of the predictive density;
- *   - Euler-Maruyama time stepping (Sec. 3.3, Eq. gene_uv_SDE_EM) applied to a
- *     stochastic logistic SDE; a GARCH(1,1) recursion (the Gaussian special
+ *   - Euler-Maruyama time stepping (Sec. 3.3, Eq. gene_uv_SDE_EM) applied to
+ *     the paper's genetic toggle switch (Sec. 3.2, Eqs. gene_uv_SDE and
+ *     gene_u_obs; 19 quantiles of the cell measurements as summaries) and to
+ *     a stochastic logistic SDE; a GARCH(1,1) recursion (the Gaussian special
  *     case of the volatility family of Sec. 4.2); a normal-mean model;
  *   - independent random streams per draw (Sec. 2.5, option (ii) taken to
  *     the limit): the counter-based Philox4x32-10 generator of Salmon, Moraes,
@@ -74,8 +76,9 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 
 /* Stream layout (reading of "keyed by (seed, i)"): key = (lo32 seed, hi32
  * seed); counter = (block b, purpose, lo32 i, hi32 i).  Purpose 0 = prior
- * draws, 1 = the simulated path.                                            */
-enum { OR_PURPOSE_PRIOR = 0, OR_PURPOSE_PATH = 1 };
+ * draws, 1 = the simulated path, 2 + c = cell c of a multi-cell model (the
+ * toggle switch simulates every cell of a draw from its own stream).        */
+enum { OR_PURPOSE_PRIOR = 0, OR_PURPOSE_PATH = 1, OR_PURPOSE_CELL0 = 2 };
 
 void or_stream_block(uint64_t seed, uint64_t draw, uint32_t block, uint32_t purpose,
                      uint32_t out[4])
@@ -108,12 +111,18 @@ void or_box_muller(uint32_t w0, uint32_t w1, double *z0, double *z1)
 
 /* Path normals of one draw: normal n comes from block n/4 of the PATH stream;
  * words (0,1) give normals 4b, 4b+1 and words (2,3) give 4b+2, 4b+3.        */
-void or_path_block(uint64_t seed, uint64_t draw, uint32_t block, double z[4])
+static void normals_block(uint64_t seed, uint64_t draw, uint32_t block, uint32_t purpose,
+                          double z[4])
 {
     uint32_t w[4];
-    or_stream_block(seed, draw, block, OR_PURPOSE_PATH, w);
+    or_stream_block(seed, draw, block, purpose, w);
     or_box_muller(w[0], w[1], &z[0], &z[1]);
     or_box_muller(w[2], w[3], &z[2], &z[3]);
+}
+
+void or_path_block(uint64_t seed, uint64_t draw, uint32_t block, double z[4])
+{
+    normals_block(seed, draw, block, OR_PURPOSE_PATH, z);
 }
 
 double or_path_normal(uint64_t seed, uint64_t draw, uint64_t n)
@@ -123,24 +132,39 @@ double or_path_normal(uint64_t seed, uint64_t draw, uint64_t n)
     return z[n % 4];
 }
 
-/* Sequential reader of the path normals z_0, z_1, ... of one draw.          */
+/* Normal n of cell `cell` of a draw (same block layout, purpose 2 + cell).  */
+double or_cell_normal(uint64_t seed, uint64_t draw, uint32_t cell, uint64_t n)
+{
+    double z[4];
+    normals_block(seed, draw, (uint32_t)(n / 4), OR_PURPOSE_CELL0 + cell, z);
+    return z[n % 4];
+}
+
+/* Sequential reader of the normals z_0, z_1, ... of one stream of a draw.  */
 typedef struct {
     uint64_t seed, draw;
+    uint32_t purpose;
     uint64_t next;
     double buf[4];
 } normal_reader;
 
-static void reader_init(normal_reader *r, uint64_t seed, uint64_t draw)
+static void reader_init_purpose(normal_reader *r, uint64_t seed, uint64_t draw, uint32_t purpose)
 {
     r->seed = seed;
     r->draw = draw;
+    r->purpose = purpose;
     r->next = 0;
+}
+
+static void reader_init(normal_reader *r, uint64_t seed, uint64_t draw)
+{
+    reader_init_purpose(r, seed, draw, OR_PURPOSE_PATH);
 }
 
 static double reader_next(normal_reader *r)
 {
     if (r->next % 4 == 0)
-        or_path_block(r->seed, r->draw, (uint32_t)(r->next / 4), r->buf);
+        normals_block(r->seed, r->draw, (uint32_t)(r->next / 4), r->purpose, r->buf);
     return r->buf[r->next++ % 4];
 }
 
@@ -148,9 +172,9 @@ static double reader_next(normal_reader *r)
 /* Model description (plain data; independent of the GPU library's structs). */
 /* ------------------------------------------------------------------------ */
 enum { OR_UNIFORM = 0, OR_NORMAL = 1, OR_LOGNORMAL = 2, OR_POINT = 3 };
-enum { OR_LOGISTIC = 0, OR_GARCH11 = 1, OR_NORMAL_MEAN = 2 };
+enum { OR_LOGISTIC = 0, OR_GARCH11 = 1, OR_NORMAL_MEAN = 2, OR_TOGGLE_SWITCH = 3 };
 enum { OR_NO_CONSTRAINT = 0, OR_GARCH_STATIONARY = 1 };
-#define OR_MAX_PARAMS 4
+#define OR_MAX_PARAMS 8
 #define OR_MAX_ATTEMPTS 32
 #define OR_GARCH_LAGS 10
 #define OR_GARCH_NSUMM (4 + OR_GARCH_LAGS)
@@ -165,11 +189,14 @@ typedef struct {
     int32_t n_params;
     or_prior prior[OR_MAX_PARAMS];
     int32_t constraint;
-    double x0;        /* logistic: initial state */
-    double t_end;     /* logistic: final time T */
-    int32_t steps;    /* logistic: Euler-Maruyama steps S; GARCH: series length */
-    int32_t n_obs;    /* logistic: observations; normal-mean: sample size */
+    double x0;        /* logistic: initial state; toggle switch: u(0) = v(0) */
+    double t_end;     /* logistic, toggle switch: final time T */
+    int32_t steps;    /* logistic, toggle switch: Euler-Maruyama steps S;
+                         GARCH: series length */
+    int32_t n_obs;    /* logistic: observations; normal-mean: sample size;
+                         toggle switch: number of quantiles */
     double noise_sd;  /* normal-mean: observation sd */
+    int32_t n_cells;  /* toggle switch: cells C */
 } or_model;
 
 /* One prior value from PRIOR block (8*attempt + j): uniform from word 0,
@@ -310,6 +337,78 @@ static void garch_summaries(const double *r, int len, double *s)
     }
 }
 
+/* Genetic toggle switch (Sec. 3.2): expression levels u, v of two genes in
+ * each of C independent cells follow the coupled SDEs of Eq. gene_uv_SDE,
+ * integrated by Euler-Maruyama as in Eq. gene_uv_SDE_EM with dt = T/S:
+ *   u <- u + dt alpha_u / (1 + v^beta_u) - dt (1 + 0.03 u) + 0.5 sqrt(dt) xi_u
+ *   v <- v + dt alpha_v / (1 + u^beta_v) - dt (1 + 0.03 v) + 0.5 sqrt(dt) xi_v
+ * both right-hand sides evaluated at the levels before the step; then each
+ * level is held at the boundary 1 (the model keeps u, v >= 1).  After S steps
+ * the cell is measured with the error model of Eq. gene_u_obs,
+ *   y = u + mu + mu sigma eta / u^gamma,
+ * and y is held at >= 1 like the levels.  theta = (mu, sigma, gamma, alpha_u,
+ * alpha_v, beta_u, beta_v); u(0) = v(0) = x0.  Cell c uses the normals of
+ * stream 2 + c: xi_u of step j is z_{2j}, xi_v is z_{2j+1}, eta is z_{2S}.   */
+static void toggle_cell(const or_model *m, const double *theta, uint64_t seed, uint64_t draw,
+                        int cell, double *u_out, double *v_out, double *y_out)
+{
+    const double mu = theta[0], sigma = theta[1], gamma = theta[2];
+    const double alpha_u = theta[3], alpha_v = theta[4];
+    const double beta_u = theta[5], beta_v = theta[6];
+    const double dt = m->t_end / (double)m->steps;
+    const double noise = 0.5 * sqrt(dt);
+    double u = m->x0, v = m->x0;
+    normal_reader rd;
+    reader_init_purpose(&rd, seed, draw, OR_PURPOSE_CELL0 + (uint32_t)cell);
+    for (int j = 0; j < m->steps; ++j) {
+        const double xi_u = reader_next(&rd);
+        const double xi_v = reader_next(&rd);
+        const double u_next = u + dt * alpha_u / (1.0 + pow(v, beta_u)) - dt * (1.0 + 0.03 * u) +
+                              noise * xi_u;
+        const double v_next = v + dt * alpha_v / (1.0 + pow(u, beta_v)) - dt * (1.0 + 0.03 * v) +
+                              noise * xi_v;
+        u = u_next < 1.0 ? 1.0 : u_next;
+        v = v_next < 1.0 ? 1.0 : v_next;
+    }
+    const double eta = reader_next(&rd);
+    double y = u + mu + mu * sigma * eta / pow(u, gamma);
+    if (y < 1.0)
+        y = 1.0;
+    *u_out = u;
+    *v_out = v;
+    *y_out = y;
+}
+
+static int cmp_double(const void *pa, const void *pb)
+{
+    double a = *(const double *)pa, b = *(const double *)pb;
+    return (a > b) - (a < b);
+}
+
+/* Rank (1-based) of the k-th of K equally spaced quantiles of C values: the
+ * empirical quantile at level k/(K+1) taken as the inverse of the empirical
+ * distribution function, i.e. the ceil(k C / (K+1))-th smallest value.  For
+ * the paper's 19 quantiles of 8000 cells the levels are 0.05, ..., 0.95 and
+ * the ranks 400, 800, ..., 7600.                                             */
+static int64_t quantile_rank(int k, int n_quantiles, int n_cells)
+{
+    return ((int64_t)k * n_cells + n_quantiles) / (n_quantiles + 1);
+}
+
+/* Summaries of one toggle-switch draw (Sec. 3.2, following Vo et al.): the
+ * n_obs equally spaced quantiles of the C measurements.  work: C doubles.   */
+static void simulate_toggle(const or_model *m, const double *theta, uint64_t seed, uint64_t draw,
+                            double *summ, double *work)
+{
+    for (int c = 0; c < m->n_cells; ++c) {
+        double u, v;
+        toggle_cell(m, theta, seed, draw, c, &u, &v, &work[c]);
+    }
+    qsort(work, (size_t)m->n_cells, sizeof(double), cmp_double);
+    for (int k = 1; k <= m->n_obs; ++k)
+        summ[k - 1] = work[quantile_rank(k, m->n_obs, m->n_cells) - 1];
+}
+
 /* Number of summaries (the "data" D of one draw) a model produces.          */
 int or_n_summaries(const or_model *m)
 {
@@ -328,6 +427,9 @@ static void simulate_summaries(const or_model *m, const double *theta, uint64_t 
         break;
     case OR_NORMAL_MEAN:
         simulate_normal_mean(m, theta, seed, draw, summ);
+        break;
+    case OR_TOGGLE_SWITCH:
+        simulate_toggle(m, theta, seed, draw, summ, work);
         break;
     case OR_GARCH11:
     default:
@@ -365,12 +467,19 @@ static int model_ok(const or_model *m)
         return m->n_obs > 0;
     if (m->model == OR_GARCH11)
         return m->n_params >= 3 && m->steps > OR_GARCH_LAGS;
+    if (m->model == OR_TOGGLE_SWITCH)
+        return m->n_params == 7 && m->steps > 0 && m->t_end > 0.0 && m->n_cells > 0 &&
+               m->n_obs > 0;
     return 0;
 }
 
 static size_t work_len(const or_model *m)
 {
-    return m->model == OR_GARCH11 ? (size_t)m->steps : 1;
+    if (m->model == OR_GARCH11)
+        return (size_t)m->steps;
+    if (m->model == OR_TOGGLE_SWITCH)
+        return (size_t)m->n_cells;
+    return 1;
 }
 
 /* Per-draw prior-predictive output for draws i in [first, first + n):
@@ -549,14 +658,16 @@ int or_pvalue(const or_model *m, int lambda_param, int lambda_family, const doub
         {
             double theta[OR_MAX_PARAMS];
             double *summ = (double *)malloc((size_t)ns * sizeof(double));
+            double *work = (double *)malloc(work_len(m) * sizeof(double));
 #pragma omp for schedule(static)
             for (int64_t q = 0; q < (int64_t)n; ++q) {
                 uint64_t draw = first + (uint64_t)q;
                 or_prior_draw(&mk, seed, draw, theta);
-                simulate_summaries(&mk, theta, seed, draw, summ, NULL);
+                simulate_summaries(&mk, theta, seed, draw, summ, work);
                 if (or_mean_stat(summ, ns) >= t_obs)
                     ++count;
             }
+            free(work);
             free(summ);
         }
         (void)np;
@@ -633,6 +744,20 @@ int or_garch_series(const or_model *m, const double *theta, uint64_t seed, uint6
     if (m->model != OR_GARCH11)
         return -1;
     simulate_garch_series(m, theta, seed, draw, r);
+    return 0;
+}
+
+/* Every cell of one toggle-switch draw at a given theta (for checks of the
+ * dynamics, the measurement model and the quantiles): final levels u, v and
+ * the measurement y of cell c, c < C, in cell order.                         */
+int or_toggle_cells(const or_model *m, const double *theta, uint64_t seed, uint64_t draw,
+                    double *u, double *v, double *y)
+{
+    if (m->model != OR_TOGGLE_SWITCH || !model_ok(m))
+        return -1;
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < m->n_cells; ++c)
+        toggle_cell(m, theta, seed, draw, c, &u[c], &v[c], &y[c]);
     return 0;
 }
 

@@ -7,17 +7,21 @@ sides turn a specification here into their own argument structures.
 
 A specification is a plain dict::
 
-    {"model": "logistic" | "garch11" | "normal_mean",
+    {"model": "logistic" | "garch11" | "normal_mean" | "toggle_switch",
      "priors": [(family, a, b), ...],   # family: uniform(a,b) | normal(mu,sd)
                                         #   | lognormal(mu,sd) | point(a)
      "constraint": None | "garch_stationary",
-     "x0": X0, "t_end": T, "steps": S, "n_obs": n, "noise_sd": sd}
+     "x0": X0, "t_end": T, "steps": S, "n_obs": n, "noise_sd": sd,
+     "n_cells": C}                      # toggle switch only
 
 The workloads follow the paper's structure (prior-predictive sampling for ABC,
 Sec. 3; prior-predictive p-values over a hyperparameter family, Sec. 4.1) on
-synthetic models of the same shape: a stochastic logistic SDE observed at 20
-times, a GARCH(1,1) return series of length 2000, and a normal-mean model whose
-prior predictive has a closed form.
+synthetic models of the same shape: the paper's own genetic toggle switch
+(Sec. 3.2: 8000 cells, T = 600, 7 uniform priors, 19 quantiles), a stochastic
+logistic SDE observed at 20 times, a GARCH(1,1) return series of length 2000,
+and a normal-mean model whose prior predictive has a closed form.  The paper's
+toggle-switch measurements are not used: observed quantiles come from a
+simulation at a fixed theta inside the prior's support.
 """
 from __future__ import annotations
 
@@ -33,6 +37,13 @@ SAMPLING_SEED = 1
 
 LOGISTIC_THETA_OBS = (1.0, 100.0, 0.2)
 GARCH_THETA_OBS = (5e-5, 0.1, 0.85)
+# (mu, sigma, gamma, alpha_u, alpha_v, beta_u, beta_v): a point inside the
+# toggle-switch prior's support, used to make the synthetic observed data.
+TOGGLE_THETA_OBS = (320.0, 0.25, 0.15, 22.0, 12.0, 4.0, 4.5)
+# Priors of Sec. 3.2 (after Bonassi et al.), in the order of theta above.
+TOGGLE_PRIORS = [("uniform", 250.0, 400.0), ("uniform", 0.05, 0.5), ("uniform", 0.05, 0.35),
+                 ("uniform", 0.0, 50.0), ("uniform", 0.0, 50.0), ("uniform", 0.0, 7.0),
+                 ("uniform", 0.0, 7.0)]
 
 
 def logistic_spec(steps: int = 1000, t_end: float = 10.0, n_obs: int = 20, x0: float = 10.0,
@@ -67,6 +78,21 @@ def normal_mean_spec(n_obs: int = 20, noise_sd: float = 1.0, prior_sd: float = 1
             "x0": 0.0, "t_end": 0.0, "steps": 0, "n_obs": n_obs, "noise_sd": noise_sd}
 
 
+def toggle_spec(n_cells: int = 8000, steps: int = 599, dt: float = 1.0, n_quantiles: int = 19,
+                x0: float = 10.0, priors=None) -> dict:
+    """The genetic toggle switch of Sec. 3.2: C cells, S Euler-Maruyama steps
+    of size dt (the paper: T = 600 time points, i.e. 599 steps, dt = 1),
+    u(0) = v(0) = x0, summaries = n_quantiles equally spaced quantiles."""
+    return {"model": "toggle_switch", "priors": list(priors or TOGGLE_PRIORS),
+            "constraint": None, "x0": x0, "t_end": steps * dt, "steps": steps,
+            "n_obs": n_quantiles, "noise_sd": 0.0, "n_cells": n_cells}
+
+
+def toggle_point_spec(theta=TOGGLE_THETA_OBS, **kw) -> dict:
+    """The toggle switch with every prior a point mass (used to make y_obs)."""
+    return toggle_spec(priors=[("point", float(t), 0.0) for t in theta], **kw)
+
+
 def lambda_grid(n: int = 64, lo: float = 0.05, hi: float = 3.0) -> np.ndarray:
     """n log-spaced values from lo to hi (inclusive)."""
     k = np.arange(n, dtype=np.float64)
@@ -85,6 +111,7 @@ ABC_LARGE = {"name": "abc_logistic_n1e7", "n": 10_000_000, "pilot_n": 100_000, "
 PVALUE_BATCH = {"name": "pvalue_logistic_64lambda_n1e6", "n": 1_000_000, "n_lambda": 64}
 SERVING_MIX = {"name": "serving_mix_2000jobs_200hz", "n_jobs": 2000, "rate_hz": 200.0, "seed": 3}
 GARCH_CHECK = {"name": "garch11_L2000_n1e6", "n": 1_000_000, "series_len": 2000}
+TOGGLE_PPS = {"name": "toggle_switch_C8000_T600_n8064", "n": 8064, "n_cells": 8000, "steps": 599}
 
 
 def serving_jobs(n_jobs: int = 2000, rate_hz: float = 200.0, seed: int = 3,
