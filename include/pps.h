@@ -24,8 +24,9 @@
  *     Work is stream-ordered; the synchronous calls block only for their
  *     final small device-to-host copy and return with all their work done.
  *   - Draw i uses its own Philox4x32-10 stream: key = (lo32 seed, hi32 seed),
- *     counter = (block, purpose, lo32 i, hi32 i), purpose 0 = prior, 1 = path
- *     (Sec. 2.5: independent streams; Philox from Salmon et al., SC'11).  So
+ *     counter = (block, purpose, lo32 i, hi32 i), purpose 0 = prior, 1 = path,
+ *     2 + c = cell c of the toggle switch (Sec. 2.5: independent streams;
+ *     Philox from Salmon et al., SC'11).  So
  *     the result of a draw depends only on (seed, i) and the model, never on
  *     launch shape, batching or which other jobs share the GPU.
  *   - Simulation runs in FP32 on the GPU; priors, p-values (counts) and ABC
@@ -54,8 +55,9 @@ extern "C" {
                             stats->n_accepted holds the true count */
 
 /* ---- model description (the "prior, simulator, discrepancy" of Alg. 1) -- */
-#define PPS_MAX_PARAMS 4
+#define PPS_MAX_PARAMS 8
 #define PPS_MAX_OBS 64
+#define PPS_TSW_MAX_CELLS 8192 /* toggle switch: cells per draw (one LDS sort) */
 #define PPS_GARCH_LAGS 10
 #define PPS_GARCH_NSUMM 14 /* mean, variance, skewness, kurtosis, ACF(r^2) lags 1..10 */
 
@@ -80,7 +82,23 @@ enum pps_model_kind {
     PPS_GARCH11 = 1,
     /* y_j = th1 + noise_sd z_j, j = 1..n_obs.  Summaries: the y_j;
      * statistic: their mean. */
-    PPS_NORMAL_MEAN = 2
+    PPS_NORMAL_MEAN = 2,
+    /* The genetic toggle switch of Sec. 3.2: n_cells independent cells, each
+     * with gene levels u, v (u(0) = v(0) = x0) advanced by Euler-Maruyama
+     * (Eq. gene_uv_SDE_EM), dt = t_end/steps,
+     *   u <- u + dt alpha_u/(1 + v^beta_u) - dt (1 + 0.03 u) + 0.5 sqrt(dt) xi_u
+     *   v <- v + dt alpha_v/(1 + u^beta_v) - dt (1 + 0.03 v) + 0.5 sqrt(dt) xi_v
+     * (both from the levels before the step), each level held at >= 1; then
+     * measured as y = u + mu + mu sigma eta / u^gamma (Eq. gene_u_obs), held
+     * at >= 1.  theta = (mu, sigma, gamma, alpha_u, alpha_v, beta_u, beta_v).
+     * Cell c draws xi_u, xi_v of step j and eta as normals 2j, 2j+1 and
+     * 2 steps of stream purpose 2 + c.  Summaries: n_obs equally spaced
+     * quantiles, the k-th being the ceil(k n_cells / (n_obs + 1))-th
+     * smallest y (the inverse empirical CDF at level k / (n_obs + 1); the
+     * paper's 19 quantiles of 8000 cells are ranks 400, 800, ..., 7600);
+     * statistic: their mean.  Simulated one draw per workgroup with the
+     * cells across lanes. */
+    PPS_TOGGLE_SWITCH = 3
 };
 
 enum pps_constraint {
@@ -98,14 +116,17 @@ typedef struct {
 
 typedef struct {
     int32_t model;    /* enum pps_model_kind */
-    int32_t n_params; /* 1..PPS_MAX_PARAMS (logistic and GARCH: 3) */
+    int32_t n_params; /* 1..PPS_MAX_PARAMS (logistic and GARCH: 3; toggle switch: 7) */
     pps_prior prior[PPS_MAX_PARAMS];
     int32_t constraint; /* enum pps_constraint */
-    double x0;          /* logistic: X(0) */
-    double t_end;       /* logistic: final time T */
-    int32_t steps;      /* logistic: EM steps (multiple of n_obs); GARCH: series length (> 10) */
-    int32_t n_obs;      /* logistic / normal-mean: observations (1..PPS_MAX_OBS) */
+    double x0;          /* logistic: X(0); toggle switch: u(0) = v(0) */
+    double t_end;       /* logistic, toggle switch: final time T */
+    int32_t steps;      /* logistic: EM steps (multiple of n_obs); toggle switch: EM
+                           steps (>= 1); GARCH: series length (multiple of 20) */
+    int32_t n_obs;      /* logistic / normal-mean: observations; toggle switch:
+                           quantiles (1..PPS_MAX_OBS) */
     double noise_sd;    /* normal-mean: observation sd */
+    int32_t n_cells;    /* toggle switch: cells per draw (1..PPS_TSW_MAX_CELLS) */
 } pps_model;
 
 typedef struct {
@@ -134,7 +155,7 @@ int pps_normals(uint64_t seed, uint64_t first_draw, uint64_t n, uint32_t m, floa
 /* Simulates draws [first_draw, first_draw + n_draws) and writes, per draw q:
  *   theta[j*n + q]  the prior draw (FP32; FP64 draw rounded), j < n_params;
  *   summ[k*n + q]   summary k (logistic: observation k; GARCH: the 14
- *                   summaries; normal-mean: y_k);
+ *                   summaries; normal-mean: y_k; toggle switch: quantile k);
  *   stat[q]         the mean of the observations (not for GARCH; may be NULL);
  *   dist[q]         Euclidean distance to y_obs (only when y_obs != NULL;
  *                   else may be NULL).
@@ -144,7 +165,8 @@ int pps_simulate(const pps_model *model, const pps_sampling *sampling, const dou
                  float *theta, float *summ, float *stat, float *dist, void *stream);
 
 /* Number of summaries a model produces (n_obs, or PPS_GARCH_NSUMM), or a
- * negative status for an invalid model. */
+ * negative status for an invalid model.  Also the validity check of a model
+ * description: PPS_EINVAL with a message for any field out of range. */
 int pps_n_summaries(const pps_model *model);
 
 /* ---- ABC rejection, fixed-N form (Alg. 1 and the paragraph after it) ---- */
@@ -181,15 +203,17 @@ int abc_sample(const pps_model *model, const double *y_obs, const pps_sampling *
  * pvalue[k] = count_ge[k] / N.  All lambda values run in one launch; for the
  * logistic SDE, lambda values are simulated in groups of 8 per lane from one
  * random stream (the common random numbers make their normals identical).
- * lambda, count_ge, pvalue: host arrays of n_lambda (1..4096).
+ * lambda, count_ge, pvalue: host arrays of n_lambda (1..4096).  For the
+ * toggle switch T_i is the mean of its quantile summaries.
  * Not for GARCH (use pps_summary_tally). */
 int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_family,
                       const double *lambda, int n_lambda, const pps_sampling *sampling,
                       double t_obs, uint64_t *count_ge, double *pvalue, void *stream);
 
 /* Per-summary tail-area counts (the prior-predictive check of a summary
- * vector): count_ge[s] = #{i : S_s(D_i) >= obs_summ[s]}, s < n_summaries.
- * obs_summ, count_ge: host. */
+ * vector): count_ge[s] = #{i : S_s(D_i) >= obs_summ[s]} (compared in FP64),
+ * s < n_summaries.  GARCH and toggle-switch models.  obs_summ, count_ge:
+ * host. */
 int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
                       const double *obs_summ, uint64_t *count_ge, void *stream);
 
@@ -307,7 +331,8 @@ double pps_last_kernel_ms(void);
 /* ---- launch shape ------------------------------------------------------- */
 
 /* Workgroup size of the persistent simulation kernel for a model class
- * (0: logistic SDE and normal-mean; 1: GARCH): 64, 128 or 256.  Results
+ * (0: logistic SDE and normal-mean; 1: GARCH; 2: lambda groups: 64, 128 or
+ * 256; 3: toggle switch: 256, 512 or 1024).  Results
  * do not depend on it (draw i's arithmetic depends only on (seed, i)).
  * Returns PPS_OK or PPS_EINVAL.  pps_get_block_size returns the current
  * size, or PPS_EINVAL for an unknown class. */
@@ -318,10 +343,11 @@ int pps_get_block_size(int model_class);
  * interleaved per lane (1 or 2) and Philox blocks generated per loop trip
  * (1 or 2; logistic SDE).  Classes: 0 logistic SDE / normal-mean, 1 GARCH,
  * 2 lambda groups of a p-value grid (8 lambda values of one draw per lane,
- * sharing its random numbers).  Supported shapes: class 0 block
- * {64, 128, 256} x draws_per_lane {1, 2} x unroll {1, 2}; classes 1 and 2
- * block {64, 128, 256} with (1, 1).  Results do not depend on the shape.
- * PPS_EINVAL otherwise. */
+ * sharing its random numbers), 3 toggle switch (one draw per workgroup, its
+ * cells across the lanes).  Supported shapes: class 0 block {64, 128, 256}
+ * x draws_per_lane {1, 2} x unroll {1, 2}; classes 1 and 2 block
+ * {64, 128, 256} with (1, 1); class 3 block {256, 512, 1024} with (1, 1).
+ * Results do not depend on the shape.  PPS_EINVAL otherwise. */
 int pps_set_launch_shape(int model_class, int block, int draws_per_lane, int unroll);
 int pps_get_launch_shape(int model_class, int *block, int *draws_per_lane, int *unroll);
 

@@ -21,14 +21,17 @@ LIB_PATH = os.path.join(_HERE, "libpps.so")
 PPS_OK, PPS_PENDING = 0, 1
 PPS_EINVAL, PPS_ENOMEM, PPS_EDEVICE, PPS_EBUSY, PPS_ENOTFOUND, PPS_ETRUNC = -1, -2, -3, -4, -5, -6
 PPS_UNIFORM, PPS_NORMAL, PPS_LOGNORMAL, PPS_POINT = 0, 1, 2, 3
-PPS_LOGISTIC_SDE, PPS_GARCH11, PPS_NORMAL_MEAN = 0, 1, 2
+PPS_LOGISTIC_SDE, PPS_GARCH11, PPS_NORMAL_MEAN, PPS_TOGGLE_SWITCH = 0, 1, 2, 3
 PPS_NO_CONSTRAINT, PPS_GARCH_STATIONARY = 0, 1
 PPS_EPS_FIXED, PPS_EPS_TOP_FRACTION = 0, 1
-PPS_MAX_PARAMS, PPS_MAX_OBS, PPS_GARCH_NSUMM = 4, 64, 14
+PPS_MAX_PARAMS, PPS_MAX_OBS, PPS_GARCH_NSUMM, PPS_TSW_MAX_CELLS = 8, 64, 14, 8192
+# kernel classes (pps_set_launch_shape)
+CLASS_PATH, CLASS_GARCH, CLASS_GROUP, CLASS_CELLS = 0, 1, 2, 3
 
 FAMILY = {"uniform": PPS_UNIFORM, "normal": PPS_NORMAL, "lognormal": PPS_LOGNORMAL,
           "point": PPS_POINT}
-MODEL = {"logistic": PPS_LOGISTIC_SDE, "garch11": PPS_GARCH11, "normal_mean": PPS_NORMAL_MEAN}
+MODEL = {"logistic": PPS_LOGISTIC_SDE, "garch11": PPS_GARCH11, "normal_mean": PPS_NORMAL_MEAN,
+         "toggle_switch": PPS_TOGGLE_SWITCH}
 
 
 class PPSError(RuntimeError):
@@ -52,6 +55,7 @@ class pps_model(ctypes.Structure):
         ("steps", ctypes.c_int32),
         ("n_obs", ctypes.c_int32),
         ("noise_sd", ctypes.c_double),
+        ("n_cells", ctypes.c_int32),
     ]
 
 
@@ -215,6 +219,7 @@ def make_model(spec: Mapping) -> pps_model:
     m.steps = int(spec.get("steps", 0))
     m.n_obs = int(spec.get("n_obs", 0))
     m.noise_sd = float(spec.get("noise_sd", 0.0))
+    m.n_cells = int(spec.get("n_cells", 0))
     return m
 
 
@@ -274,6 +279,7 @@ def pps_get_launch_shape(model_class: int) -> tuple[int, int, int]:
 
 PATH_SHAPES = [(b, d, u) for b in (64, 128, 256) for d in (1, 2) for u in (1, 2)]
 GARCH_SHAPES = [(b, 1, 1) for b in (64, 128, 256)]
+CELL_SHAPES = [(b, 1, 1) for b in (256, 512, 1024)]
 
 
 def pps_autotune(model, n_draws: int, use_cache: bool = True, stream=None) -> dict:

@@ -240,8 +240,9 @@ int abc_sample(const pps_model *model, const double *y_obs, const pps_sampling *
     for (int k = 0; k < ns; ++k)
         J.y_obs[k] = static_cast<float>(y_obs[k]);
     J.dist = scr.dist;
-    whole_job(*c->engine, CLASS_PATH, J);
-    plan.rows[CLASS_PATH].push_back(J);
+    const int cls = model_class(model);
+    whole_job(*c->engine, cls, J);
+    plan.rows[cls].push_back(J);
     FinJob F;
     fill_fin(F, J, eps_mode, eps_or_frac, capacity, acc_idx, acc_theta, acc_dist, scr);
     plan.fins.push_back(F);
@@ -300,7 +301,7 @@ int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_famil
     EpochPlan plan;
     std::vector<std::pair<int, size_t>> where(n_lambda);  // (class, row index)
     for (int k = 0; k < n_lambda; ++k) {
-        const int cls = k < grouped ? CLASS_GROUP : CLASS_PATH;
+        const int cls = k < grouped ? CLASS_GROUP : model_class(model);
         JobDev J;
         fill_job(J, &mk[k], sampling, ns, JOB_TALLY_STAT);
         J.t_obs = t_obs;
@@ -329,8 +330,8 @@ int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
     int ns = 0, rc;
     PPS_TRY(validate_model(model, &ns));
     PPS_TRY(validate_sampling(sampling));
-    if (model->model != PPS_GARCH11)
-        return fail(PPS_EINVAL, "pps_summary_tally: GARCH models only");
+    if (model->model != PPS_GARCH11 && model->model != PPS_TOGGLE_SWITCH)
+        return fail(PPS_EINVAL, "pps_summary_tally: GARCH and toggle-switch models only");
     if (!obs_summ || !count_ge)
         return fail(PPS_EINVAL, "obs_summ and count_ge are required");
     Context *c = current_context(&rc);
@@ -346,8 +347,9 @@ int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
     J.counts = c->counts.as<unsigned long long>();
     J.n_counts = static_cast<uint32_t>(ns);
     J.row_flags = ROW_ZERO_COUNTS | ROW_COPY_COUNTS;
-    whole_job(*c->engine, CLASS_GARCH, J);
-    plan.rows[CLASS_GARCH].push_back(J);
+    const int cls = model_class(model);
+    whole_job(*c->engine, cls, J);
+    plan.rows[cls].push_back(J);
     PPS_TRY(run_sync(*c, plan, as_stream(stream)));
     std::memcpy(count_ge, c->engine->out_counts(0), ns * sizeof(unsigned long long));
     return PPS_OK;

@@ -18,7 +18,7 @@ namespace {
 std::vector<SimShape> candidate_shapes(int cls)
 {
     std::vector<SimShape> out;
-    for (int block : {64, 128, 256})
+    for (int block : {64, 128, 256, 512, 1024})
         for (int dpl : {1, 2})
             for (int unroll : {1, 2}) {
                 SimShape sh;

@@ -42,7 +42,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     return {c0, c1, c2, c3};
 }
 
-enum : uint32_t { PURPOSE_PRIOR = 0, PURPOSE_PATH = 1 };
+// Stream purposes: prior draws, the path of a one-lane model, and cell c of a
+// multi-cell model (the toggle switch) as PURPOSE_CELL0 + c.
+enum : uint32_t { PURPOSE_PRIOR = 0, PURPOSE_PATH = 1, PURPOSE_CELL0 = 2 };
 
 struct StreamKey {
     uint32_t k0, k1;  // (lo32 seed, hi32 seed)
@@ -105,6 +107,16 @@ __device__ __forceinline__ void path_normals4(StreamKey key, uint64_t draw, uint
     box_muller_f32(w.z, w.w, z2, z3);
 }
 
+// Four normals z_{4b..4b+3} of cell `cell` of one draw.
+__device__ __forceinline__ void cell_normals4(StreamKey key, uint64_t draw, uint32_t cell,
+                                              uint32_t block, float &z0, float &z1, float &z2,
+                                              float &z3)
+{
+    const Words4 w = stream_block(key, draw, block, PURPOSE_CELL0 + cell);
+    box_muller_f32(w.x, w.y, z0, z1);
+    box_muller_f32(w.z, w.w, z2, z3);
+}
+
 // ---------------------------------------------------------------------------
 // Prior draws (FP64).  Parameter j of attempt t uses PRIOR block 8t + j:
 // uniform from word 0, normal / log-normal from words (0, 1).  The uniform
@@ -130,12 +142,14 @@ constexpr int MAX_PRIOR_ATTEMPTS = 32;
 
 // theta ~ pi(theta); with the GARCH constraint, attempts whose
 // theta[1] + theta[2] >= 1 are redrawn (the last attempt is kept after 32).
+// MAXP is the size of `theta` (the parameters a kernel holds in registers).
+template <int MAXP>
 __device__ __forceinline__ void prior_draw(const PriorDev *prior, int n_params, int constraint,
                                            StreamKey key, uint64_t draw, double *theta)
 {
     for (int attempt = 0;; ++attempt) {
 #pragma unroll
-        for (int j = 0; j < PPS_MAX_PARAMS; ++j)
+        for (int j = 0; j < MAXP; ++j)
             if (j < n_params)
                 theta[j] = prior_value(prior[j], key, draw, j, attempt);
         if (constraint != PPS_GARCH_STATIONARY)

@@ -41,8 +41,12 @@ class EpochEngine {
 
     void set_shape(int cls, const SimShape &sh) { shape_.sim[cls] = sh; }
     const SimShape &shape(int cls) const { return shape_.sim[cls]; }
+    // Draws per tile: one per workgroup for the cell class, else one per lane
+    // and interleaved draw.
     uint64_t tile_size(int cls) const
     {
+        if (cls == CLASS_CELLS)
+            return 1;
         return static_cast<uint64_t>(shape_.sim[cls].block) * shape_.sim[cls].dpl;
     }
     uint64_t tiles_for(int cls, uint64_t n) const

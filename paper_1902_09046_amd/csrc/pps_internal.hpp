@@ -21,9 +21,14 @@ enum : int32_t {
 // holds p-value rows of one lambda grid in groups of GROUP_LPL consecutive
 // rows that differ only in the prior of parameter `lambda_param`: one lane
 // simulates a draw under every lambda of its group from one random stream
-// (common random numbers).
-enum : int { CLASS_PATH = 0, CLASS_GARCH = 1, CLASS_GROUP = 2, N_CLASSES = 3 };
+// (common random numbers).  CLASS_CELLS runs one draw per workgroup with the
+// draw's cells across the lanes (the toggle switch): a tile is one draw.
+enum : int { CLASS_PATH = 0, CLASS_GARCH = 1, CLASS_GROUP = 2, CLASS_CELLS = 3, N_CLASSES = 4 };
 constexpr int GROUP_LPL = 8;
+
+// Prior parameters held by the one-lane-per-draw kernels (logistic SDE,
+// normal-mean, GARCH: at most 3 used); the cell kernel holds PPS_MAX_PARAMS.
+constexpr int SDE_MAX_PARAMS = 4;
 
 // Row flags handled by the epoch stage-in / stage-out kernels.
 enum : uint32_t {
@@ -50,6 +55,8 @@ struct alignas(16) JobDev {
     int32_t obs_stride;
     int32_t constraint;
     int32_t tile_size;
+    int32_t n_cells;       // CLASS_CELLS: cells per draw
+    int32_t pad0;
     uint64_t seed;
     uint64_t first_draw;
     uint64_t n_draws;
@@ -61,7 +68,7 @@ struct alignas(16) JobDev {
     double dt;
     double noise_sd;
     double t_obs;
-    double summ_obs[PPS_GARCH_NSUMM];
+    double summ_obs[PPS_MAX_OBS];  // JOB_TALLY_SUMM: observed summaries (FP64)
     float y_obs[PPS_MAX_OBS];
     float *dist;                 // JOB_WRITE_DIST: n_draws floats
     unsigned long long *counts;  // tallies

@@ -6,6 +6,11 @@
 //                 registers (no random-number buffers), then per-draw
 //                 epilogues: rho to HBM (ABC), tail-area tallies by wave
 //                 ballot + popcount (p-values), or a full per-draw dump.
+// k_simulate_group  p-value grids: one lane simulates a draw under 8 lambda
+//                 values of a grid from one random stream.
+// k_simulate_cells  the toggle switch: one draw per workgroup, its cells
+//                 across the lanes, their measurements sorted in LDS and
+//                 reduced to quantile summaries on the CU.
 // k_sel_*         radix select of the k-th smallest rho on its FP32 bit
 //                 pattern (rho >= 0, so bit order = value order): 11/11/10
 //                 bit digits, LDS histograms merged into a global histogram.
@@ -30,6 +35,12 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// A float known to be equal in every lane, moved to a scalar register.
+__device__ __forceinline__ float wave_uniform_f32(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
 
 // ===========================================================================
 // Per-draw simulators.  Each returns the summaries the epilogue needs.
@@ -230,7 +241,7 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
 template <int DPL, int UNROLL>
 __device__ __forceinline__ void sim_logistic_ilp(const JobDev *__restrict__ J, StreamKey key,
                                                  const uint64_t (&draw)[DPL],
-                                                 const double (&theta)[DPL][PPS_MAX_PARAMS],
+                                                 const double (&theta)[DPL][SDE_MAX_PARAMS],
                                                  Kahan (&d2)[DPL], Kahan (&sum)[DPL])
 {
     const double dt = J->dt;
@@ -369,19 +380,19 @@ __global__ __launch_bounds__(BLOCK) void k_simulate(const EpochHeader *__restric
             valid[d] = q[d] < n;
             draw[d] = J->first_draw + q[d];
         }
-        double theta[DPL][PPS_MAX_PARAMS];
+        double theta[DPL][SDE_MAX_PARAMS];
         double summ[PPS_GARCH_NSUMM];
         Kahan d2[DPL], sum[DPL];
 #pragma unroll
         for (int d = 0; d < DPL; ++d)
 #pragma unroll
-            for (int j = 0; j < PPS_MAX_PARAMS; ++j)
+            for (int j = 0; j < SDE_MAX_PARAMS; ++j)
                 theta[d][j] = 0.0;
         const int model = J->model;
         if (wave_live) {
 #pragma unroll
             for (int d = 0; d < DPL; ++d)
-                prior_draw(J->prior, J->n_params, J->constraint, key, draw[d], theta[d]);
+                prior_draw<SDE_MAX_PARAMS>(J->prior, J->n_params, J->constraint, key, draw[d], theta[d]);
             if constexpr (CLASS == CLASS_GARCH) {
                 sim_garch(J, key, draw[0], theta[0], summ);
             } else {
@@ -499,8 +510,8 @@ __global__ __launch_bounds__(BLOCK) void k_simulate_group(const EpochHeader *__r
         const StreamKey key = make_key(J->seed);
         Kahan sum[LPL];
         if (wave_live) {
-            double theta[PPS_MAX_PARAMS] = {0.0, 0.0, 0.0, 0.0};
-            prior_draw(J->prior, J->n_params, J->constraint, key, draw, theta);
+            double theta[SDE_MAX_PARAMS] = {0.0, 0.0, 0.0, 0.0};
+            prior_draw<SDE_MAX_PARAMS>(J->prior, J->n_params, J->constraint, key, draw, theta);
             const int lp = J->lambda_param;
             const double dt = J->dt;
             float a[LPL], b[LPL], c[LPL], x[LPL];
@@ -563,6 +574,205 @@ __global__ __launch_bounds__(BLOCK) void k_simulate_group(const EpochHeader *__r
             if (tot)
                 atomicAdd(&J[tid].counts[0], static_cast<unsigned long long>(tot));
         }
+    }
+}
+
+// ===========================================================================
+// Genetic toggle switch (one draw per workgroup).
+//
+// A tile is one draw.  Every lane draws the same theta (FP64, rounded to
+// FP32 constants), then the workgroup's lanes take the draw's cells in turn,
+// each cell's two gene levels held in VGPRs for all steps with its normals
+// regenerated from the cell's own stream.  The cells' measurements land in
+// LDS, a bitonic sort orders them there, and the quantile summaries are read
+// at their ranks: the measurements of a draw never leave the CU.
+// ===========================================================================
+struct ToggleConsts {
+    float mu;        // mu
+    float mu_sigma;  // mu * sigma
+    float gamma;
+    float dt_alpha_u, dt_alpha_v;  // dt alpha_u, dt alpha_v
+    float beta_u, beta_v;
+    float dt;        // dt
+    float decay;     // 0.03 dt
+    float noise;     // 0.5 sqrt(dt)
+};
+
+// One Euler-Maruyama step of one cell (Eq. gene_uv_SDE_EM) from the levels
+// before the step; v^beta_u = exp2(beta_u log2 v) with the hardware log2 /
+// exp2 (levels are >= 1, so log2 >= 0), the Hill factor 1 / (1 + p) by the
+// hardware reciprocal.
+__device__ __forceinline__ void toggle_step(const ToggleConsts &P, float &u, float &v, float xi_u,
+                                            float xi_v)
+{
+    const float pu = __builtin_amdgcn_exp2f(P.beta_u * __builtin_amdgcn_logf(v));
+    const float pv = __builtin_amdgcn_exp2f(P.beta_v * __builtin_amdgcn_logf(u));
+    float du = __builtin_fmaf(-P.decay, u, -P.dt);  // -dt (1 + 0.03 u)
+    float dv = __builtin_fmaf(-P.decay, v, -P.dt);
+    du = __builtin_fmaf(P.dt_alpha_u, __builtin_amdgcn_rcpf(1.0f + pu), du);
+    dv = __builtin_fmaf(P.dt_alpha_v, __builtin_amdgcn_rcpf(1.0f + pv), dv);
+    u = __builtin_fmaxf(__builtin_fmaf(P.noise, xi_u, u + du), 1.0f);
+    v = __builtin_fmaxf(__builtin_fmaf(P.noise, xi_v, v + dv), 1.0f);
+}
+
+// Measurement of one cell after `steps` steps (Eq. gene_u_obs), held at >= 1.
+// Step j uses normals 2j, 2j+1 of the cell's stream (Philox block j/2 holds
+// steps 2b and 2b+1); the measurement noise is normal 2 steps.
+__device__ __forceinline__ float toggle_cell(const ToggleConsts &P, StreamKey key, uint64_t draw,
+                                             uint32_t cell, int steps, float x0)
+{
+    float u = x0, v = x0;
+    const int pairs = steps >> 1;
+    for (int b = 0; b < pairs; ++b) {
+        float z0, z1, z2, z3;
+        cell_normals4(key, draw, cell, static_cast<uint32_t>(b), z0, z1, z2, z3);
+        toggle_step(P, u, v, z0, z1);
+        toggle_step(P, u, v, z2, z3);
+    }
+    const Words4 w = stream_block(key, draw, static_cast<uint32_t>(pairs), PURPOSE_CELL0 + cell);
+    float z0, z1, eta;
+    box_muller_f32(w.x, w.y, z0, z1);
+    if (steps & 1) {
+        toggle_step(P, u, v, z0, z1);
+        float z3;
+        box_muller_f32(w.z, w.w, eta, z3);
+    } else {
+        eta = z0;
+    }
+    // u^-gamma = exp2(-gamma log2 u)
+    const float scale = __builtin_amdgcn_exp2f(-P.gamma * __builtin_amdgcn_logf(u));
+    const float y = __builtin_fmaf(P.mu_sigma * eta, scale, u + P.mu);
+    return __builtin_fmaxf(y, 1.0f);
+}
+
+// Ascending bitonic sort of s[0 .. n2) (n2 a power of two) by the workgroup.
+template <int BLOCK>
+__device__ __forceinline__ void lds_bitonic_sort(float *s, unsigned n2)
+{
+    for (unsigned k = 2; k <= n2; k <<= 1) {
+        for (unsigned j = k >> 1; j > 0; j >>= 1) {
+            for (unsigned i = threadIdx.x; i < (n2 >> 1); i += BLOCK) {
+                const unsigned lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                const unsigned hi = lo | j;
+                const float a = s[lo];
+                const float b = s[hi];
+                if ((a > b) == ((lo & k) == 0)) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_simulate_cells(const EpochHeader *__restrict__ hdr,
+                                                          const JobDev *__restrict__ rows,
+                                                          LaunchState *__restrict__ states)
+{
+    __shared__ unsigned long long s_tile;
+    __shared__ double s_theta[PPS_MAX_PARAMS];
+    __shared__ float s_q[PPS_MAX_OBS];
+    __shared__ float s_y[PPS_TSW_MAX_CELLS];
+    const unsigned tid = threadIdx.x;
+    const int n_jobs = static_cast<int>(hdr->class_rows[CLASS_CELLS]);
+    const uint64_t total_tiles = hdr->class_tiles[CLASS_CELLS];
+    const JobDev *__restrict__ jobs = rows + hdr->class_first[CLASS_CELLS];
+    LaunchState *__restrict__ state = states + CLASS_CELLS;
+    for (;;) {
+        if (tid == 0)
+            s_tile = atomicAdd(&state->next_tile, 1ull);
+        __syncthreads();
+        const uint64_t t = uniform_u64(s_tile);
+        __syncthreads();
+        if (t >= total_tiles)
+            break;
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const JobDev *__restrict__ J = jobs + lo;
+        const int flags = J->flags;
+        const uint64_t n = J->n_draws;
+        const uint64_t q = t - J->tile_begin + J->tile_offset;  // one draw per tile
+        const uint64_t draw = J->first_draw + q;
+        const StreamKey key = make_key(J->seed);
+        // theta ~ prior: lane j draws parameter j (the model has no
+        // constraint, so the parameters are independent draws, attempt 0)
+        if (tid < static_cast<unsigned>(J->n_params))
+            s_theta[tid] = prior_value(J->prior[tid], key, draw, static_cast<int>(tid), 0);
+        __syncthreads();
+        ToggleConsts P;
+        {
+            // the same in every lane: the constants live in SGPRs
+            const double dt = J->dt;
+            P.mu = wave_uniform_f32(static_cast<float>(s_theta[0]));
+            P.mu_sigma = wave_uniform_f32(static_cast<float>(s_theta[0] * s_theta[1]));
+            P.gamma = wave_uniform_f32(static_cast<float>(s_theta[2]));
+            P.dt_alpha_u = wave_uniform_f32(static_cast<float>(dt * s_theta[3]));
+            P.dt_alpha_v = wave_uniform_f32(static_cast<float>(dt * s_theta[4]));
+            P.beta_u = wave_uniform_f32(static_cast<float>(s_theta[5]));
+            P.beta_v = wave_uniform_f32(static_cast<float>(s_theta[6]));
+            P.dt = wave_uniform_f32(static_cast<float>(dt));
+            P.decay = wave_uniform_f32(static_cast<float>(0.03 * dt));
+            P.noise = wave_uniform_f32(static_cast<float>(0.5 * sqrt(dt)));
+        }
+        const unsigned n_cells = static_cast<unsigned>(J->n_cells);
+        const int steps = J->steps;
+        const float x0 = static_cast<float>(J->x0);
+        for (unsigned c = tid; c < n_cells; c += BLOCK)
+            s_y[c] = toggle_cell(P, key, draw, c, steps, x0);
+        unsigned n2 = 1;
+        while (n2 < n_cells)
+            n2 <<= 1;
+        for (unsigned c = n_cells + tid; c < n2; c += BLOCK)
+            s_y[c] = __builtin_inff();
+        __syncthreads();
+        lds_bitonic_sort<BLOCK>(s_y, n2);
+        // quantile k (1-based) is the ceil(k C / (K + 1))-th smallest value
+        const int ns = J->n_summ;
+        const unsigned kq = tid + 1;
+        const float qv = static_cast<int>(tid) < ns
+                             ? s_y[(kq * n_cells + static_cast<unsigned>(ns)) / (ns + 1) - 1]
+                             : 0.0f;
+        if ((flags & JOB_DUMP) && J->dump_summ && static_cast<int>(tid) < ns)
+            J->dump_summ[static_cast<uint64_t>(tid) * n + q] = qv;
+        if ((flags & JOB_TALLY_SUMM) && static_cast<int>(tid) < ns &&
+            static_cast<double>(qv) >= J->summ_obs[tid])
+            atomicAdd(&J->counts[tid], 1ull);
+        if (static_cast<int>(tid) < ns)
+            s_q[tid] = qv;
+        if ((flags & JOB_DUMP) && J->dump_theta && static_cast<int>(tid) < J->n_params)
+            J->dump_theta[static_cast<uint64_t>(tid) * n + q] = static_cast<float>(s_theta[tid]);
+        __syncthreads();
+        // Distance and statistic: every lane runs the same loop over the
+        // quantiles in LDS (uniform control flow: no divergent loop may sit
+        // between the last barrier of a tile and the first of the next).
+        Kahan d2, sum;
+        for (int k = 0; k < ns; ++k) {
+            const float v = s_q[k];
+            const float diff = v - J->y_obs[k];
+            d2.add(diff * diff);
+            sum.add(v);
+        }
+        const float dist = static_cast<float>(sqrt(d2.value()));
+        const double stat = sum.value() / static_cast<double>(ns);
+        if (tid == 0) {
+            if (flags & JOB_WRITE_DIST)
+                J->dist[q] = dist;
+            if ((flags & JOB_DUMP) && J->dump_stat)
+                J->dump_stat[q] = static_cast<float>(stat);
+            if ((flags & JOB_DUMP) && J->dump_dist)
+                J->dump_dist[q] = dist;
+            if ((flags & JOB_TALLY_STAT) && stat >= J->t_obs)
+                atomicAdd(&J->counts[0], 1ull);
+        }
+        __syncthreads();
     }
 }
 
@@ -1007,7 +1217,7 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *
                 if (acc) {
                     const uint64_t pos = my_lt + (my_eq < quota ? my_eq : quota);
                     double theta[PPS_MAX_PARAMS];
-                    prior_draw(F->prior, np, F->constraint, key, F->first_draw + e, theta);
+                    prior_draw<PPS_MAX_PARAMS>(F->prior, np, F->constraint, key, F->first_draw + e, theta);
                     if (pos < F->capacity) {
                         F->acc_idx[pos] = F->first_draw + e;
                         F->acc_dist[pos] = d;
@@ -1136,6 +1346,16 @@ static SimKernel sim_kernel(int cls, const SimShape &sh)
         case 64: return sim_ptr<64, CLASS_GARCH, 1, 1>();
         case 128: return sim_ptr<128, CLASS_GARCH, 1, 1>();
         case 256: return sim_ptr<256, CLASS_GARCH, 1, 1>();
+        default: return nullptr;
+        }
+    }
+    if (cls == CLASS_CELLS) {
+        if (sh.dpl != 1 || sh.unroll != 1)
+            return nullptr;
+        switch (sh.block) {
+        case 256: return k_simulate_cells<256>;
+        case 512: return k_simulate_cells<512>;
+        case 1024: return k_simulate_cells<1024>;
         default: return nullptr;
         }
     }

@@ -25,7 +25,7 @@ struct SimShape {
 // grid of the per-element finalisation kernels.
 struct EpochShape {
     SimShape sim[N_CLASSES];
-    unsigned sim_grid[N_CLASSES] = {0, 0, 0};
+    unsigned sim_grid[N_CLASSES] = {};
     unsigned fin_grid = 0;
     bool operator==(const EpochShape &o) const
     {

@@ -94,7 +94,14 @@ Context *current_context(int *status)
     return g_contexts[dev];
 }
 
-int model_class(const pps_model *m) { return m->model == PPS_GARCH11 ? CLASS_GARCH : CLASS_PATH; }
+int model_class(const pps_model *m)
+{
+    if (m->model == PPS_GARCH11)
+        return CLASS_GARCH;
+    if (m->model == PPS_TOGGLE_SWITCH)
+        return CLASS_CELLS;
+    return CLASS_PATH;
+}
 
 static bool finite(double v) { return std::isfinite(v); }
 
@@ -158,6 +165,24 @@ int validate_model(const pps_model *m, int *n_summ)
                         m->steps);
         *n_summ = PPS_GARCH_NSUMM;
         return PPS_OK;
+    case PPS_TOGGLE_SWITCH:
+        if (m->n_params != 7)
+            return fail(PPS_EINVAL, "toggle switch needs 7 parameters "
+                                    "(mu, sigma, gamma, alpha_u, alpha_v, beta_u, beta_v)");
+        if (m->n_cells < 1 || m->n_cells > PPS_TSW_MAX_CELLS)
+            return fail(PPS_EINVAL, "n_cells %d out of range [1, %d]", m->n_cells,
+                        PPS_TSW_MAX_CELLS);
+        if (m->n_obs < 1 || m->n_obs > PPS_MAX_OBS)
+            return fail(PPS_EINVAL, "n_obs (quantiles) %d out of range [1, %d]", m->n_obs,
+                        PPS_MAX_OBS);
+        if (m->steps < 1)
+            return fail(PPS_EINVAL, "toggle switch needs steps >= 1");
+        if (!finite(m->t_end) || !(m->t_end > 0.0) || !finite(m->x0))
+            return fail(PPS_EINVAL, "toggle switch needs finite t_end > 0 and x0");
+        if (m->constraint != PPS_NO_CONSTRAINT)
+            return fail(PPS_EINVAL, "constraint only applies to GARCH");
+        *n_summ = m->n_obs;
+        return PPS_OK;
     default:
         return fail(PPS_EINVAL, "unknown model %d", m->model);
     }
@@ -189,6 +214,11 @@ void fill_job(JobDev &J, const pps_model *m, const pps_sampling *s, int n_summ, 
     } else if (m->model == PPS_GARCH11) {
         J.steps = m->steps;
         J.obs_stride = 1;
+    } else if (m->model == PPS_TOGGLE_SWITCH) {
+        J.steps = m->steps;
+        J.obs_stride = 1;
+        J.dt = m->t_end / static_cast<double>(m->steps);
+        J.n_cells = m->n_cells;
     } else {
         J.steps = m->n_obs;
         J.obs_stride = 1;

@@ -133,7 +133,7 @@ static int validate_job(const pps_job *j, int *n_summ)
         return rc;
     if ((rc = validate_sampling(&j->sampling)) != PPS_OK)
         return rc;
-    if (j->model.model == PPS_GARCH11)
+    if (j->model.model != PPS_LOGISTIC_SDE && j->model.model != PPS_NORMAL_MEAN)
         return fail(PPS_EINVAL, "jobs run the logistic SDE or normal-mean models");
     if (j->kind == PPS_JOB_ABC)
         return validate_abc(&j->model, j->y_obs, *n_summ, &j->sampling, j->eps_mode,
@@ -615,7 +615,8 @@ int pps_run_batch(const pps_job *jobs, int n_jobs, const pps_server_config *conf
             return rc;
         c->batch_engine = std::move(e);
     }
-    c->batch_engine->set_shape(CLASS_PATH, c->engine->shape(CLASS_PATH));
+    for (int cls = 0; cls < N_CLASSES; ++cls)
+        c->batch_engine->set_shape(cls, c->engine->shape(cls));
     Scheduler sched;
     sched.init(*config, c->batch_engine.get(), static_cast<hipStream_t>(config->stream), true);
     for (int i = 0; i < n_jobs; ++i)
@@ -655,7 +656,8 @@ int pps_server_create(const pps_server_config *config, pps_server **server)
         return rc;
     {
         std::lock_guard<std::mutex> lk(c->mu);
-        s->engine->set_shape(CLASS_PATH, c->engine->shape(CLASS_PATH));
+        for (int cls = 0; cls < N_CLASSES; ++cls)
+            s->engine->set_shape(cls, c->engine->shape(cls));
     }
     s->sched.init(*config, s->engine.get(), stream, false);
     pps_server *raw = s.get();

@@ -6,6 +6,10 @@ prior-predictive simulation at a fixed theta (point priors), seed 0, draw 0:
 * logistic SDE, theta = (1, 100, 0.2), X0 = 10, T = 10, S = 1000, observed at
   steps 50, 100, ..., 1000 -> ``y_obs`` (20 values) and ``t_obs`` = their mean;
 * GARCH(1,1), theta = (5e-5, 0.1, 0.85), L = 2000 -> the 14 summaries;
+* genetic toggle switch, theta = (320, 0.25, 0.15, 22, 12, 4, 4.5), C = 8000
+  cells, 599 Euler-Maruyama steps of dt = 1 (T = 600 time points), x0 = 10
+  -> the 19 quantile summaries ``y_obs`` and ``t_obs`` = their mean (the
+  paper's measured cells are not available; this stands in for them);
 * the fixed tolerance of the 1e7-draw ABC workload: the 0.1% distance
   quantile of the oracle's pilot on draws [0, 1e5) of the sampling seed
   (the 100th smallest distance, type-1 inverse empirical CDF).
@@ -48,6 +52,13 @@ def main():
     gs = oracle.simulate(gspec, W.OBS_SEED, W.OBS_DRAW, 1)
     out["garch_L2000"] = {"theta": list(W.GARCH_THETA_OBS), "seed": W.OBS_SEED,
                           "draw": W.OBS_DRAW, "summaries": [float(v) for v in gs["summ"][0]]}
+    tspec = W.toggle_point_spec()
+    ts = oracle.simulate(tspec, W.OBS_SEED, W.OBS_DRAW, 1)
+    out["toggle_C8000_T600"] = {"theta": list(W.TOGGLE_THETA_OBS), "seed": W.OBS_SEED,
+                                "draw": W.OBS_DRAW, "n_cells": tspec["n_cells"],
+                                "steps": tspec["steps"],
+                                "y_obs": [float(v) for v in ts["summ"][0]],
+                                "t_obs": float(ts["stat"][0])}
     path = os.path.join(HERE, "observed.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)

@@ -55,9 +55,9 @@ _LAYOUT_PROG = r"""
 #include "pps.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(pps_prior), sizeof(pps_model), sizeof(pps_sampling), sizeof(pps_abc_stats));
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(pps_model, prior), offsetof(pps_model, constraint),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", offsetof(pps_model, prior), offsetof(pps_model, constraint),
          offsetof(pps_model, x0), offsetof(pps_model, t_end), offsetof(pps_model, steps),
-         offsetof(pps_model, n_obs), offsetof(pps_model, noise_sd));
+         offsetof(pps_model, n_obs), offsetof(pps_model, noise_sd), offsetof(pps_model, n_cells));
   printf("%zu %zu %zu\n", offsetof(pps_abc_stats, eps_used), offsetof(pps_abc_stats, mean), offsetof(pps_abc_stats, var));
   printf("%zu %zu %zu %zu\n", sizeof(pps_job), sizeof(pps_job_result), sizeof(pps_server_config), sizeof(pps_server_stats));
   printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", offsetof(pps_job, model), offsetof(pps_job, sampling), offsetof(pps_job, y_obs),
@@ -84,7 +84,7 @@ def test_struct_layout_matches_binding(P):
                      ctypes.sizeof(B.pps_sampling), ctypes.sizeof(B.pps_abc_stats)]
     offs = [int(v) for v in lines[1].split()]
     assert offs == [getattr(B.pps_model, f).offset for f in
-                    ("prior", "constraint", "x0", "t_end", "steps", "n_obs", "noise_sd")]
+                    ("prior", "constraint", "x0", "t_end", "steps", "n_obs", "noise_sd", "n_cells")]
     offs2 = [int(v) for v in lines[2].split()]
     assert offs2 == [getattr(B.pps_abc_stats, f).offset for f in ("eps_used", "mean", "var")]
     assert [int(v) for v in lines[3].split()] == [ctypes.sizeof(B.pps_job), ctypes.sizeof(B.pps_job_result),
@@ -104,9 +104,18 @@ def test_validation_without_device(P):
     assert P.pps_n_summaries(W.logistic_spec()) == 20
     assert P.pps_n_summaries(W.garch_spec()) == 14
     assert P.pps_n_summaries(W.normal_mean_spec(n_obs=7)) == 7
+    assert P.pps_n_summaries(W.toggle_spec()) == 19
+    assert P.pps_n_summaries(W.toggle_spec(n_cells=P.PPS_TSW_MAX_CELLS, n_quantiles=64, steps=1)) == 64
+    tsw_six = W.toggle_spec()
+    tsw_six["priors"] = tsw_six["priors"][:6]
+    tsw_constrained = W.toggle_spec()
+    tsw_constrained["constraint"] = "garch_stationary"
     bad = [W.logistic_spec(steps=999), W.logistic_spec(n_obs=0), W.logistic_spec(n_obs=65, steps=65),
            W.garch_spec(series_len=1990), W.logistic_spec(theta1=("uniform", 2.0, 1.0)),
-           W.logistic_spec(theta1=("normal", 0.0, -1.0)), W.logistic_spec(t_end=-1.0)]
+           W.logistic_spec(theta1=("normal", 0.0, -1.0)), W.logistic_spec(t_end=-1.0),
+           W.toggle_spec(n_cells=0), W.toggle_spec(n_cells=P.PPS_TSW_MAX_CELLS + 1),
+           W.toggle_spec(n_quantiles=0), W.toggle_spec(n_quantiles=65), W.toggle_spec(steps=0),
+           W.toggle_spec(dt=-1.0), tsw_six, tsw_constrained]
     for spec in bad:
         assert L.pps_n_summaries(ctypes.byref(P.make_model(spec))) == P.PPS_EINVAL
         assert L.pps_last_error()
