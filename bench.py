@@ -72,6 +72,23 @@ GARCH_OPS_PER_STEP = 43.8
 GARCH_OPS_PER_DRAW_FIXED = 600
 
 
+# Toggle switch (Sec. 3.2), per cell-step: half a Philox call (30), one
+# Box-Muller pair for (xi_u, xi_v) (12), and per gene the power
+# exp2(beta log2 level) (3), the Hill factor 1 / (1 + p) (2), the drift
+# and noise updates and the boundary (5) = 62; per cell the measurement
+# (power, scale, two adds, boundary: 7), half a pair for eta (6) and a
+# linear-time share of the quantile selection (2); per draw the 7 prior
+# values (~600).  The LDS bitonic sort that does the selection is not
+# counted beyond that linear share.
+TSW_OPS_PER_CELL_STEP = 62
+TSW_OPS_PER_CELL = 15
+TSW_OPS_PER_DRAW = 600
+
+
+def toggle_ops_per_draw(n_cells: int, steps: int) -> float:
+    return n_cells * (steps * TSW_OPS_PER_CELL_STEP + TSW_OPS_PER_CELL) + TSW_OPS_PER_DRAW
+
+
 def kernel_source_digest() -> str:
     """sha256 of the device sources; HBM traffic taken from the PMC counters is
     reported only while it matches the digest recorded with them."""
@@ -189,12 +206,14 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="draws of the oracle's timed sample (0 disables the CPU baseline)")
     ap.add_argument("--only-main", action="store_true",
-                    help="skip the p-value batch, GARCH and serving workloads")
+                    help="skip the p-value batch, GARCH, toggle-switch and serving workloads")
     ap.add_argument("--serving-jobs", type=int, default=2000,
                     help="jobs of the serving mix (0 skips it)")
     ap.add_argument("--launch-shape", default="",
                     help="block,draws_per_lane,unroll of the simulation kernel instead of autotuning "
                          "(profiling runs pin the shape so that every run times the same kernel)")
+    ap.add_argument("--cell-block", type=int, default=0,
+                    help="workgroup size of the toggle-switch kernel instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -316,6 +335,44 @@ def main():
             "valu_frac": round(gops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
             "kernel": "k_simulate<256,garch>",
             "traffic": measured_traffic("k_simulate_garch_L2000_n1e6")}
+        # The paper's own prior-predictive run (Sec. 3.2, Table A.1): the
+        # genetic toggle switch, N = 8064 draws x 8000 cells x 599 steps,
+        # each draw reduced to 19 quantiles; ABC keeps the closest 1 %.
+        tspec = W.toggle_spec()
+        tn, tc, ts = W.TOGGLE_PPS["n"], W.TOGGLE_PPS["n_cells"], W.TOGGLE_PPS["steps"]
+        ty = np.array(golden["toggle_C8000_T600"]["y_obs"])
+        tcap = 128
+        tidx = torch.empty(tcap, dtype=torch.int64, device="cuda")
+        tth = torch.empty((7, tcap), dtype=torch.float32, device="cuda")
+        tdd = torch.empty(tcap, dtype=torch.float32, device="cuda")
+        if args.cell_block:
+            P.pps_set_launch_shape(P.CLASS_CELLS, args.cell_block, 1, 1)
+            cell_block = args.cell_block
+        else:
+            cell_block = P.pps_autotune(tspec, 2048, use_cache=True)["best"][0]
+        print(f"bench: toggle switch {tn} x {tc} cells x {ts} steps (block {cell_block})",
+              file=sys.stderr, flush=True)
+        tsamp = P.make_sampling(tn, 0, W.SAMPLING_SEED)
+        wall, kms = time_calls(P, torch, lambda: P.abc_sample(
+            tspec, ty, tsamp, P.PPS_EPS_TOP_FRACTION, 0.01, tcap, tidx, tth, tdd), 1, 3)
+        tops = toggle_ops_per_draw(tc, ts) * tn
+        tw = {"sims_per_s": round(tn / wall, 1), "cell_steps_per_s": round(tn * tc * ts / wall, 1),
+              "ms": round(wall * 1e3, 3), "kernel_ms": round(kms, 3),
+              "valu_frac": round(tops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
+              "kernel": f"k_simulate_cells<{cell_block}>",
+              "traffic": measured_traffic("k_simulate_cells_toggle_n8064"),
+              "paper_context": {"table": "A.1", "seconds": 69.0, "cpu": "Xeon Gold 6140",
+                                "threads": 16, "code": "C, AVX512, FP64",
+                                "ratio_to_gpu": round(69.0 / wall, 1)}}
+        if args.cpu_sample > 0:
+            import oracle
+            tns = 32
+            c0 = time.perf_counter()
+            oracle.simulate(tspec, W.SAMPLING_SEED, 0, tns, y_obs=ty)
+            c1 = time.perf_counter()
+            tw["oracle"] = {"sims_per_s": round(tns / (c1 - c0), 3), "cores": oracle.threads(),
+                            "sample": f"draws [0, {tns}), simulation and summaries (FP64)"}
+        workloads["toggle_switch_C8000_T600_n8064"] = tw
         if args.serving_jobs > 0:
             workloads["serving_mix"] = serving_bench(P, torch, W, golden, args.serving_jobs,
                                                      W.SERVING_MIX["rate_hz"])
