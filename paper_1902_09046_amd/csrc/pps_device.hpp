@@ -17,11 +17,19 @@ namespace pps {
 // The key is the seed and is wave-uniform, so its schedule lives in SGPRs.
 // Each widening product is written as one 64-bit multiply, which gfx950
 // issues as a single v_mad_u64_u32 (both halves at once; measured 18 % faster
-// for the whole simulation than separate v_mul_hi_u32 / v_mul_lo_u32).
+// for the whole simulation than separate v_mul_hi_u32 / v_mul_lo_u32).  The
+// three-way xors of rounds 1..9 (all operands per lane but the key) are one
+// gfx950 v_bitop3_b32 each (truth table 0x96 = a ^ b ^ c); round 0, whose
+// counter words 1 and 3 are often wave-uniform, is left to the compiler.
 // ---------------------------------------------------------------------------
 struct Words4 {
     uint32_t x, y, z, w;
 };
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1)
@@ -32,9 +40,14 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
         const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
         const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
         const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
-        c0 = hi1 ^ c1 ^ k0;
+        if (r == 0) {
+            c0 = hi1 ^ c1 ^ k0;
+            c2 = hi0 ^ c3 ^ k1;
+        } else {
+            c0 = xor3(hi1, c1, k0);
+            c2 = xor3(hi0, c3, k1);
+        }
         c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
         c3 = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
