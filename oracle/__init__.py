@@ -21,6 +21,10 @@ Each function follows one passage of the paper:
   hyperparameter grid (Eqs. pppv, pppvhype), using a tail-area statistic.
 * ``summary_tally`` -- per-summary tail areas (the GARCH and toggle-switch
   checks).
+* ``bio_simulate`` / ``bio_loglik`` / ``smc_log_evidence`` / ``wip_test`` --
+  the weak-informativity test of Sec. 4.1 (Alg. 2) with the evidence of the
+  logistic dose-response model (Eq. bioassay) estimated by the adaptive SMC
+  sampler of Alg. 3 (``wip_oracle.c``).
 * ``toggle_cells`` -- every cell of one draw of the genetic toggle switch
   (Sec. 3.2, Eqs. gene_uv_SDE, gene_uv_SDE_EM and gene_u_obs), for checks of
   its dynamics, measurement model and quantile summaries.
@@ -35,7 +39,7 @@ from typing import Mapping, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "pps_oracle.c")
+_SRCS = [os.path.join(_HERE, "pps_oracle.c"), os.path.join(_HERE, "wip_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 UNIFORM, NORMAL, LOGNORMAL, POINT = 0, 1, 2, 3
@@ -55,7 +59,7 @@ def build(force: bool = True) -> str:
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp"
     subprocess.run(
-        ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-Wall", _SRC, "-o", tmp, "-lm"],
+        ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-Wall", *_SRCS, "-o", tmp, "-lm"],
         check=True,
     )
     os.replace(tmp, _LIB_PATH)
@@ -80,6 +84,20 @@ class _Model(ctypes.Structure):
         ("n_cells", ctypes.c_int32),
     ]
 
+
+class _Bioassay(ctypes.Structure):
+    _fields_ = [("n_groups", ctypes.c_int32), ("n_trials", ctypes.c_int32 * 8),
+                ("dose", ctypes.c_double * 8)]
+
+
+class _SmcConfig(ctypes.Structure):
+    _fields_ = [("n_particles", ctypes.c_int32), ("max_mcmc", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("bisect_iters", ctypes.c_int32),
+                ("c", ctypes.c_double), ("h", ctypes.c_double)]
+
+
+# stream purposes of the weak-informativity test (counter word 1)
+P_DATA_BASE, P_DATA_K = 0x40000000, 0x40000001
 
 _lib = None
 
@@ -134,6 +152,26 @@ def _load():
         lib.or_distance.argtypes = [f64p, f64p, ctypes.c_int]
         lib.or_distance.restype = ctypes.c_double
         lib.or_max_threads.restype = ctypes.c_int
+        bp, cp = ctypes.POINTER(_Bioassay), ctypes.POINTER(_SmcConfig)
+        lib.or_bio_simulate.argtypes = [bp, f64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                        i32p, f64p]
+        lib.or_bio_loglik.argtypes = [bp, i32p, ctypes.c_double, ctypes.c_double]
+        lib.or_bio_loglik.restype = ctypes.c_double
+        lib.or_bio_logprior.argtypes = [f64p, ctypes.c_double, ctypes.c_double]
+        lib.or_bio_logprior.restype = ctypes.c_double
+        lib.or_smc_log_evidence.argtypes = [bp, i32p, f64p, cp, ctypes.c_uint64, ctypes.c_uint64,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]
+        lib.or_smc_log_evidence.restype = ctypes.c_double
+        lib.or_wip_test.argtypes = [bp, f64p, ctypes.c_int, ctypes.c_uint64, cp, ctypes.c_uint64,
+                                    ctypes.c_double, f64p, f64p, f64p, f64p]
+        lib.or_wip_test.restype = ctypes.c_int
+        lib.or_smc_temper.argtypes = [f64p, ctypes.c_int, ctypes.c_double, ctypes.c_int, cp]
+        lib.or_smc_temper.restype = ctypes.c_double
+        lib.or_smc_resample.argtypes = [f64p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_uint32, i32p]
+        lib.or_smc_proposal.argtypes = [f64p, f64p, ctypes.c_int, ctypes.c_double, f64p]
+        lib.or_smc_moves.argtypes = [ctypes.c_int, ctypes.c_int, cp]
+        lib.or_smc_moves.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -319,3 +357,94 @@ def distance(x, y) -> float:
     x = np.ascontiguousarray(x, np.float64)
     y = np.ascontiguousarray(y, np.float64)
     return float(_load().or_distance(x, y, len(x)))
+
+
+def _bioassay(spec: Mapping) -> _Bioassay:
+    b = _Bioassay()
+    b.n_groups = len(spec["dose"])
+    for i, (n, x) in enumerate(zip(spec["n_trials"], spec["dose"])):
+        b.n_trials[i] = int(n)
+        b.dose[i] = float(x)
+    return b
+
+
+def _smc(cfg: Mapping) -> _SmcConfig:
+    c = _SmcConfig()
+    c.n_particles = int(cfg["n_particles"])
+    c.max_mcmc = int(cfg["max_mcmc"])
+    c.max_steps = int(cfg["max_steps"])
+    c.bisect_iters = int(cfg["bisect_iters"])
+    c.c = float(cfg["c"])
+    c.h = float(cfg["h"])
+    return c
+
+
+def bio_simulate(spec: Mapping, lam, seed: int, data_id: int, purpose: int) -> tuple[np.ndarray, np.ndarray]:
+    """One data set D ~ p(D | lambda): (y per group, theta)."""
+    y = np.zeros(len(spec["dose"]), np.int32)
+    th = np.zeros(2, np.float64)
+    _load().or_bio_simulate(ctypes.byref(_bioassay(spec)), np.ascontiguousarray(lam, np.float64),
+                            seed, data_id, purpose, y, th)
+    return y, th
+
+
+def bio_loglik(spec: Mapping, y, b0: float, b1: float) -> float:
+    return float(_load().or_bio_loglik(ctypes.byref(_bioassay(spec)),
+                                       np.ascontiguousarray(y, np.int32), b0, b1))
+
+
+def bio_logprior(lam, b0: float, b1: float) -> float:
+    return float(_load().or_bio_logprior(np.ascontiguousarray(lam, np.float64), b0, b1))
+
+
+def smc_log_evidence(spec: Mapping, y, lam, cfg: Mapping, seed: int, run: int) -> dict:
+    """Alg. 3 for log p(D | lambda); trace rows (t_n, delta_n, p_acc_n, R_n)."""
+    c = _smc(cfg)
+    trace = np.zeros((c.max_steps, 4), np.float64)
+    n = ctypes.c_int32()
+    lz = _load().or_smc_log_evidence(ctypes.byref(_bioassay(spec)), np.ascontiguousarray(y, np.int32),
+                                     np.ascontiguousarray(lam, np.float64), ctypes.byref(c), seed,
+                                     run, ctypes.byref(n), trace.ctypes.data)
+    return {"log_z": float(lz), "n_steps": int(n.value), "trace": trace[: n.value]}
+
+
+def wip_test(spec: Mapping, lambdas, n_data: int, cfg: Mapping, seed: int, alpha: float) -> dict:
+    """Alg. 2: log evidences, p-values and alpha cut-offs per lambda (row 0 =
+    the base prior)."""
+    lam = np.ascontiguousarray(lambdas, np.float64).reshape(-1, 2)
+    k = lam.shape[0]
+    lz0 = np.zeros((k, n_data), np.float64)
+    lzk = np.zeros((k, n_data), np.float64)
+    pv = np.zeros((k, n_data), np.float64)
+    gamma = np.zeros(k, np.float64)
+    rc = _load().or_wip_test(ctypes.byref(_bioassay(spec)), lam, k, n_data, ctypes.byref(_smc(cfg)),
+                             seed, alpha, lz0, lzk, pv, gamma)
+    if rc != 0:
+        raise ValueError("oracle: invalid weak-informativity input")
+    return {"log_z0": lz0, "log_zk": lzk, "pvalues": pv, "gamma": gamma}
+
+
+def smc_temper(ll, t: float, step: int, cfg: Mapping) -> float:
+    """Tempering increment of one SMC step (the ESS = N_p / 2 condition)."""
+    ll = np.ascontiguousarray(ll, np.float64)
+    return float(_load().or_smc_temper(ll, len(ll), t, step, ctypes.byref(_smc(cfg))))
+
+
+def smc_resample(w, seed: int, run: int, step: int) -> np.ndarray:
+    """Ancestors of a multinomial resampling step with weights w (max 1)."""
+    w = np.ascontiguousarray(w, np.float64)
+    anc = np.zeros(len(w), np.int32)
+    _load().or_smc_resample(w, len(w), seed, run, step, anc)
+    return anc
+
+
+def smc_proposal(b0, b1, h: float) -> np.ndarray:
+    """(l11, l21, l22): the Cholesky factor of h^2 times the sample covariance."""
+    out = np.zeros(3, np.float64)
+    b0 = np.ascontiguousarray(b0, np.float64)
+    _load().or_smc_proposal(b0, np.ascontiguousarray(b1, np.float64), len(b0), h, out)
+    return out
+
+
+def smc_moves(accepted: int, n_particles: int, cfg: Mapping) -> int:
+    return int(_load().or_smc_moves(accepted, n_particles, ctypes.byref(_smc(cfg))))

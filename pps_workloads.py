@@ -93,6 +93,32 @@ def toggle_point_spec(theta=TOGGLE_THETA_OBS, **kw) -> dict:
     return toggle_spec(priors=[("point", float(t), 0.0) for t in theta], **kw)
 
 
+# Weak-informativity test (Sec. 4.1): the logistic dose-response model of
+# Eq. bioassay with the design printed in the paper (M = 4 groups of 5
+# animals; the dose of group 4 is used as printed), prior N(0, diag(lambda)^2),
+# base lambda_0 = (10, 2.5), K hyperparameters lambda_k ~ U([0.1,10] x
+# [0.1,20]), N data sets per hyperparameter, and the SMC settings of the paper
+# (N_p = 500, c = 0.01, h = 2.38/sqrt(2)).  alpha (the conflict level) is not
+# printed in the paper; 0.05 is used.
+BIOASSAY = {"n_trials": [5, 5, 5, 5], "dose": [-0.86, -0.3, -0.05, -0.75]}
+WIP_LAMBDA0 = (10.0, 2.5)
+WIP_ALPHA = 0.05
+SMC_CONFIG = {"n_particles": 500, "max_mcmc": 100, "max_steps": 100, "bisect_iters": 50,
+              "c": 0.01, "h": 2.38 / math.sqrt(2.0)}
+WIP_TEST = {"name": "wip_bioassay_K400_N400_Np500", "n_lambda": 400, "n_data": 400, "seed": 11}
+
+
+def wip_lambdas(k: int = 400, seed: int = 11) -> np.ndarray:
+    """Rows: lambda_0 (the base prior), then k hyperparameters drawn uniformly
+    on [0.1, 10] x [0.1, 20] (the paper's benchmark design)."""
+    rng = np.random.default_rng(seed)
+    lam = np.empty((k + 1, 2))
+    lam[0] = WIP_LAMBDA0
+    lam[1:, 0] = rng.uniform(0.1, 10.0, size=k)
+    lam[1:, 1] = rng.uniform(0.1, 20.0, size=k)
+    return lam
+
+
 def lambda_grid(n: int = 64, lo: float = 0.05, hi: float = 3.0) -> np.ndarray:
     """n log-spaced values from lo to hi (inclusive)."""
     k = np.arange(n, dtype=np.float64)
