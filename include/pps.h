@@ -318,6 +318,68 @@ int pps_server_stats_get(pps_server *server, pps_server_stats *stats);
  * are dropped.  The arena is not freed (it belongs to the caller). */
 int pps_server_destroy(pps_server *server);
 
+/* ---- weak-informativity test (Sec. 4.1: Alg. 2, evidence by Alg. 3) ---- */
+/* The logistic dose-response model of Eq. bioassay: group i of n_groups has
+ * n_trials[i] animals at dose x_i; y_i ~ Bin(n_trials[i], p_i) with
+ * p_i = 1 / (1 + exp(b0 + b1 x_i)); theta = (b0, b1) ~ N(0, diag(lambda)^2).
+ * The evidence p(D | lambda) is estimated in FP64 by the adaptive SMC
+ * sampler of Alg. 3, one sampler per workgroup with one particle per lane:
+ *   particles from the prior; per step the tempering increment with
+ *   ESS = N_p / 2 (bisection, bisect_iters halvings; the whole remaining
+ *   increment when it keeps ESS >= N_p / 2 or at step max_steps);
+ *   log Z += log((1/N_p) sum_i L_i^delta); multinomial resampling by
+ *   inversion of fixed-point weights floor(w 2^52) (exact integer prefix
+ *   sums); a random-walk proposal N(0, h^2 Sigma_hat) (Cholesky of the
+ *   particles' sample covariance); one trial Metropolis-Hastings move of
+ *   every particle gives p_acc, then R = ceil(ln c / ln(1 - p_acc)) moves in
+ *   all, clamped to [1, max_mcmc] (p_acc = 0: max_mcmc); until t = 1.
+ * Random numbers (key = seed, counter = (block, purpose, lo32, hi32 of the
+ * run or data-set index)): data sets purpose 0x40000000 (base prior, index i)
+ * or 0x40000001 (prior k, index k N + i), theta from words (0,1) of block 0,
+ * the trial uniforms in order from blocks 1, 2, ...; particle j of an SMC
+ * run: purpose 0x50000000 + j block 0 (initial draw), 0x60000000 + j block n
+ * (resampling), 0x70000000 + j block 256 n + r (move r of step n: words (0,1)
+ * the proposal normals, word 2 the acceptance uniform). */
+#define PPS_BIO_MAX_GROUPS 8
+#define PPS_SMC_MAX_PARTICLES 1024
+
+typedef struct {
+    int32_t n_groups;                     /* 1..PPS_BIO_MAX_GROUPS */
+    int32_t n_trials[PPS_BIO_MAX_GROUPS]; /* 0..1000 each */
+    double dose[PPS_BIO_MAX_GROUPS];
+} pps_bioassay;
+
+typedef struct {
+    int32_t n_particles;  /* N_p: 2..PPS_SMC_MAX_PARTICLES */
+    int32_t max_mcmc;     /* 1..256 */
+    int32_t max_steps;    /* 1..4096 */
+    int32_t bisect_iters; /* 1..64 */
+    double c;             /* in (0, 1) */
+    double h;             /* > 0 */
+} pps_smc_config;
+
+/* log p(D_s | lambda_s) for s < n_sets: data y (host, n_sets x n_groups
+ * counts), lambda (host, n_sets x 2), SMC run index first_run + s.
+ * log_z: device, n_sets doubles.  Errors: PPS_EINVAL. */
+int pps_smc_log_evidence(const pps_bioassay *model, const int32_t *y, const double *lambda,
+                         uint64_t n_sets, const pps_smc_config *smc, uint64_t seed,
+                         uint64_t first_run, double *log_z, void *stream);
+
+/* The weak-informativity test of Alg. 2 for lambda_0 (row 0 of `lambda`, the
+ * base prior) and lambda_1..lambda_{n_lambda-1}: N = n_data base data sets
+ * D_0^(i) ~ p(D | lambda_0) (shared by every k) and N data sets D_k^(i) ~
+ * p(D | lambda_k) per k; log pi_0^i = log p(D_0^(i) | lambda_k) (SMC run
+ * (k N + i) 2) and log pi_k^i = log p(D_k^(i) | lambda_k) (run (k N + i) 2 + 1);
+ * p_k^i = (1/N) #{j : pi_k^j <= pi_0^i}; gamma[k] = the ceil(alpha N)-th
+ * smallest p_k^i (the alpha quantile).  Priors with gamma[k] > gamma[0] are
+ * weakly informative with respect to the base (Eq. weakinfprior).
+ * lambda: host, n_lambda x 2 (> 0); log_z0, log_zk, pvalues: device,
+ * n_lambda x n_data doubles (pvalues may be NULL); gamma: host, n_lambda.
+ * n_data: 1..65536.  Errors: PPS_EINVAL, PPS_ENOMEM, PPS_EDEVICE. */
+int pps_wip_test(const pps_bioassay *model, const double *lambda, int n_lambda, uint64_t n_data,
+                 const pps_smc_config *smc, uint64_t seed, double alpha, double *log_z0,
+                 double *log_zk, double *pvalues, double *gamma, void *stream);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Kernel timing.  While enabled (process-wide; off by default) every call

@@ -6,7 +6,8 @@ rejection (Alg. 1) and prior-predictive p-values over a hyperparameter grid
 (Sec. 4.1), one lane per prior draw (one workgroup per draw for the paper's
 toggle-switch model, Sec. 3.2), counter-based Philox streams keyed by (seed,
 draw), FP32 simulation with compensated summaries, FP64 tallies and
-moments.  The kernels and runtime live in ``libpps.so`` (C ABI in
+moments; and the weak-informativity test of Sec. 4.1 (Alg. 2) with one FP64
+adaptive SMC evidence sampler (Alg. 3) per workgroup.  The kernels and runtime live in ``libpps.so`` (C ABI in
 ``include/pps.h``); this package is its thin ctypes binding.
 """
 from ._pps import (  # noqa: F401
@@ -23,4 +24,6 @@ from ._pps import (  # noqa: F401
     pps_job, pps_job_result, pps_server_config, pps_server_stats,
     make_abc_job, make_pvalue_job, make_server_config, pps_job_arena_bytes, pps_run_batch,
     Server, records, pps_autotune,
+    PPS_BIO_MAX_GROUPS, PPS_SMC_MAX_PARTICLES, pps_bioassay, pps_smc_config, make_bioassay,
+    make_smc_config, pps_smc_log_evidence, pps_wip_test,
 )

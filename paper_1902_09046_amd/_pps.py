@@ -138,6 +138,20 @@ class pps_tune_report(ctypes.Structure):
                 ("from_cache", ctypes.c_int32)]
 
 
+PPS_BIO_MAX_GROUPS, PPS_SMC_MAX_PARTICLES = 8, 1024
+
+
+class pps_bioassay(ctypes.Structure):
+    _fields_ = [("n_groups", ctypes.c_int32), ("n_trials", ctypes.c_int32 * PPS_BIO_MAX_GROUPS),
+                ("dose", ctypes.c_double * PPS_BIO_MAX_GROUPS)]
+
+
+class pps_smc_config(ctypes.Structure):
+    _fields_ = [("n_particles", ctypes.c_int32), ("max_mcmc", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("bisect_iters", ctypes.c_int32),
+                ("c", ctypes.c_double), ("h", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -187,6 +201,11 @@ def lib():
         L.pps_server_destroy.argtypes = [vp]
         L.pps_autotune.argtypes = [mp, u64, ctypes.c_int, ctypes.POINTER(pps_tune_report), vp]
         L.pps_autotune.restype = ctypes.c_int
+        bp, scp = ctypes.POINTER(pps_bioassay), ctypes.POINTER(pps_smc_config)
+        L.pps_smc_log_evidence.argtypes = [bp, vp, vp, u64, scp, u64, u64, vp, vp]
+        L.pps_smc_log_evidence.restype = ctypes.c_int
+        L.pps_wip_test.argtypes = [bp, vp, ctypes.c_int, u64, scp, u64, f64, vp, vp, vp, vp, vp]
+        L.pps_wip_test.restype = ctypes.c_int
         for name in ("pps_philox", "pps_normals", "pps_simulate", "pps_n_summaries", "abc_sample",
                      "prior_pred_pvalue", "pps_summary_tally", "pps_run_batch", "pps_server_create",
                      "pps_submit", "pps_poll", "pps_release", "pps_server_stats_get",
@@ -508,3 +527,60 @@ def records(result: pps_job_result, arena, n_params: int):
                    for j in range(n_params)])
     d = span(result.acc_dist, 4 * n).cpu().numpy().view(np.float32).copy()
     return idx, th, d
+
+
+
+# --------------------------------------------------------------------------
+# Weak-informativity test (Sec. 4.1): SMC evidence (Alg. 3) and Alg. 2.
+# --------------------------------------------------------------------------
+def make_bioassay(spec: Mapping) -> pps_bioassay:
+    """pps_bioassay from {"n_trials": [...], "dose": [...]}."""
+    b = pps_bioassay()
+    b.n_groups = len(spec["dose"])
+    for i, (n, x) in enumerate(zip(spec["n_trials"], spec["dose"])):
+        b.n_trials[i] = int(n)
+        b.dose[i] = float(x)
+    return b
+
+
+def make_smc_config(cfg: Mapping) -> pps_smc_config:
+    c = pps_smc_config()
+    c.n_particles = int(cfg["n_particles"])
+    c.max_mcmc = int(cfg["max_mcmc"])
+    c.max_steps = int(cfg["max_steps"])
+    c.bisect_iters = int(cfg["bisect_iters"])
+    c.c = float(cfg["c"])
+    c.h = float(cfg["h"])
+    return c
+
+
+def pps_smc_log_evidence(spec: Mapping, y, lambdas, cfg: Mapping, seed: int, first_run: int = 0,
+                         device="cuda", stream=None):
+    """log p(y_s | lambda_s) per set s (device FP64 tensor)."""
+    import torch
+    yy = np.ascontiguousarray(y, np.int32).reshape(-1, len(spec["dose"]))
+    lam = np.ascontiguousarray(lambdas, np.float64).reshape(-1, 2)
+    n = yy.shape[0]
+    assert lam.shape[0] == n
+    out = torch.empty(n, dtype=torch.float64, device=device)
+    _check(lib().pps_smc_log_evidence(ctypes.byref(make_bioassay(spec)), yy.ctypes.data,
+                                      lam.ctypes.data, n, ctypes.byref(make_smc_config(cfg)), seed,
+                                      first_run, int(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def pps_wip_test(spec: Mapping, lambdas, n_data: int, cfg: Mapping, seed: int, alpha: float,
+                 with_pvalues: bool = True, device="cuda", stream=None) -> dict:
+    """Alg. 2 over the rows of `lambdas` (row 0 = the base prior): device
+    tensors log_z0, log_zk (and pvalues), host array gamma."""
+    import torch
+    lam = np.ascontiguousarray(lambdas, np.float64).reshape(-1, 2)
+    k = lam.shape[0]
+    z0 = torch.empty((k, n_data), dtype=torch.float64, device=device)
+    zk = torch.empty((k, n_data), dtype=torch.float64, device=device)
+    pv = torch.empty((k, n_data), dtype=torch.float64, device=device) if with_pvalues else None
+    gamma = np.zeros(k, np.float64)
+    _check(lib().pps_wip_test(ctypes.byref(make_bioassay(spec)), lam.ctypes.data, k, n_data,
+                              ctypes.byref(make_smc_config(cfg)), seed, alpha, int(z0.data_ptr()),
+                              int(zk.data_ptr()), _ptr(pv), gamma.ctypes.data, _stream(stream)))
+    return {"log_z0": z0, "log_zk": zk, "pvalues": pv, "gamma": gamma}

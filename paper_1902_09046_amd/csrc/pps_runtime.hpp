@@ -38,6 +38,9 @@ struct Context {
     std::unique_ptr<EpochEngine> engine;        // synchronous calls (one slot)
     std::unique_ptr<EpochEngine> batch_engine;  // pps_run_batch (two slots)
     DevBuf dist, block_counts, partials, hist, results, counts;
+    // weak-informativity test: data sets, hyperparameters, tile counter,
+    // tally counts and cut-offs
+    DevBuf smc_y, smc_lam, smc_coef, smc_ctr, smc_counts, smc_gamma;
     double last_kernel_ms = -1.0;
 };
 

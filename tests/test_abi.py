@@ -66,6 +66,8 @@ int main(void) {
          offsetof(pps_job_result, n_records), offsetof(pps_job_result, record_stride), offsetof(pps_job_result, t_done));
   printf("%zu %zu %zu %zu\n", offsetof(pps_server_config, max_active), offsetof(pps_server_config, epoch_ms), offsetof(pps_server_config, policy),
          offsetof(pps_server_config, stream));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pps_bioassay), offsetof(pps_bioassay, dose), sizeof(pps_smc_config),
+         offsetof(pps_smc_config, bisect_iters), offsetof(pps_smc_config, c), offsetof(pps_smc_config, h));
   return 0;
 }
 """
@@ -96,6 +98,45 @@ def test_struct_layout_matches_binding(P):
         "abc", "count_ge", "acc_idx", "n_records", "record_stride", "t_done")]
     assert [int(v) for v in lines[6].split()] == [getattr(B.pps_server_config, f).offset for f in (
         "max_active", "epoch_ms", "policy", "stream")]
+    assert [int(v) for v in lines[7].split()] == [
+        ctypes.sizeof(B.pps_bioassay), B.pps_bioassay.dose.offset, ctypes.sizeof(B.pps_smc_config),
+        B.pps_smc_config.bisect_iters.offset, B.pps_smc_config.c.offset, B.pps_smc_config.h.offset]
+
+
+def test_wip_validation_without_device(P):
+    import pps_workloads as W
+    L = P.lib()
+    b = P.make_bioassay(W.BIOASSAY)
+    cfg = P.make_smc_config(W.SMC_CONFIG)
+    lam = np.array([[10.0, 2.5], [1.0, 1.0]])
+    g = np.zeros(2)
+
+    def call(b_, cfg_, lam_, n_lambda, n_data, alpha):
+        return L.pps_wip_test(ctypes.byref(b_), lam_.ctypes.data, n_lambda, n_data, ctypes.byref(cfg_),
+                              1, alpha, 1, 1, None, g.ctypes.data, None)
+    for field, bad in [("n_particles", 1), ("n_particles", 1025), ("max_mcmc", 0), ("max_mcmc", 257),
+                       ("bisect_iters", 0), ("max_steps", 0)]:
+        c2 = P.make_smc_config(W.SMC_CONFIG)
+        setattr(c2, field, bad)
+        assert call(b, c2, lam, 2, 10, 0.05) == P.PPS_EINVAL
+    for field, bad in [("c", 0.0), ("c", 1.0), ("h", 0.0), ("h", float("inf"))]:
+        c2 = P.make_smc_config(W.SMC_CONFIG)
+        setattr(c2, field, bad)
+        assert call(b, c2, lam, 2, 10, 0.05) == P.PPS_EINVAL
+    b2 = P.make_bioassay(W.BIOASSAY)
+    b2.n_groups = 9
+    assert call(b2, cfg, lam, 2, 10, 0.05) == P.PPS_EINVAL
+    b3 = P.make_bioassay(W.BIOASSAY)
+    b3.n_trials[1] = -1
+    assert call(b3, cfg, lam, 2, 10, 0.05) == P.PPS_EINVAL
+    assert call(b, cfg, lam, 0, 10, 0.05) == P.PPS_EINVAL
+    assert call(b, cfg, lam, 2, 0, 0.05) == P.PPS_EINVAL
+    assert call(b, cfg, lam, 2, 10, 0.0) == P.PPS_EINVAL
+    assert call(b, cfg, np.array([[10.0, 2.5], [1.0, -1.0]]), 2, 10, 0.05) == P.PPS_EINVAL
+    assert L.pps_last_error()
+    y_bad = np.array([[6, 0, 0, 0]], np.int32)
+    assert L.pps_smc_log_evidence(ctypes.byref(b), y_bad.ctypes.data, lam.ctypes.data, 1, ctypes.byref(cfg),
+                                  1, 0, 1, None) == P.PPS_EINVAL
 
 
 def test_validation_without_device(P):
