@@ -206,7 +206,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="draws of the oracle's timed sample (0 disables the CPU baseline)")
     ap.add_argument("--only-main", action="store_true",
-                    help="skip the p-value batch, GARCH, toggle-switch and serving workloads")
+                    help="skip the p-value batch, GARCH, toggle-switch, weak-informativity and "
+                         "serving workloads")
     ap.add_argument("--serving-jobs", type=int, default=2000,
                     help="jobs of the serving mix (0 skips it)")
     ap.add_argument("--launch-shape", default="",
@@ -373,6 +374,32 @@ def main():
             tw["oracle"] = {"sims_per_s": round(tns / (c1 - c0), 3), "cores": oracle.threads(),
                             "sample": f"draws [0, {tns}), simulation and summaries (FP64)"}
         workloads["toggle_switch_C8000_T600_n8064"] = tw
+        # The weak-informativity test (Sec. 4.1, Table A.2's run): K = 400
+        # hyperparameters plus the base, N = 400 data sets each, one adaptive
+        # SMC evidence sampler with N_p = 500 particles per data set and prior.
+        wlam = W.wip_lambdas(W.WIP_TEST["n_lambda"], seed=W.WIP_TEST["seed"])
+        wn = W.WIP_TEST["n_data"]
+        print(f"bench: weak-informativity test {wlam.shape[0]} x {wn} (N_p = "
+              f"{W.SMC_CONFIG['n_particles']})", file=sys.stderr, flush=True)
+        wall, kms = time_calls(P, torch, lambda: P.pps_wip_test(
+            W.BIOASSAY, wlam, wn, W.SMC_CONFIG, W.WIP_TEST["seed"], W.WIP_ALPHA), 1, 3)
+        runs = 2 * wlam.shape[0] * wn
+        ww = {"smc_runs_per_s": round(runs / wall, 1), "ms": round(wall * 1e3, 3),
+              "kernel_ms": round(kms, 3), "smc_runs": runs, "kernel": "k_smc<512> (FP64)",
+              "traffic": measured_traffic("k_smc_wip_K400_N400"),
+              "paper_context": {"table": "A.2", "seconds": 90.0, "cpu": "Xeon Gold 6140",
+                                "threads": 16, "code": "C, AVX512, FP64",
+                                "ratio_to_gpu": round(90.0 / wall, 1)}}
+        if args.cpu_sample > 0:
+            import oracle
+            sl, sn = wlam[:6], 200
+            c0 = time.perf_counter()
+            oracle.wip_test(W.BIOASSAY, sl, sn, W.SMC_CONFIG, W.WIP_TEST["seed"], W.WIP_ALPHA)
+            c1 = time.perf_counter()
+            ww["oracle"] = {"smc_runs_per_s": round(2 * 6 * sn / (c1 - c0), 1),
+                            "cores": oracle.threads(),
+                            "sample": f"6 priors x {sn} data sets (FP64, the same algorithm)"}
+        workloads["wip_bioassay_K400_N400_Np500"] = ww
         if args.serving_jobs > 0:
             workloads["serving_mix"] = serving_bench(P, torch, W, golden, args.serving_jobs,
                                                      W.SERVING_MIX["rate_hz"])
