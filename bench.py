@@ -94,7 +94,8 @@ def kernel_source_digest() -> str:
     reported only while it matches the digest recorded with them."""
     csrc = os.path.join(ROOT, "paper_1902_09046_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("pps_device.hpp", "pps_internal.hpp", "pps_kernels.hip"):
+    for name in ("pps_device.hpp", "pps_internal.hpp", "pps_kernels.hip", "pps_smc.hpp",
+                 "pps_smc.hip"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

@@ -44,6 +44,16 @@ __device__ __attribute__((noinline)) void box_muller_pair_f64(uint32_t w0, uint3
     z1 = r * s;
 }
 
+// A double known to be equal in every lane, moved to scalar registers (frees
+// the vector registers that the sampler's per-run constants would occupy).
+__device__ __forceinline__ double sgpr_f64(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 __device__ __forceinline__ uint32_t word_of(const Words4 &w, uint32_t k)
 {
     return k == 0 ? w.x : (k == 1 ? w.y : (k == 2 ? w.z : w.w));
@@ -101,7 +111,7 @@ __device__ __forceinline__ double wg_sum(double v, double *s_red)
     for (int w = 0; w < NW; ++w)
         tot += s_red[w];
     __syncthreads();
-    return tot;
+    return sgpr_f64(tot);
 }
 
 template <int BLOCK>
@@ -122,8 +132,8 @@ __device__ __forceinline__ void wg_sum2(double &a, double &b, double *s_red)
         tb += s_red[NW + w];
     }
     __syncthreads();
-    a = ta;
-    b = tb;
+    a = sgpr_f64(ta);
+    b = sgpr_f64(tb);
 }
 
 template <int BLOCK>
@@ -147,9 +157,9 @@ __device__ __forceinline__ void wg_sum3(double &a, double &b, double &c, double 
         tc += s_red[2 * NW + w];
     }
     __syncthreads();
-    a = ta;
-    b = tb;
-    c = tc;
+    a = sgpr_f64(ta);
+    b = sgpr_f64(tb);
+    c = sgpr_f64(tc);
 }
 
 template <int BLOCK>
@@ -165,7 +175,7 @@ __device__ __forceinline__ double wg_max(double v, double *s_red)
     for (int w = 1; w < NW; ++w)
         m = fmax(m, s_red[w]);
     __syncthreads();
-    return m;
+    return sgpr_f64(m);
 }
 
 template <int BLOCK>
@@ -251,6 +261,16 @@ __global__ void k_bio_data(BioDesign b, const double *__restrict__ lam, int n_la
                            uint64_t n_data, uint64_t seed, int32_t *__restrict__ y0,
                            int32_t *__restrict__ yk, double *__restrict__ lcoef)
 {
+    __shared__ double s_dose[PPS_BIO_MAX_GROUPS];
+    __shared__ int s_trials[PPS_BIO_MAX_GROUPS];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < PPS_BIO_MAX_GROUPS; ++j) {
+            s_dose[j] = b.dose[j];
+            s_trials[j] = b.n_trials[j];
+        }
+    }
+    __syncthreads();
     const StreamKey key = make_key(seed);
     const uint64_t total = n_data * (1 + static_cast<uint64_t>(n_lambda));
     const int m = b.n_groups;
@@ -282,16 +302,16 @@ __global__ void k_bio_data(BioDesign b, const double *__restrict__ lam, int n_la
         Words4 cur = w0;
         double lc = 0.0;
         for (int i = 0; i < m; ++i) {
-            const double p = 1.0 / (1.0 + exp(b0 + b1 * b.dose[i]));
+            const double p = 1.0 / (1.0 + exp(b0 + b1 * s_dose[i]));
             int32_t count = 0;
-            for (int r = 0; r < b.n_trials[i]; ++r, ++k) {
+            for (int r = 0; r < s_trials[i]; ++r, ++k) {
                 if ((k & 3) == 0)
                     cur = stream_block(key, id, 1 + (k >> 2), purpose);
                 if (uniform_f64(word_of(cur, k & 3)) < p)
                     ++count;
             }
             out[i] = count;
-            const double nn = b.n_trials[i], kk = count;
+            const double nn = s_trials[i], kk = count;
             lc += lgamma(nn + 1.0) - lgamma(kk + 1.0) - lgamma(nn - kk + 1.0);
         }
         lcoef[q] = lc;
@@ -352,15 +372,25 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             run = r;
             out = (base ? R.out0 : R.outk) + ki;
         }
-        const double l0 = lam[0], l1 = lam[1];
+        const double l0 = sgpr_f64(lam[0]), l1 = sgpr_f64(lam[1]);
         const int m = b.n_groups;
         if (tid < m) {
-            s_g.n[tid] = static_cast<double>(b.n_trials[tid]);
+            // static indices into the by-value design (a lane index would
+            // place the argument in scratch memory)
+            double nn = 0.0, xx = 0.0;
+#pragma unroll
+            for (int j = 0; j < PPS_BIO_MAX_GROUPS; ++j) {
+                if (j == tid) {
+                    nn = static_cast<double>(b.n_trials[j]);
+                    xx = b.dose[j];
+                }
+            }
+            s_g.n[tid] = nn;
             s_g.k[tid] = static_cast<double>(y[tid]);
-            s_g.x[tid] = b.dose[tid];
+            s_g.x[tid] = xx;
         }
         __syncthreads();
-        const double lcoef = *lc;
+        const double lcoef = sgpr_f64(*lc);
         // initial particles from the prior
         double b0 = 0.0, b1 = 0.0, ll = -INFINITY;
         if (live) {
@@ -394,10 +424,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             }
             const double w = live ? exp(delta * (ll - lmax)) : 0.0;
             const double sum_w = wg_sum<BLOCK>(w, s_red);
-            log_z += delta * lmax + log(sum_w / np);
+            log_z = sgpr_f64(log_z + (delta * lmax + log(sum_w / np)));
             if (delta == rest)
                 break;  // t = 1: the evidence is complete
-            t += delta;
+            t = sgpr_f64(t + delta);
             // multinomial resampling by inversion of fixed-point weights
             const uint64_t q = live ? static_cast<uint64_t>(floor(w * TWO_POW_52)) : 0ull;
             s_b0[tid] = b0;
@@ -435,10 +465,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             c01 /= (np - 1);
             c11 /= (np - 1);
             const double h2 = P.h * P.h;
-            const double f11 = c00 > 0.0 ? sqrt(h2 * c00) : 0.0;
-            const double f21 = c00 > 0.0 ? h2 * c01 / f11 : 0.0;
+            const double f11 = sgpr_f64(c00 > 0.0 ? sqrt(h2 * c00) : 0.0);
+            const double f21 = sgpr_f64(c00 > 0.0 ? h2 * c01 / f11 : 0.0);
             const double r22 = h2 * c11 - f21 * f21;
-            const double f22 = r22 > 0.0 ? sqrt(r22) : 0.0;
+            const double f22 = sgpr_f64(r22 > 0.0 ? sqrt(r22) : 0.0);
             // Metropolis-Hastings moves targeting L^t pi(theta | lambda)
             int moves = 1;
             for (int mv = 0; mv < moves; ++mv) {
