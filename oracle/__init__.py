@@ -25,6 +25,9 @@ Each function follows one passage of the paper:
   the weak-informativity test of Sec. 4.1 (Alg. 2) with the evidence of the
   logistic dose-response model (Eq. bioassay) estimated by the adaptive SMC
   sampler of Alg. 3 (``wip_oracle.c``).
+* ``gamma_p`` / ``bege_cdf`` / ``bege_density`` / ``bege_loglik`` -- the
+  log-likelihood of the BEGE volatility model (Sec. 4.2: Eqs. BEGE, shape,
+  BEGE_LL, CDF_BEGE, BEGE_LL_approx, incompGamma; ``bege_oracle.c``).
 * ``toggle_cells`` -- every cell of one draw of the genetic toggle switch
   (Sec. 3.2, Eqs. gene_uv_SDE, gene_uv_SDE_EM and gene_u_obs), for checks of
   its dynamics, measurement model and quantile summaries.
@@ -39,7 +42,8 @@ from typing import Mapping, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "pps_oracle.c"), os.path.join(_HERE, "wip_oracle.c")]
+_SRCS = [os.path.join(_HERE, "pps_oracle.c"), os.path.join(_HERE, "wip_oracle.c"),
+         os.path.join(_HERE, "bege_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 UNIFORM, NORMAL, LOGNORMAL, POINT = 0, 1, 2, 3
@@ -172,6 +176,20 @@ def _load():
         lib.or_smc_proposal.argtypes = [f64p, f64p, ctypes.c_int, ctypes.c_double, f64p]
         lib.or_smc_moves.argtypes = [ctypes.c_int, ctypes.c_int, cp]
         lib.or_smc_moves.restype = ctypes.c_int
+        lib.or_gamma_p.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.or_gamma_p.restype = ctypes.c_double
+        d5 = [ctypes.c_double] * 5
+        lib.or_bege_cdf.argtypes = d5 + [ctypes.c_int]
+        lib.or_bege_cdf.restype = ctypes.c_double
+        lib.or_bege_density.argtypes = d5 + [ctypes.c_int]
+        lib.or_bege_density.restype = ctypes.c_double
+        lib.or_bege_loglik.argtypes = [f64p, f64p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_double)]
+        lib.or_bege_loglik.restype = ctypes.c_int
+        lib.or_bege_loglik_batch.argtypes = [f64p, ctypes.c_int, f64p, ctypes.c_int, ctypes.c_int, f64p]
+        lib.or_bege_loglik_batch.restype = ctypes.c_int
+        lib.or_bege_simulate.argtypes = [f64p, ctypes.c_int, ctypes.c_uint64, f64p]
+        lib.or_bege_simulate.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -448,3 +466,44 @@ def smc_proposal(b0, b1, h: float) -> np.ndarray:
 
 def smc_moves(accepted: int, n_particles: int, cfg: Mapping) -> int:
     return int(_load().or_smc_moves(accepted, n_particles, ctypes.byref(_smc(cfg))))
+
+
+def gamma_p(a: float, x: float) -> float:
+    """Regularised lower incomplete gamma function P(a, x)."""
+    return float(_load().or_gamma_p(a, x))
+
+
+def bege_cdf(u: float, p: float, n: float, sp: float, sn: float, n_omega: int = 100) -> float:
+    return float(_load().or_bege_cdf(u, p, n, sp, sn, n_omega))
+
+
+def bege_density(u: float, p: float, n: float, sp: float, sn: float, n_omega: int = 100) -> float:
+    return float(_load().or_bege_density(u, p, n, sp, sn, n_omega))
+
+
+def bege_loglik(theta, r, n_omega: int = 100) -> dict:
+    """log L(theta; r_0..r_T) and the T per-step log densities."""
+    th = np.ascontiguousarray(theta, np.float64)
+    rr = np.ascontiguousarray(r, np.float64)
+    T = len(rr) - 1
+    ld = np.zeros(T, np.float64)
+    out = ctypes.c_double()
+    _load().or_bege_loglik(th, rr, T, n_omega, ld.ctypes.data, ctypes.byref(out))
+    return {"loglik": float(out.value), "logdens": ld}
+
+
+def bege_loglik_batch(thetas, r, n_omega: int = 100) -> np.ndarray:
+    th = np.ascontiguousarray(thetas, np.float64).reshape(-1, 11)
+    rr = np.ascontiguousarray(r, np.float64)
+    out = np.zeros(th.shape[0], np.float64)
+    _load().or_bege_loglik_batch(th, th.shape[0], rr, len(rr) - 1, n_omega, out)
+    return out
+
+
+def bege_simulate(theta, T: int, seed: int) -> np.ndarray:
+    """A synthetic BEGE return series r_0..r_T at theta."""
+    r = np.zeros(T + 1, np.float64)
+    rc = _load().or_bege_simulate(np.ascontiguousarray(theta, np.float64), T, seed, r)
+    if rc != 0:
+        raise ValueError("oracle: a BEGE shape became non-positive")
+    return r

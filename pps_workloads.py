@@ -119,6 +119,31 @@ def wip_lambdas(k: int = 400, seed: int = 11) -> np.ndarray:
     return lam
 
 
+# BEGE volatility model (Sec. 4.2).  theta = (p0, sigma_p, rho_p, phi_p+,
+# phi_p-, n0, sigma_n, rho_n, phi_n+, phi_n-, mu) with the paper's eleven
+# uniform priors.  The observed S&P series (T = 1099 monthly returns) is not
+# available; a series of the same length simulated at BEGE_THETA_OBS stands in
+# for it (monthly sd about 0.057, mean about 0.01, a -0.44 crash month,
+# negative skew).  The likelihood batch is N_p = 1024 parameter vectors, the
+# particle count of the paper's sampler, drawn from the prior (the sampler's
+# first likelihood evaluation), with the paper's quadrature N_omega = 100.
+BEGE_PRIORS = [(1e-4, 0.5), (1e-4, 0.3), (1e-4, 0.99), (1e-4, 0.5), (1e-4, 0.5),
+               (1e-4, 1.0), (1e-4, 0.3), (1e-4, 0.99), (-0.2, 0.1), (1e-4, 0.75),
+               (-0.9, 0.9)]
+BEGE_THETA_OBS = (0.3, 0.02, 0.9, 0.01, 0.03, 0.04, 0.02, 0.85, 0.01, 0.3, 0.008)
+BEGE_SERIES = {"name": "bege_T1099", "T": 1099, "seed": 11}
+BEGE_BATCH = {"name": "bege_loglik_T1099_Np1024_Nw100", "n_theta": 1024, "n_omega": 100,
+              "seed": 7}
+
+
+def bege_prior_draws(n: int, seed: int = 7) -> np.ndarray:
+    """n parameter vectors (rows of 11) drawn from the BEGE priors."""
+    rng = np.random.default_rng(seed)
+    lo = np.array([b[0] for b in BEGE_PRIORS])
+    hi = np.array([b[1] for b in BEGE_PRIORS])
+    return lo + (hi - lo) * rng.uniform(size=(n, len(BEGE_PRIORS)))
+
+
 def lambda_grid(n: int = 64, lo: float = 0.05, hi: float = 3.0) -> np.ndarray:
     """n log-spaced values from lo to hi (inclusive)."""
     k = np.arange(n, dtype=np.float64)

@@ -10,6 +10,9 @@ prior-predictive simulation at a fixed theta (point priors), seed 0, draw 0:
   cells, 599 Euler-Maruyama steps of dt = 1 (T = 600 time points), x0 = 10
   -> the 19 quantile summaries ``y_obs`` and ``t_obs`` = their mean (the
   paper's measured cells are not available; this stands in for them);
+* BEGE volatility model, theta = (0.3, 0.02, 0.9, 0.01, 0.03, 0.04, 0.02,
+  0.85, 0.01, 0.3, 0.008), T = 1099, seed 11 -> the returns r_0..r_T (the
+  S&P series of the paper is not available; this stands in for it);
 * the fixed tolerance of the 1e7-draw ABC workload: the 0.1% distance
   quantile of the oracle's pilot on draws [0, 1e5) of the sampling seed
   (the 100th smallest distance, type-1 inverse empirical CDF).
@@ -59,6 +62,10 @@ def main():
                                 "steps": tspec["steps"],
                                 "y_obs": [float(v) for v in ts["summ"][0]],
                                 "t_obs": float(ts["stat"][0])}
+    bs = W.BEGE_SERIES
+    r = oracle.bege_simulate(W.BEGE_THETA_OBS, bs["T"], bs["seed"])
+    out["bege_T1099"] = {"theta": list(W.BEGE_THETA_OBS), "seed": bs["seed"], "T": bs["T"],
+                         "r": [float(v) for v in r]}
     path = os.path.join(HERE, "observed.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
