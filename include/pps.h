@@ -380,6 +380,38 @@ int pps_wip_test(const pps_bioassay *model, const double *lambda, int n_lambda, 
                  const pps_smc_config *smc, uint64_t seed, double alpha, double *log_z0,
                  double *log_zk, double *pvalues, double *gamma, void *stream);
 
+/* ---- BEGE log-likelihood (Sec. 4.2: Eqs. BEGE, shape, BEGE_LL, CDF_BEGE,
+ *      BEGE_LL_approx, incompGamma) ------------------------------------------ */
+/* log L(theta_k; r_0..r_T) for n_theta parameter vectors against one return
+ * series, FP64.  theta_k = (p0, s_p, rho_p, phi_p+, phi_p-, n0, s_n, rho_n,
+ * phi_n+, phi_n-, mu) (row k of `theta`, 11 doubles).  The shapes start at
+ * (p0, n0) and follow Eq. shape:
+ *   p_t = p0 + rho_p p_{t-1} + phi_p^{+/-} u_t^2 / (2 s_p^2)  (+ for u_t >= 0),
+ *   n_t likewise with (n0, rho_n, phi_n^{+/-}, s_n),  u_t = r_t - mu;
+ * log L = sum_{t=1..T} log f(u_t | p_{t-1}, n_{t-1}) (Eq. BEGE_LL; r_0 is
+ * conditioned on).  f is the central difference (F(u + h) - F(u - h)) / (2h),
+ * h = 1e-3 sqrt(s_p^2 p + s_n^2 n), of the distribution function F of
+ * u = s_p w_p - s_n w_n (centred gamma shocks) discretised as in
+ * Eq. BEGE_LL_approx on the n_omega + 1 nodes w^j = w^0 + j dw,
+ * w^0 = 1e-4 - p s_p, dw = (10 s_p sqrt(p) - w^0) / (n_omega - 1) (the paper
+ * uses n_omega = 100), with P(a, x) evaluated to full FP64 accuracy (power
+ * series for x < a + 1, continued fraction otherwise).  A step whose shapes
+ * are not positive, or whose density estimate is not positive, has
+ * log f = -inf, and so has every step when s_p or s_n is not positive; the
+ * sum is then -inf.
+ * theta (n_theta x 11), r (T + 1), loglik (n_theta) and logdens (n_theta x T,
+ * logdens[k T + t - 1] = log f(u_t); may be NULL) are device pointers; the
+ * library keeps its own scratch (16 bytes per (vector, t), and 8 more when
+ * logdens is NULL).  Returns after the results are written.
+ * Errors: PPS_EINVAL (sizes out of range, NULL pointers), PPS_ENOMEM,
+ * PPS_EDEVICE. */
+#define PPS_BEGE_MAX_THETA (1 << 20)
+#define PPS_BEGE_MAX_T (1 << 20)
+#define PPS_BEGE_MAX_CELLS (1ull << 31)
+#define PPS_BEGE_MAX_NODES 65536
+int pps_bege_loglik(const double *theta, int n_theta, const double *r, int T, int n_omega,
+                    double *loglik, double *logdens, void *stream);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Kernel timing.  While enabled (process-wide; off by default) every call

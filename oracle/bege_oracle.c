@@ -111,17 +111,19 @@ double or_bege_density(double u, double p, double n, double sp, double sn, int n
  *   for t = 1..T: u_t = r_t - mu; log f(u_t | p_{t-1}, n_{t-1}); then
  *     p_t = p0 + rho_p p_{t-1} + phi_p^{+/-} u_t^2 / (2 s_p^2)  (+ for u_t >= 0),
  *     n_t = n0 + rho_n n_{t-1} + phi_n^{+/-} u_t^2 / (2 s_n^2)   (Eq. shape).
- * A non-positive shape or density estimate gives log L = -inf.  ld (optional,
- * T values) receives each log f.  Returns 0.                                 */
+ * A non-positive shape or density estimate gives log f = -inf at that step;
+ * scales that are not positive (outside the model's domain) give -inf at
+ * every step.  ld (optional, T values) receives each log f.  Returns 0.      */
 int or_bege_loglik(const double *th, const double *r, int T, int n_omega, double *ld, double *ll)
 {
     const double p0 = th[0], sp = th[1], rp = th[2], ppos = th[3], pneg = th[4];
     const double n0 = th[5], sn = th[6], rn = th[7], npos = th[8], nneg = th[9], mu = th[10];
+    const int scales_ok = sp > 0.0 && sn > 0.0;
     double p = p0, n = n0, acc = 0.0;
     for (int t = 1; t <= T; ++t) {
         const double u = r[t] - mu;
         double lf = -INFINITY;
-        if (p > 0.0 && n > 0.0) {
+        if (scales_ok && p > 0.0 && n > 0.0) {
             const double f = or_bege_density(u, p, n, sp, sn, n_omega);
             lf = f > 0.0 ? log(f) : -INFINITY;
         }

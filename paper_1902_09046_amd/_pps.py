@@ -206,6 +206,8 @@ def lib():
         L.pps_smc_log_evidence.restype = ctypes.c_int
         L.pps_wip_test.argtypes = [bp, vp, ctypes.c_int, u64, scp, u64, f64, vp, vp, vp, vp, vp]
         L.pps_wip_test.restype = ctypes.c_int
+        L.pps_bege_loglik.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.pps_bege_loglik.restype = ctypes.c_int
         for name in ("pps_philox", "pps_normals", "pps_simulate", "pps_n_summaries", "abc_sample",
                      "prior_pred_pvalue", "pps_summary_tally", "pps_run_batch", "pps_server_create",
                      "pps_submit", "pps_poll", "pps_release", "pps_server_stats_get",
@@ -584,3 +586,26 @@ def pps_wip_test(spec: Mapping, lambdas, n_data: int, cfg: Mapping, seed: int, a
                               ctypes.byref(make_smc_config(cfg)), seed, alpha, int(z0.data_ptr()),
                               int(zk.data_ptr()), _ptr(pv), gamma.ctypes.data, _stream(stream)))
     return {"log_z0": z0, "log_zk": zk, "pvalues": pv, "gamma": gamma}
+
+
+BEGE_NPAR = 11
+
+
+def pps_bege_loglik(theta, r, n_omega: int = 100, with_logdens: bool = False, device="cuda",
+                    stream=None) -> dict:
+    """BEGE log-likelihoods (Sec. 4.2) of the rows of `theta` (n x 11) against
+    the returns r_0..r_T: device FP64 tensors loglik (n) and, if asked for,
+    logdens (n x T).  theta and r may be host arrays or device tensors."""
+    import torch
+    th = torch.as_tensor(np.asarray(theta, np.float64) if not isinstance(theta, torch.Tensor)
+                         else theta, dtype=torch.float64, device=device).reshape(-1, BEGE_NPAR)
+    rr = torch.as_tensor(np.asarray(r, np.float64) if not isinstance(r, torch.Tensor) else r,
+                         dtype=torch.float64, device=device).reshape(-1)
+    th = th.contiguous()
+    rr = rr.contiguous()
+    n, T = th.shape[0], rr.shape[0] - 1
+    ll = torch.empty(n, dtype=torch.float64, device=device)
+    ld = torch.empty((n, T), dtype=torch.float64, device=device) if with_logdens else None
+    _check(lib().pps_bege_loglik(int(th.data_ptr()), n, int(rr.data_ptr()), T, n_omega,
+                                 int(ll.data_ptr()), _ptr(ld), _stream(stream)))
+    return {"loglik": ll, "logdens": ld}

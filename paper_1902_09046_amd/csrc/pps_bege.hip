@@ -1,0 +1,259 @@
+// BEGE log-likelihood on gfx950 (Sec. 4.2: Eqs. BEGE, shape, BEGE_LL,
+// CDF_BEGE, BEGE_LL_approx, incompGamma), FP64.
+//
+// The paper vectorises the incomplete gamma function across the quadrature
+// nodes of one transition density.  Here the unit of parallelism is the
+// transition density itself: the shapes (p_{t-1}, n_{t-1}) of every
+// (parameter vector, t) are known once the shape recursion has run over the
+// data, so the T densities of a parameter vector are independent and go one
+// per lane, 64 consecutive t of one vector per wave (neighbouring t have
+// similar shapes, so the lanes' series lengths stay close).  Three kernels:
+//   k_bege_shapes   one lane per vector: the recursion of Eq. shape;
+//   k_bege_density  one lane per (vector, t): log f(u_t | p_{t-1}, n_{t-1});
+//   k_bege_sum      one workgroup per vector: log L, summed in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "pps_bege.hpp"
+
+namespace pps {
+
+namespace {
+
+constexpr int DENSITY_BLOCK = 64;
+constexpr int SUM_BLOCK = 256;
+constexpr int SHAPES_BLOCK = 64;
+
+// Regularised incomplete gamma: truncation and iteration cap.
+constexpr double IG_EPS = 1.1102230246251565e-16;  // 2^-53
+constexpr int IG_MAXIT = 100000;
+
+// theta = (p0, s_p, rho_p, phi_p+, phi_p-, n0, s_n, rho_n, phi_n+, phi_n-, mu)
+enum { P0, SP, RP, PPOS, PNEG, N0, SN, RN, NPOS, NNEG, MU };
+
+// P(a, x) of Eq. incompGamma for x > 0, given ln Gamma(a), without a
+// division inside either loop (an FP64 division costs a dozen instructions on
+// this GPU, a multiply one):
+//   x < a + 1: e^-x x^a / Gamma(a + 1) times S = sum_m x^m / prod_{i<=m}(a+i).
+//     S is carried as N / D with D = prod (a+i), N = D S, X = x^m:
+//     N <- N (a+k) + X; the series is cut once a term is below 2^-53 of the
+//     sum, i.e. X < 2^-53 N;
+//   x >= a + 1: 1 - e^-x x^a / Gamma(a) / K with Legendre's continued fraction
+//     K = b_0 + a_1 / (b_1 + a_2 / (b_2 + ...)), b_i = x + 2i + 1 - a,
+//     a_i = -i (i - a), by the convergents A_i / B_i of the three-term
+//     recurrences (A, B)_i = b_i (A, B)_{i-1} + a_i (A, B)_{i-2}; it stops
+//     once successive values of 1/K agree to 2^-53, i.e.
+//     |B_i A_{i-1} - A_i B_{i-1}| < 2^-53 |A_i B_{i-1}|.
+// N, D, X (and A, B) are scaled by 2^-600 together when they grow large:
+// exact, and their ratios are all that is used.
+__device__ __attribute__((noinline)) double igam_p(double a, double x, double lga)
+{
+    if (!(x > 0.0))
+        return 0.0;
+    const double e = a * log(x) - x - lga;
+    if (x < a + 1.0) {
+        double n = 1.0, d = 1.0, xm = 1.0, ak = a;
+        for (int k = 1; k < IG_MAXIT; ++k) {
+            ak += 1.0;
+            xm *= x;
+            n = fma(n, ak, xm);
+            d *= ak;
+            if (xm < n * IG_EPS)
+                break;
+            if (d > 0x1p600) {
+                n *= 0x1p-600;
+                d *= 0x1p-600;
+                xm *= 0x1p-600;
+            }
+        }
+        return exp(e) * (n / (a * d));
+    }
+    double am = 1.0, A = x + 1.0 - a, bm = 0.0, B = 1.0, bi = A;
+    for (int i = 1; i < IG_MAXIT; ++i) {
+        const double ai = -i * (i - a);
+        bi += 2.0;
+        const double An = fma(bi, A, ai * am);
+        const double Bn = fma(bi, B, ai * bm);
+        const double cross = An * B;
+        const double diff = fma(Bn, A, -cross);
+        am = A;
+        A = An;
+        bm = B;
+        B = Bn;
+        if (fabs(diff) < IG_EPS * fabs(cross))
+            break;
+        if (fabs(A) > 0x1p600) {
+            am *= 0x1p-600;
+            A *= 0x1p-600;
+            bm *= 0x1p-600;
+            B *= 0x1p-600;
+        }
+    }
+    return 1.0 - exp(e) * (B / A);
+}
+
+__global__ __launch_bounds__(SHAPES_BLOCK) void k_bege_shapes(BegeBatch b)
+{
+    const int k = blockIdx.x * SHAPES_BLOCK + threadIdx.x;
+    if (k >= b.n_theta)
+        return;
+    const double *th = b.theta + static_cast<size_t>(k) * BEGE_NPAR;
+    const double p0 = th[P0], sp = th[SP], rp = th[RP], ppos = th[PPOS], pneg = th[PNEG];
+    const double n0 = th[N0], sn = th[SN], rn = th[RN], npos = th[NPOS], nneg = th[NNEG];
+    const double mu = th[MU];
+    const double cp = 0.5 / (sp * sp), cn = 0.5 / (sn * sn);
+    double *outp = b.shape_p + static_cast<size_t>(k) * b.T;
+    double *outn = b.shape_n + static_cast<size_t>(k) * b.T;
+    double p = p0, n = n0;
+    for (int t = 1; t <= b.T; ++t) {
+        outp[t - 1] = p;
+        outn[t - 1] = n;
+        const double u = b.r[t] - mu;
+        const double u2 = u * u;
+        const bool pos = u >= 0.0;
+        p = p0 + rp * p + (pos ? ppos : pneg) * u2 * cp;
+        n = n0 + rn * n + (pos ? npos : nneg) * u2 * cn;
+    }
+}
+
+// Integral of the Gamma(n, 1) density over [y_m - d/2, y_m + d/2] by its
+// Taylor series about the midpoint,
+//   d g(y_m) [1 + B_2 d^2/24 + B_4 d^4/1920 + B_6 d^6/322560],
+// with g^(k) / g = B_k(L_1, ..., L_k) (complete Bell polynomials) of the
+// derivatives of L = ln g: L_1 = c/y - 1, L_k = (-1)^(k-1) (k-1)! c / y^k
+// (k >= 2), c = n - 1.  With z = d (|L_1| + (1 + sqrt|c|)/y) <= 0.03 every
+// omitted term is below 2^-52 of the sum.  lg = ln Gamma(n).
+__device__ __forceinline__ double gamma_mass_taylor(double c, double ym, double v, double L1, double d,
+                                                    double lg)
+{
+    const double cv = c * v;
+    const double L2 = -cv * v;
+    const double L3 = -2.0 * L2 * v;
+    const double L4 = -3.0 * L3 * v;
+    const double L5 = -4.0 * L4 * v;
+    const double L6 = -5.0 * L5 * v;
+    const double a2 = L1 * L1;
+    const double B2 = a2 + L2;
+    const double B4 = a2 * (a2 + 6.0 * L2) + 4.0 * L1 * L3 + 3.0 * L2 * L2 + L4;
+    const double B6 = a2 * (a2 * (a2 + 15.0 * L2) + 20.0 * L1 * L3 + 45.0 * L2 * L2 + 15.0 * L4) +
+                      L2 * (15.0 * L2 * L2 + 60.0 * L1 * L3 + 15.0 * L4) + 10.0 * L3 * L3 + 6.0 * L1 * L5 +
+                      L6;
+    const double d2 = d * d;
+    const double g = exp(c * log(ym) - ym - lg);
+    return d * g * (1.0 + d2 * (B2 * (1.0 / 24.0) + d2 * (B4 * (1.0 / 1920.0) + d2 * (B6 * (1.0 / 322560.0)))));
+}
+
+// f(u) ~ (F(u + h) - F(u - h)) / (2h) with F the discretised distribution
+// function of Eq. BEGE_LL_approx on the nodes w^j = w^0 + j dw, w^0 = 1e-4 -
+// p s_p, dw = (10 s_p sqrt(p) - w^0) / (N - 1), and h = 1e-3 sqrt(s_p^2 p +
+// s_n^2 n).  Both distribution functions share the increments
+// dF_j = P(p, (w^j + p s_p)/s_p) - P(p, (w^{j-1} + p s_p)/s_p), so the
+// difference is accumulated directly:
+//   F(u + h) - F(u - h) = sum_j dF_j [P(n, y_j + d/2) - P(n, y_j - d/2)],
+//   y_j = (w^{j-1} - u + n s_n) / s_n,  d = 2h / s_n,
+// where the bracket is the Gamma(n, 1) mass of [y_j - d/2, y_j + d/2]:
+// zero when the interval lies below 0, the Taylor form above when the
+// interval is short against the density's scale (the usual case: d is 2e-3
+// standard deviations of u over s_n), else the difference of the two
+// incomplete gamma values.  Nodes with dF_j = 0 (where P(p, .) has
+// saturated) add nothing.
+__device__ double bege_density(double u, double p, double n, double sp, double sn, int n_omega)
+{
+    const double h = 1e-3 * sqrt(sp * sp * p + sn * sn * n);
+    const double w0 = 1e-4 - p * sp;
+    const double dw = (10.0 * sp * sqrt(p) - w0) / (n_omega - 1);
+    const double lgp = lgamma(p), lgn = lgamma(n);
+    const double psp = p * sp, nsn = n * sn;
+    const double c = n - 1.0;
+    const double zc = 1.0 + sqrt(fabs(c));
+    const double d = 2.0 * h / sn;
+    double prev = igam_p(p, (w0 + psp) / sp, lgp);
+    double acc = 0.0;
+    for (int j = 1; j <= n_omega; ++j) {
+        const double cur = igam_p(p, (w0 + j * dw + psp) / sp, lgp);
+        const double dF = cur - prev;
+        prev = cur;
+        if (dF == 0.0)
+            continue;
+        const double base = w0 + (j - 1) * dw - u + nsn;
+        const double yhi = (base + h) / sn;
+        if (!(yhi > 0.0))
+            continue;
+        const double ylo = (base - h) / sn;
+        const double ym = base / sn;
+        const double v = 1.0 / ym;
+        const double L1 = c * v - 1.0;
+        const double z = d * (fabs(L1) + zc * v);
+        double mass;
+        if (ylo > 0.0 && z <= 0.03)
+            mass = gamma_mass_taylor(c, ym, v, L1, d, lgn);
+        else
+            mass = igam_p(n, yhi, lgn) - igam_p(n, ylo, lgn);
+        acc += dF * mass;
+    }
+    return acc / (2.0 * h);
+}
+
+__global__ __launch_bounds__(DENSITY_BLOCK) void k_bege_density(BegeBatch b, int chunks)
+{
+    const int k = blockIdx.x / chunks;
+    const int t = (blockIdx.x - k * chunks) * DENSITY_BLOCK + threadIdx.x + 1;
+    if (t > b.T)
+        return;
+    const double *th = b.theta + static_cast<size_t>(k) * BEGE_NPAR;
+    const double sp = th[SP], sn = th[SN], mu = th[MU];
+    const size_t o = static_cast<size_t>(k) * b.T + (t - 1);
+    const double p = b.shape_p[o], n = b.shape_n[o];
+    double out = -INFINITY;
+    if (sp > 0.0 && sn > 0.0 && p > 0.0 && n > 0.0) {
+        const double f = bege_density(b.r[t] - mu, p, n, sp, sn, b.n_omega);
+        if (f > 0.0)
+            out = log(f);
+    }
+    b.logdens[o] = out;
+}
+
+__global__ __launch_bounds__(SUM_BLOCK) void k_bege_sum(BegeBatch b)
+{
+    __shared__ double s[SUM_BLOCK];
+    const int k = blockIdx.x;
+    const double *ld = b.logdens + static_cast<size_t>(k) * b.T;
+    double v = 0.0;
+    for (int t = threadIdx.x; t < b.T; t += SUM_BLOCK)
+        v += ld[t];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = SUM_BLOCK / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w)
+            s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        b.loglik[k] = s[0];
+}
+
+}  // namespace
+
+hipError_t launch_bege(const BegeBatch &b, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    const int shape_grid = (b.n_theta + SHAPES_BLOCK - 1) / SHAPES_BLOCK;
+    hipLaunchKernelGGL(k_bege_shapes, dim3(shape_grid), dim3(SHAPES_BLOCK), 0, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int chunks = (b.T + DENSITY_BLOCK - 1) / DENSITY_BLOCK;
+    const uint64_t grid = static_cast<uint64_t>(chunks) * b.n_theta;
+    if (ev0)
+        (void)hipEventRecord(ev0, s);
+    hipLaunchKernelGGL(k_bege_density, dim3(static_cast<unsigned>(grid)), dim3(DENSITY_BLOCK), 0, s,
+                       b, chunks);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if (ev1)
+        (void)hipEventRecord(ev1, s);
+    hipLaunchKernelGGL(k_bege_sum, dim3(b.n_theta), dim3(SUM_BLOCK), 0, s, b);
+    return hipGetLastError();
+}
+
+}  // namespace pps

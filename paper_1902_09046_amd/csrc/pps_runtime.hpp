@@ -41,6 +41,9 @@ struct Context {
     // weak-informativity test: data sets, hyperparameters, tile counter,
     // tally counts and cut-offs
     DevBuf smc_y, smc_lam, smc_coef, smc_ctr, smc_counts, smc_gamma;
+    // BEGE log-likelihood: the shapes of every (vector, t), and the per-t
+    // log densities when the caller does not take them
+    DevBuf bege_shapes, bege_logdens;
     double last_kernel_ms = -1.0;
 };
 

@@ -241,3 +241,18 @@ def test_strerror(P):
     for code in (0, 1, -1, -2, -3, -4, -5, -6, 42):
         assert L.pps_strerror(code)
     assert L.pps_strerror(-6) == b"output truncated to capacity"
+
+
+def test_bege_validation_without_device(P):
+    L = P.lib()
+    dev = 1  # never dereferenced: every call below fails validation first
+
+    def call(n_theta, T, n_omega, theta=dev, r=dev, ll=dev):
+        return L.pps_bege_loglik(theta, n_theta, r, T, n_omega, ll, None, None)
+    for args in [(0, 10, 100), (-1, 10, 100), ((1 << 20) + 1, 10, 100), (4, 0, 100),
+                 (4, (1 << 20) + 1, 100), (1 << 20, 1 << 12, 100), (4, 10, 1), (4, 10, 65537)]:
+        assert call(*args) == P.PPS_EINVAL, args
+    assert call(4, 10, 100, theta=None) == P.PPS_EINVAL
+    assert call(4, 10, 100, r=None) == P.PPS_EINVAL
+    assert call(4, 10, 100, ll=None) == P.PPS_EINVAL
+    assert b"n_omega" in L.pps_last_error() or L.pps_last_error()
