@@ -32,6 +32,8 @@ METRIC = "prior-predictive sims/s + % FP32 VALU peak vs plain GPU; p50/p99 job l
 # peak with an FMA counted as one operation (two flops).
 CUS, LANES_PER_CU, CLOCK = 256, 128, 2.4e9
 VALU_PEAK_OPS = CUS * LANES_PER_CU * CLOCK  # 7.86e13 lane-ops/s
+# Published FP64 vector peak (an FMA counted as two operations).
+FP64_PEAK_TFLOPS = 78.6
 
 # Algorithmic VALU lane-operations of the logistic path (see the design notes):
 #   Philox4x32-10 call: 10 rounds x (2 widening 32x32->64 multiplies + 4 xor) = 60
@@ -89,13 +91,20 @@ def toggle_ops_per_draw(n_cells: int, steps: int) -> float:
     return n_cells * (steps * TSW_OPS_PER_CELL_STEP + TSW_OPS_PER_CELL) + TSW_OPS_PER_DRAW
 
 
-def kernel_source_digest() -> str:
-    """sha256 of the device sources; HBM traffic taken from the PMC counters is
-    reported only while it matches the digest recorded with them."""
+# Device sources of each profiled kernel: HBM traffic taken from the PMC
+# counters is reported only while these files hash to the digest recorded
+# with the counters.
+KERNEL_SOURCES = {
+    "simulate": ("pps_device.hpp", "pps_internal.hpp", "pps_kernels.hip"),
+    "smc": ("pps_device.hpp", "pps_smc.hpp", "pps_smc.hip"),
+    "bege": ("pps_bege.hpp", "pps_bege.hip"),
+}
+
+
+def kernel_source_digest(family: str) -> str:
     csrc = os.path.join(ROOT, "paper_1902_09046_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("pps_device.hpp", "pps_internal.hpp", "pps_kernels.hip", "pps_smc.hpp",
-                 "pps_smc.hip"):
+    for name in KERNEL_SOURCES[family]:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -107,9 +116,10 @@ def measured_traffic(key: str):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha256") != kernel_source_digest() or key not in t:
+    e = t.get(key)
+    if not e or e.get("kernel_source_sha256") != kernel_source_digest(e.get("sources", "simulate")):
         return None
-    return t[key]["bytes_per_launch"]
+    return e["bytes_per_launch"]
 
 
 def time_calls(P, torch, fn, warmup: int, reps: int):
@@ -401,6 +411,41 @@ def main():
                             "cores": oracle.threads(),
                             "sample": f"6 priors x {sn} data sets (FP64, the same algorithm)"}
         workloads["wip_bioassay_K400_N400_Np500"] = ww
+        # BEGE log-likelihood batch (Sec. 4.2): the N_p = 1024 particles of
+        # the paper's sampler, drawn from the prior (its first likelihood
+        # evaluation), against a T = 1099 return series, N_omega = 100.
+        bb = W.BEGE_BATCH
+        bser = np.array(golden["bege_T1099"]["r"])
+        bT = len(bser) - 1
+        bth = torch.tensor(W.bege_prior_draws(bb["n_theta"], seed=bb["seed"]), device="cuda")
+        brd = torch.tensor(bser, device="cuda")
+        print(f"bench: BEGE log-likelihood {bb['n_theta']} x T={bT} (N_omega = {bb['n_omega']})",
+              file=sys.stderr, flush=True)
+        bops = P.pps_bege_count_ops(bth, brd, bb["n_omega"])
+        wall, kms = time_calls(P, torch, lambda: P.pps_bege_loglik(bth, brd, bb["n_omega"]), 1, 5)
+        bach = bops / (kms * 1e-3) / 1e12
+        bw = {"loglik_per_s": round(bb["n_theta"] / wall, 1),
+              "densities_per_s": round(bb["n_theta"] * bT / wall, 1),
+              "ms": round(wall * 1e3, 3), "kernel_ms": round(kms, 3),
+              "kernel": "k_bege_density<64> (FP64)",
+              "roofline": {"bound": "alu", "achieved": round(bach, 3), "peak": FP64_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(bach / FP64_PEAK_TFLOPS, 4),
+                           "ops_per_launch": bops,
+                           "traffic": measured_traffic("k_bege_density_T1099_Np1024")},
+              "paper_context": {"table": "A.3", "what": "whole SMC inference (N_p = 1024), "
+                                "not one likelihood batch", "seconds": 3115.0,
+                                "cpu": "Xeon E5-2680v3", "threads": 16, "code": "C, AVX2, FP64"}}
+        if args.cpu_sample > 0:
+            import oracle
+            bs = 128
+            bsample = W.bege_prior_draws(bb["n_theta"], seed=bb["seed"])[:bs]
+            c0 = time.perf_counter()
+            oracle.bege_loglik_batch(bsample, bser, bb["n_omega"])
+            c1 = time.perf_counter()
+            bw["oracle"] = {"loglik_per_s": round(bs / (c1 - c0), 2), "cores": oracle.threads(),
+                            "sample": f"the first {bs} of the {bb['n_theta']} vectors (FP64, "
+                                      "the same quadrature)"}
+        workloads[bb["name"]] = bw
         if args.serving_jobs > 0:
             workloads["serving_mix"] = serving_bench(P, torch, W, golden, args.serving_jobs,
                                                      W.SERVING_MIX["rate_hz"])

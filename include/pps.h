@@ -420,6 +420,16 @@ int pps_bege_loglik(const double *theta, int n_theta, const double *r, int T, in
  * kernel's duration in milliseconds for the most recent such call on the
  * current device, or a negative value if none was timed.  Returns PPS_OK. */
 int pps_set_timing(int enable);
+
+/* Work of one pps_bege_loglik call, for roofline accounting: runs the same
+ * batch (results discarded) with the operation-counting instantiation of the
+ * density kernel and stores in *ops (host) the FP64 operations that the
+ * lanes executed as the algorithm states them: an FMA counts 2, a division
+ * 1, a series iteration of P(a, x) 6, a continued-fraction iteration 13, exp
+ * 32, log 90 and lgamma 200 (the FP64 operations of their gfx950 code).
+ * Arguments and errors as pps_bege_loglik (ops must not be NULL). */
+int pps_bege_count_ops(const double *theta, int n_theta, const double *r, int T, int n_omega,
+                       double *ops, void *stream);
 double pps_last_kernel_ms(void);
 
 /* ---- launch shape ------------------------------------------------------- */

@@ -25,5 +25,5 @@ from ._pps import (  # noqa: F401
     make_abc_job, make_pvalue_job, make_server_config, pps_job_arena_bytes, pps_run_batch,
     Server, records, pps_autotune,
     PPS_BIO_MAX_GROUPS, PPS_SMC_MAX_PARTICLES, pps_bioassay, pps_smc_config, make_bioassay,
-    make_smc_config, pps_smc_log_evidence, pps_wip_test, pps_bege_loglik, BEGE_NPAR,
+    make_smc_config, pps_smc_log_evidence, pps_wip_test, pps_bege_loglik, pps_bege_count_ops, BEGE_NPAR,
 )

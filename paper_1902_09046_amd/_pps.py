@@ -208,6 +208,9 @@ def lib():
         L.pps_wip_test.restype = ctypes.c_int
         L.pps_bege_loglik.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.pps_bege_loglik.restype = ctypes.c_int
+        L.pps_bege_count_ops.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double), vp]
+        L.pps_bege_count_ops.restype = ctypes.c_int
         for name in ("pps_philox", "pps_normals", "pps_simulate", "pps_n_summaries", "abc_sample",
                      "prior_pred_pvalue", "pps_summary_tally", "pps_run_batch", "pps_server_create",
                      "pps_submit", "pps_poll", "pps_release", "pps_server_stats_get",
@@ -609,3 +612,17 @@ def pps_bege_loglik(theta, r, n_omega: int = 100, with_logdens: bool = False, de
     _check(lib().pps_bege_loglik(int(th.data_ptr()), n, int(rr.data_ptr()), T, n_omega,
                                  int(ll.data_ptr()), _ptr(ld), _stream(stream)))
     return {"loglik": ll, "logdens": ld}
+
+
+def pps_bege_count_ops(theta, r, n_omega: int = 100, device="cuda", stream=None) -> float:
+    """FP64 operations of one pps_bege_loglik call on the same batch."""
+    import torch
+    th = torch.as_tensor(np.asarray(theta, np.float64) if not isinstance(theta, torch.Tensor)
+                         else theta, dtype=torch.float64, device=device).reshape(-1, BEGE_NPAR)
+    rr = torch.as_tensor(np.asarray(r, np.float64) if not isinstance(r, torch.Tensor) else r,
+                         dtype=torch.float64, device=device).reshape(-1)
+    th, rr = th.contiguous(), rr.contiguous()
+    ops = ctypes.c_double()
+    _check(lib().pps_bege_count_ops(int(th.data_ptr()), th.shape[0], int(rr.data_ptr()),
+                                    rr.shape[0] - 1, n_omega, ctypes.byref(ops), _stream(stream)))
+    return float(ops.value)

@@ -7,9 +7,14 @@
 // (parameter vector, t) are known once the shape recursion has run over the
 // data, so the T densities of a parameter vector are independent and go one
 // per lane, 64 consecutive t of one vector per wave (neighbouring t have
-// similar shapes, so the lanes' series lengths stay close).  Three kernels:
-//   k_bege_shapes   one lane per vector: the recursion of Eq. shape;
-//   k_bege_density  one lane per (vector, t): log f(u_t | p_{t-1}, n_{t-1});
+// similar shapes, so the lanes' series lengths stay close).  Kernels:
+//   k_bege_shapes   one lane per vector: the recursion of Eq. shape, and a
+//                   cost class per chunk of 64 steps from its largest shape;
+//   k_bege_order    one workgroup: the chunks in decreasing cost class;
+//   k_bege_density  one lane per (vector, t): log f(u_t | p_{t-1}, n_{t-1}),
+//                   chunks taken in that order so that the long waves (large
+//                   shapes need long series) start first and the short ones
+//                   fill in behind them;
 //   k_bege_sum      one workgroup per vector: log L, summed in a fixed order.
 #include <hip/hip_runtime.h>
 
@@ -24,6 +29,8 @@ namespace {
 constexpr int DENSITY_BLOCK = 64;
 constexpr int SUM_BLOCK = 256;
 constexpr int SHAPES_BLOCK = 64;
+constexpr int ORDER_BLOCK = 1024;
+constexpr int N_COST_CLASSES = 64;
 
 // Regularised incomplete gamma: truncation and iteration cap.
 constexpr double IG_EPS = 1.1102230246251565e-16;  // 2^-53
@@ -31,6 +38,24 @@ constexpr int IG_MAXIT = 100000;
 
 // theta = (p0, s_p, rho_p, phi_p+, phi_p-, n0, s_n, rho_n, phi_n+, phi_n-, mu)
 enum { P0, SP, RP, PPOS, PNEG, N0, SN, RN, NPOS, NNEG, MU };
+
+// Operation counting (the COUNT instantiation, for measurement only): FP64
+// operations per lane as the source states them, an FMA counting 2 and a
+// division 1, and the library functions at the FP64 operations of their
+// gfx950 code (exp 32 and log 90, both branch-free; lgamma ~200; sqrt 1).
+constexpr double OPS_EXP = 32.0, OPS_LOG = 90.0, OPS_LGAMMA = 200.0;
+constexpr double OPS_SERIES_IT = 6.0, OPS_CF_IT = 13.0, OPS_IGAM_FIXED = OPS_LOG + OPS_EXP + 6.0;
+constexpr double OPS_TAYLOR = 62.0 + OPS_LOG + OPS_EXP;
+
+template <bool COUNT>
+struct OpCount {
+    double v = 0.0;
+    __device__ __forceinline__ void add(double k)
+    {
+        if constexpr (COUNT)
+            v += k;
+    }
+};
 
 // P(a, x) of Eq. incompGamma for x > 0, given ln Gamma(a), without a
 // division inside either loop (an FP64 division costs a dozen instructions on
@@ -47,14 +72,16 @@ enum { P0, SP, RP, PPOS, PNEG, N0, SN, RN, NPOS, NNEG, MU };
 //     |B_i A_{i-1} - A_i B_{i-1}| < 2^-53 |A_i B_{i-1}|.
 // N, D, X (and A, B) are scaled by 2^-600 together when they grow large:
 // exact, and their ratios are all that is used.
-__device__ __attribute__((noinline)) double igam_p(double a, double x, double lga)
+template <bool COUNT>
+__device__ __attribute__((noinline)) double igam_p(double a, double x, double lga, OpCount<COUNT> &ops)
 {
     if (!(x > 0.0))
         return 0.0;
     const double e = a * log(x) - x - lga;
     if (x < a + 1.0) {
         double n = 1.0, d = 1.0, xm = 1.0, ak = a;
-        for (int k = 1; k < IG_MAXIT; ++k) {
+        int k = 1;
+        for (; k < IG_MAXIT; ++k) {
             ak += 1.0;
             xm *= x;
             n = fma(n, ak, xm);
@@ -67,10 +94,12 @@ __device__ __attribute__((noinline)) double igam_p(double a, double x, double lg
                 xm *= 0x1p-600;
             }
         }
+        ops.add(OPS_IGAM_FIXED + OPS_SERIES_IT * k);
         return exp(e) * (n / (a * d));
     }
     double am = 1.0, A = x + 1.0 - a, bm = 0.0, B = 1.0, bi = A;
-    for (int i = 1; i < IG_MAXIT; ++i) {
+    int i = 1;
+    for (; i < IG_MAXIT; ++i) {
         const double ai = -i * (i - a);
         bi += 2.0;
         const double An = fma(bi, A, ai * am);
@@ -90,7 +119,20 @@ __device__ __attribute__((noinline)) double igam_p(double a, double x, double lg
             B *= 0x1p-600;
         }
     }
+    ops.add(OPS_IGAM_FIXED + OPS_CF_IT * i);
     return 1.0 - exp(e) * (B / A);
+}
+
+// Cost class of a chunk from the largest shape p among its valid steps: the
+// series of P(p, x) near x = p need about sqrt(p) terms, so the class is
+// 2 log2(max p) + 16 clamped to [1, 63] (quarter octaves of sqrt p); a chunk
+// with no valid step is class 0.
+__device__ __forceinline__ int cost_class(double pmax)
+{
+    if (!(pmax > 0.0))
+        return 0;
+    const int c = static_cast<int>(2.0 * log2(pmax)) + 16;
+    return c < 1 ? 1 : (c > N_COST_CLASSES - 1 ? N_COST_CLASSES - 1 : c);
 }
 
 __global__ __launch_bounds__(SHAPES_BLOCK) void k_bege_shapes(BegeBatch b)
@@ -105,16 +147,49 @@ __global__ __launch_bounds__(SHAPES_BLOCK) void k_bege_shapes(BegeBatch b)
     const double cp = 0.5 / (sp * sp), cn = 0.5 / (sn * sn);
     double *outp = b.shape_p + static_cast<size_t>(k) * b.T;
     double *outn = b.shape_n + static_cast<size_t>(k) * b.T;
-    double p = p0, n = n0;
+    int32_t *cls = b.chunk_class + static_cast<size_t>(k) * b.chunks;
+    const bool scales_ok = sp > 0.0 && sn > 0.0;
+    double p = p0, n = n0, pmax = 0.0;
     for (int t = 1; t <= b.T; ++t) {
         outp[t - 1] = p;
         outn[t - 1] = n;
+        if (scales_ok && p > 0.0 && n > 0.0)
+            pmax = fmax(pmax, p);
+        if (t % DENSITY_BLOCK == 0 || t == b.T) {
+            cls[(t - 1) / DENSITY_BLOCK] = cost_class(pmax);
+            pmax = 0.0;
+        }
         const double u = b.r[t] - mu;
         const double u2 = u * u;
         const bool pos = u >= 0.0;
         p = p0 + rp * p + (pos ? ppos : pneg) * u2 * cp;
         n = n0 + rn * n + (pos ? npos : nneg) * u2 * cn;
     }
+}
+
+// Counting sort of the chunks by decreasing cost class (one workgroup; the
+// order within a class is immaterial: every chunk writes its own outputs).
+__global__ __launch_bounds__(ORDER_BLOCK) void k_bege_order(BegeBatch b)
+{
+    __shared__ unsigned hist[N_COST_CLASSES];
+    __shared__ unsigned start[N_COST_CLASSES];
+    const uint32_t n = static_cast<uint32_t>(b.n_theta) * static_cast<uint32_t>(b.chunks);
+    if (threadIdx.x < N_COST_CLASSES)
+        hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += ORDER_BLOCK)
+        atomicAdd(&hist[b.chunk_class[i]], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned acc = 0;
+        for (int c = N_COST_CLASSES - 1; c >= 0; --c) {
+            start[c] = acc;
+            acc += hist[c];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += ORDER_BLOCK)
+        b.chunk_order[atomicAdd(&start[b.chunk_class[i]], 1u)] = static_cast<int32_t>(i);
 }
 
 // Integral of the Gamma(n, 1) density over [y_m - d/2, y_m + d/2] by its
@@ -158,7 +233,9 @@ __device__ __forceinline__ double gamma_mass_taylor(double c, double ym, double 
 // standard deviations of u over s_n), else the difference of the two
 // incomplete gamma values.  Nodes with dF_j = 0 (where P(p, .) has
 // saturated) add nothing.
-__device__ double bege_density(double u, double p, double n, double sp, double sn, int n_omega)
+template <bool COUNT>
+__device__ double bege_density(double u, double p, double n, double sp, double sn, int n_omega,
+                               OpCount<COUNT> &ops)
 {
     const double h = 1e-3 * sqrt(sp * sp * p + sn * sn * n);
     const double w0 = 1e-4 - p * sp;
@@ -168,10 +245,12 @@ __device__ double bege_density(double u, double p, double n, double sp, double s
     const double c = n - 1.0;
     const double zc = 1.0 + sqrt(fabs(c));
     const double d = 2.0 * h / sn;
-    double prev = igam_p(p, (w0 + psp) / sp, lgp);
+    ops.add(2.0 * OPS_LGAMMA + 30.0);
+    double prev = igam_p(p, (w0 + psp) / sp, lgp, ops);
     double acc = 0.0;
     for (int j = 1; j <= n_omega; ++j) {
-        const double cur = igam_p(p, (w0 + j * dw + psp) / sp, lgp);
+        const double cur = igam_p(p, (w0 + j * dw + psp) / sp, lgp, ops);
+        ops.add(5.0);
         const double dF = cur - prev;
         prev = cur;
         if (dF == 0.0)
@@ -186,32 +265,47 @@ __device__ double bege_density(double u, double p, double n, double sp, double s
         const double L1 = c * v - 1.0;
         const double z = d * (fabs(L1) + zc * v);
         double mass;
-        if (ylo > 0.0 && z <= 0.03)
+        ops.add(17.0);
+        if (ylo > 0.0 && z <= 0.03) {
             mass = gamma_mass_taylor(c, ym, v, L1, d, lgn);
-        else
-            mass = igam_p(n, yhi, lgn) - igam_p(n, ylo, lgn);
+            ops.add(OPS_TAYLOR);
+        } else {
+            mass = igam_p(n, yhi, lgn, ops) - igam_p(n, ylo, lgn, ops);
+        }
         acc += dF * mass;
     }
     return acc / (2.0 * h);
 }
 
-__global__ __launch_bounds__(DENSITY_BLOCK) void k_bege_density(BegeBatch b, int chunks)
+template <bool COUNT>
+__global__ __launch_bounds__(DENSITY_BLOCK) void k_bege_density(BegeBatch b)
 {
-    const int k = blockIdx.x / chunks;
-    const int t = (blockIdx.x - k * chunks) * DENSITY_BLOCK + threadIdx.x + 1;
-    if (t > b.T)
-        return;
-    const double *th = b.theta + static_cast<size_t>(k) * BEGE_NPAR;
-    const double sp = th[SP], sn = th[SN], mu = th[MU];
-    const size_t o = static_cast<size_t>(k) * b.T + (t - 1);
-    const double p = b.shape_p[o], n = b.shape_n[o];
-    double out = -INFINITY;
-    if (sp > 0.0 && sn > 0.0 && p > 0.0 && n > 0.0) {
-        const double f = bege_density(b.r[t] - mu, p, n, sp, sn, b.n_omega);
-        if (f > 0.0)
-            out = log(f);
+    const int chunk = b.chunk_order[blockIdx.x];
+    const int k = chunk / b.chunks;
+    const int t = (chunk - k * b.chunks) * DENSITY_BLOCK + threadIdx.x + 1;
+    OpCount<COUNT> ops;
+    if (t <= b.T) {
+        const double *th = b.theta + static_cast<size_t>(k) * BEGE_NPAR;
+        const double sp = th[SP], sn = th[SN], mu = th[MU];
+        const size_t o = static_cast<size_t>(k) * b.T + (t - 1);
+        const double p = b.shape_p[o], n = b.shape_n[o];
+        double out = -INFINITY;
+        if (sp > 0.0 && sn > 0.0 && p > 0.0 && n > 0.0) {
+            const double f = bege_density(b.r[t] - mu, p, n, sp, sn, b.n_omega, ops);
+            ops.add(OPS_LOG + 2.0);
+            if (f > 0.0)
+                out = log(f);
+        }
+        b.logdens[o] = out;
     }
-    b.logdens[o] = out;
+    if constexpr (COUNT) {
+        // integer-valued totals: exact in any order
+        double v = ops.v;
+        for (int m = 32; m > 0; m >>= 1)
+            v += __shfl_xor(v, m, 64);
+        if (threadIdx.x == 0)
+            atomicAdd(b.ops, v);
+    }
 }
 
 __global__ __launch_bounds__(SUM_BLOCK) void k_bege_sum(BegeBatch b)
@@ -235,6 +329,11 @@ __global__ __launch_bounds__(SUM_BLOCK) void k_bege_sum(BegeBatch b)
 
 }  // namespace
 
+int bege_chunks(int T)
+{
+    return (T + DENSITY_BLOCK - 1) / DENSITY_BLOCK;
+}
+
 hipError_t launch_bege(const BegeBatch &b, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     const int shape_grid = (b.n_theta + SHAPES_BLOCK - 1) / SHAPES_BLOCK;
@@ -242,12 +341,18 @@ hipError_t launch_bege(const BegeBatch &b, hipStream_t s, hipEvent_t ev0, hipEve
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const int chunks = (b.T + DENSITY_BLOCK - 1) / DENSITY_BLOCK;
-    const uint64_t grid = static_cast<uint64_t>(chunks) * b.n_theta;
+    hipLaunchKernelGGL(k_bege_order, dim3(1), dim3(ORDER_BLOCK), 0, s, b);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    const uint64_t grid = static_cast<uint64_t>(b.chunks) * b.n_theta;
     if (ev0)
         (void)hipEventRecord(ev0, s);
-    hipLaunchKernelGGL(k_bege_density, dim3(static_cast<unsigned>(grid)), dim3(DENSITY_BLOCK), 0, s,
-                       b, chunks);
+    if (b.ops)
+        hipLaunchKernelGGL(k_bege_density<true>, dim3(static_cast<unsigned>(grid)), dim3(DENSITY_BLOCK),
+                           0, s, b);
+    else
+        hipLaunchKernelGGL(k_bege_density<false>, dim3(static_cast<unsigned>(grid)),
+                           dim3(DENSITY_BLOCK), 0, s, b);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     if (ev1)

@@ -19,15 +19,22 @@ struct BegeBatch {
     int32_t n_theta;
     int32_t T;
     int32_t n_omega;
-    int32_t pad;
+    int32_t chunks;        // chunks of 64 steps per vector: bege_chunks(T)
+    int32_t *chunk_class;  // n_theta x chunks cost classes
+    int32_t *chunk_order;  // the chunks (k chunks + c) in decreasing class
     double *shape_p;
     double *shape_n;
     double *logdens;
     double *loglik;
+    double *ops;  // when not null: FP64 operations of the density kernel added here
 };
 
-// Shapes, transition densities, then the per-vector sums, in stream order.
-// When ev0/ev1 are given they bracket the density kernel.
+int bege_chunks(int T);
+
+// Shapes, chunk order, transition densities, then the per-vector sums, in
+// stream order.
+// When ev0/ev1 are given they bracket the density kernel; when b.ops is set
+// the density kernel is the operation-counting instantiation.
 hipError_t launch_bege(const BegeBatch &b, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 
 }  // namespace pps

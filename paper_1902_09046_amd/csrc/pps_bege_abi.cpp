@@ -6,12 +6,11 @@
 
 using namespace pps;
 
-extern "C" {
+namespace {
 
-int pps_bege_loglik(const double *theta, int n_theta, const double *r, int T, int n_omega,
-                    double *loglik, double *logdens, void *stream)
+int bege_run(const double *theta, int n_theta, const double *r, int T, int n_omega, double *loglik,
+             double *logdens, double *ops_host, void *stream)
 {
-    clear_error();
     if (n_theta < 1 || n_theta > PPS_BEGE_MAX_THETA)
         return fail(PPS_EINVAL, "n_theta %d out of range [1, %d]", n_theta, PPS_BEGE_MAX_THETA);
     if (T < 1 || T > PPS_BEGE_MAX_T)
@@ -21,8 +20,8 @@ int pps_bege_loglik(const double *theta, int n_theta, const double *r, int T, in
                     static_cast<unsigned long long>(PPS_BEGE_MAX_CELLS));
     if (n_omega < 2 || n_omega > PPS_BEGE_MAX_NODES)
         return fail(PPS_EINVAL, "n_omega %d out of range [2, %d]", n_omega, PPS_BEGE_MAX_NODES);
-    if (!theta || !r || !loglik)
-        return fail(PPS_EINVAL, "pps_bege_loglik: theta, r and loglik are required");
+    if (!theta || !r || (!loglik && !ops_host))
+        return fail(PPS_EINVAL, "theta, r and loglik are required");
     int rc;
     Context *c = current_context(&rc);
     if (!c)
@@ -31,8 +30,13 @@ int pps_bege_loglik(const double *theta, int n_theta, const double *r, int T, in
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t cells = static_cast<size_t>(n_theta) * T;
     hipError_t e;
-    if ((e = c->bege_shapes.ensure(2 * cells * sizeof(double))) != hipSuccess ||
-        (!logdens && (e = c->bege_logdens.ensure(cells * sizeof(double))) != hipSuccess))
+    // shapes, the operation total, chunk classes and order; per-step log
+    // densities and sums when the caller does not take them
+    const int chunks = bege_chunks(T);
+    const size_t n_chunks = static_cast<size_t>(n_theta) * chunks;
+    if ((e = c->bege_shapes.ensure(2 * cells * sizeof(double) + 256 + 2 * n_chunks * sizeof(int32_t))) !=
+            hipSuccess ||
+        (!logdens && (e = c->bege_logdens.ensure((cells + n_theta) * sizeof(double))) != hipSuccess))
         return fail_hip(e, "BEGE scratch");
     BegeBatch b{};
     b.theta = theta;
@@ -40,10 +44,21 @@ int pps_bege_loglik(const double *theta, int n_theta, const double *r, int T, in
     b.n_theta = n_theta;
     b.T = T;
     b.n_omega = n_omega;
+    b.chunks = chunks;
     b.shape_p = c->bege_shapes.as<double>();
     b.shape_n = b.shape_p + cells;
+    // after the shapes: the operation total (256 bytes), then the chunk
+    // classes and order
+    b.chunk_class = reinterpret_cast<int32_t *>(b.shape_n + cells + 32);
+    b.chunk_order = b.chunk_class + n_chunks;
     b.logdens = logdens ? logdens : c->bege_logdens.as<double>();
-    b.loglik = loglik;
+    b.loglik = loglik ? loglik : c->bege_logdens.as<double>() + cells;
+    if (ops_host) {
+        // the operation total sits after the shapes
+        b.ops = b.shape_n + cells;
+        if ((e = hipMemsetAsync(b.ops, 0, sizeof(double), st)) != hipSuccess)
+            return fail_hip(e, "BEGE operation counter");
+    }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (g_timing) {
         (void)hipEventCreate(&ev0);
@@ -59,9 +74,31 @@ int pps_bege_loglik(const double *theta, int n_theta, const double *r, int T, in
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
     }
+    if (e == hipSuccess && ops_host)
+        e = hipMemcpy(ops_host, b.ops, sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess)
-        return fail_hip(e, "pps_bege_loglik");
+        return fail_hip(e, "BEGE launch");
     return PPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pps_bege_loglik(const double *theta, int n_theta, const double *r, int T, int n_omega,
+                    double *loglik, double *logdens, void *stream)
+{
+    clear_error();
+    return bege_run(theta, n_theta, r, T, n_omega, loglik, logdens, nullptr, stream);
+}
+
+int pps_bege_count_ops(const double *theta, int n_theta, const double *r, int T, int n_omega,
+                       double *ops, void *stream)
+{
+    clear_error();
+    if (!ops)
+        return fail(PPS_EINVAL, "ops is required");
+    return bege_run(theta, n_theta, r, T, n_omega, nullptr, nullptr, ops, stream);
 }
 
 }  // extern "C"

@@ -256,3 +256,12 @@ def test_bege_validation_without_device(P):
     assert call(4, 10, 100, r=None) == P.PPS_EINVAL
     assert call(4, 10, 100, ll=None) == P.PPS_EINVAL
     assert b"n_omega" in L.pps_last_error() or L.pps_last_error()
+
+
+def test_bege_count_ops_validation_without_device(P):
+    import ctypes as C
+    L = P.lib()
+    ops = C.c_double()
+    assert L.pps_bege_count_ops(1, 4, 1, 10, 100, None, None) == P.PPS_EINVAL
+    assert L.pps_bege_count_ops(1, 0, 1, 10, 100, C.byref(ops), None) == P.PPS_EINVAL
+    assert L.pps_bege_count_ops(None, 4, 1, 10, 100, C.byref(ops), None) == P.PPS_EINVAL

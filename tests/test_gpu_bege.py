@@ -13,7 +13,7 @@ error of a few ulps of its largest term, and the oracle's two sums carry up
 to N_omega ulps each, so the numerator F(u + h) - F(u - h) = 2h f may differ
 by
 
-    tol_F = 2^-46 (1 + a (1 + |ln a|)),   a = max(p_{t-1}, n_{t-1}) + N_omega / 100,
+    tol_F = 2^-45 (1 + a (1 + |ln a|)),   a = max(p_{t-1}, n_{t-1}) + N_omega / 100,
 
 and the log density by tol_F / (2h f).  A step whose oracle numerator is
 itself below tol_F is not resolved by either side: there only "both are
@@ -81,7 +81,7 @@ def compare(P, thetas, r, n_omega=100, label=""):
         with np.errstate(invalid="ignore"):
             h2 = 2e-3 * np.sqrt(th[1] ** 2 * np.where(valid, ps, 0) + th[6] ** 2 * np.where(valid, ns, 0))
         a = np.maximum(ps, ns) + n_omega / 100.0
-        tol_f = 2.0 ** -46 * (1.0 + a * (1.0 + np.abs(np.log(np.maximum(a, 1e-300)))))
+        tol_f = 2.0 ** -45 * (1.0 + a * (1.0 + np.abs(np.log(np.maximum(a, 1e-300)))))
         num_o = h2 * np.exp(o["logdens"])          # 2h f of the oracle (0 where -inf)
         num_g = h2 * np.exp(gld[k])
         res = valid & (num_o > tol_f)
@@ -174,3 +174,18 @@ def test_bege_full_batch_sampled(P, torch, series):
 def test_bege_invalid(P, torch, series):
     with pytest.raises(P.PPSError):
         P.pps_bege_loglik(W.bege_prior_draws(2), series, n_omega=1)
+
+
+def test_bege_count_ops(P, torch, series):
+    """The counting instantiation reports the work of the same batch: more
+    work for more nodes, none lost between calls, and results unchanged."""
+    th = W.bege_prior_draws(32, seed=9)
+    a = P.pps_bege_count_ops(th, series[:200], 100)
+    b = P.pps_bege_count_ops(th, series[:200], 100)
+    c = P.pps_bege_count_ops(th, series[:200], 200)
+    assert a == b and a > 0 and c > 1.5 * a
+    # at least the fixed work of every valid step: two lgammas and one log
+    assert a > 32 * 199 * 0.5 * (2 * 200 + 90)
+    ll = P.pps_bege_loglik(th, series[:200])["loglik"].cpu().numpy()
+    ll2 = P.pps_bege_loglik(th, series[:200])["loglik"].cpu().numpy()
+    np.testing.assert_array_equal(ll, ll2)
