@@ -44,7 +44,8 @@ enum { P0, SP, RP, PPOS, PNEG, N0, SN, RN, NPOS, NNEG, MU };
 // division 1, and the library functions at the FP64 operations of their
 // gfx950 code (exp 32 and log 90, both branch-free; lgamma ~200; sqrt 1).
 constexpr double OPS_EXP = 32.0, OPS_LOG = 90.0, OPS_LGAMMA = 200.0;
-constexpr double OPS_SERIES_IT = 6.0, OPS_CF_IT = 13.0, OPS_IGAM_FIXED = OPS_LOG + OPS_EXP + 6.0;
+constexpr double OPS_SERIES_IT = 5.0, OPS_SERIES_CHECK = 1.0, OPS_CF_IT = 10.0, OPS_CF_CHECK = 4.0;
+constexpr double OPS_IGAM_FIXED = OPS_LOG + OPS_EXP + 6.0;
 constexpr double OPS_TAYLOR = 62.0 + OPS_LOG + OPS_EXP;
 
 template <bool COUNT>
@@ -70,57 +71,102 @@ struct OpCount {
 //     recurrences (A, B)_i = b_i (A, B)_{i-1} + a_i (A, B)_{i-2}; it stops
 //     once successive values of 1/K agree to 2^-53, i.e.
 //     |B_i A_{i-1} - A_i B_{i-1}| < 2^-53 |A_i B_{i-1}|.
-// N, D, X (and A, B) are scaled by 2^-600 together when they grow large:
-// exact, and their ratios are all that is used.
+// Both loops run in blocks (8 series terms, 4 fraction steps) and test
+// convergence and scale at the end of a block: a block adds at most a few
+// terms past the cut, each below 2^-53 of the result.  One term multiplies
+// the values by at most a + k (series) or x + a + 4k (fraction), so a block
+// grows them by less than 2^400 while a, x < 2^40 (shapes within the priors
+// stay far below); larger arguments take blocks of one term, safe up to
+// 2^400.  N, D, X (and A, B) are scaled by 2^-600 together when they pass
+// 2^600: exact, and only their ratios are used.
+template <int BLK>
+__device__ __forceinline__ double igam_series(double a, double x, int &k)
+{
+    double n = 1.0, d = 1.0, xm = 1.0, ak = a;
+    k = 0;
+    do {
+#pragma unroll
+        for (int u = 0; u < BLK; ++u) {
+            ak += 1.0;
+            xm *= x;
+            n = fma(n, ak, xm);
+            d *= ak;
+        }
+        k += BLK;
+        if (xm < n * IG_EPS)
+            break;
+        if (d > 0x1p600) {
+            n *= 0x1p-600;
+            d *= 0x1p-600;
+            xm *= 0x1p-600;
+        }
+    } while (k < IG_MAXIT);
+    return n / (a * d);
+}
+
+// 1/K; steps in pairs so that (A1, B1) is always the latest convergent and
+// (A0, B0) the one before.
+template <int BLK>
+__device__ __forceinline__ double igam_fraction(double a, double x, int &i)
+{
+    double A0 = 1.0, A1 = x + 1.0 - a, B0 = 0.0, B1 = 1.0, bi = A1, di = 0.0;
+    i = 0;
+    do {
+#pragma unroll
+        for (int u = 0; u < BLK; ++u) {
+            di += 1.0;
+            bi += 2.0;
+            const double ai = -di * (di - a);
+            if (u % 2 == 0) {
+                A0 = fma(bi, A1, ai * A0);
+                B0 = fma(bi, B1, ai * B0);
+            } else {
+                A1 = fma(bi, A0, ai * A1);
+                B1 = fma(bi, B0, ai * B1);
+            }
+        }
+        if (BLK % 2 == 1) {
+            // odd block: bring the latest convergent back to (A1, B1)
+            const double ta = A0, tb = B0;
+            A0 = A1;
+            B0 = B1;
+            A1 = ta;
+            B1 = tb;
+        }
+        i += BLK;
+        const double cross = A1 * B0;
+        const double diff = fma(B1, A0, -cross);
+        if (fabs(diff) < IG_EPS * fabs(cross))
+            break;
+        if (fabs(A1) > 0x1p600) {
+            A0 *= 0x1p-600;
+            A1 *= 0x1p-600;
+            B0 *= 0x1p-600;
+            B1 *= 0x1p-600;
+        }
+    } while (i < IG_MAXIT);
+    return B1 / A1;
+}
+
+constexpr int SERIES_BLOCK = 8;
+constexpr int CF_BLOCK = 4;
+
 template <bool COUNT>
 __device__ __attribute__((noinline)) double igam_p(double a, double x, double lga, OpCount<COUNT> &ops)
 {
     if (!(x > 0.0))
         return 0.0;
     const double e = a * log(x) - x - lga;
+    const bool blocked = a < 0x1p40 && x < 0x1p40;
+    int it;
     if (x < a + 1.0) {
-        double n = 1.0, d = 1.0, xm = 1.0, ak = a;
-        int k = 1;
-        for (; k < IG_MAXIT; ++k) {
-            ak += 1.0;
-            xm *= x;
-            n = fma(n, ak, xm);
-            d *= ak;
-            if (xm < n * IG_EPS)
-                break;
-            if (d > 0x1p600) {
-                n *= 0x1p-600;
-                d *= 0x1p-600;
-                xm *= 0x1p-600;
-            }
-        }
-        ops.add(OPS_IGAM_FIXED + OPS_SERIES_IT * k);
-        return exp(e) * (n / (a * d));
+        const double s = blocked ? igam_series<SERIES_BLOCK>(a, x, it) : igam_series<1>(a, x, it);
+        ops.add(OPS_IGAM_FIXED + OPS_SERIES_IT * it + OPS_SERIES_CHECK * (it / (blocked ? SERIES_BLOCK : 1)));
+        return exp(e) * s;
     }
-    double am = 1.0, A = x + 1.0 - a, bm = 0.0, B = 1.0, bi = A;
-    int i = 1;
-    for (; i < IG_MAXIT; ++i) {
-        const double ai = -i * (i - a);
-        bi += 2.0;
-        const double An = fma(bi, A, ai * am);
-        const double Bn = fma(bi, B, ai * bm);
-        const double cross = An * B;
-        const double diff = fma(Bn, A, -cross);
-        am = A;
-        A = An;
-        bm = B;
-        B = Bn;
-        if (fabs(diff) < IG_EPS * fabs(cross))
-            break;
-        if (fabs(A) > 0x1p600) {
-            am *= 0x1p-600;
-            A *= 0x1p-600;
-            bm *= 0x1p-600;
-            B *= 0x1p-600;
-        }
-    }
-    ops.add(OPS_IGAM_FIXED + OPS_CF_IT * i);
-    return 1.0 - exp(e) * (B / A);
+    const double f = blocked ? igam_fraction<CF_BLOCK>(a, x, it) : igam_fraction<1>(a, x, it);
+    ops.add(OPS_IGAM_FIXED + OPS_CF_IT * it + OPS_CF_CHECK * (it / (blocked ? CF_BLOCK : 1)));
+    return 1.0 - exp(e) * f;
 }
 
 // Cost class of a chunk from the largest shape p among its valid steps: the
