@@ -8,8 +8,9 @@
 // data, so the T densities of a parameter vector are independent and go one
 // per lane, 64 consecutive t of one vector per wave (neighbouring t have
 // similar shapes, so the lanes' series lengths stay close).  Kernels:
-//   k_bege_shapes   one lane per vector: the recursion of Eq. shape, and a
-//                   cost class per chunk of 64 steps from its largest shape;
+//   k_bege_shapes   one wave per vector: the recursion of Eq. shape as a scan
+//                   over chunks of 64 steps, and a cost class per chunk from
+//                   its largest shape;
 //   k_bege_order    one workgroup: the chunks in decreasing cost class;
 //   k_bege_density  one lane per (vector, t): log f(u_t | p_{t-1}, n_{t-1}),
 //                   chunks taken in that order so that the long waves (large
@@ -181,35 +182,86 @@ __device__ __forceinline__ int cost_class(double pmax)
     return c < 1 ? 1 : (c > N_COST_CLASSES - 1 ? N_COST_CLASSES - 1 : c);
 }
 
+// The recursion p_t = rho p_{t-1} + c_t, c_t = p0 + phi^{+/-} u_t^2 / (2 s^2),
+// is affine with a constant multiplier, so a wave scans it 64 steps at a
+// time: lane j of a chunk starting at step t_c holds c_{t_c + j}, an
+// inclusive scan v_j = sum_{s <= j} rho^{j-s} c_{t_c + s} takes six shuffle
+// steps, and the shape meeting step t_c + j is rho^j P + v_{j-1}, P the
+// shape carried into the chunk (p_{t_c - 1}).  One wave per vector; the
+// shapes leave as contiguous rows.  (The sums are associated differently
+// from the step-by-step recursion: rounding-level differences.)
+__device__ __forceinline__ double shfl_up_f64(double v, int d)
+{
+    return __shfl_up(v, d, 64);
+}
+
 __global__ __launch_bounds__(SHAPES_BLOCK) void k_bege_shapes(BegeBatch b)
 {
-    const int k = blockIdx.x * SHAPES_BLOCK + threadIdx.x;
-    if (k >= b.n_theta)
-        return;
+    static_assert(SHAPES_BLOCK == 64 && DENSITY_BLOCK == 64, "one wave per vector, chunks of 64");
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
     const double *th = b.theta + static_cast<size_t>(k) * BEGE_NPAR;
     const double p0 = th[P0], sp = th[SP], rp = th[RP], ppos = th[PPOS], pneg = th[PNEG];
     const double n0 = th[N0], sn = th[SN], rn = th[RN], npos = th[NPOS], nneg = th[NNEG];
     const double mu = th[MU];
     const double cp = 0.5 / (sp * sp), cn = 0.5 / (sn * sn);
+    const bool scales_ok = sp > 0.0 && sn > 0.0;
+    // rho^j for this lane and rho^(2^i) for the scan (squarings)
+    double rpow[6], npow[6];
+    rpow[0] = rp;
+    npow[0] = rn;
+#pragma unroll
+    for (int i = 1; i < 6; ++i) {
+        rpow[i] = rpow[i - 1] * rpow[i - 1];
+        npow[i] = npow[i - 1] * npow[i - 1];
+    }
+    double rj = 1.0, nj = 1.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        if (lane & (1 << i)) {
+            rj *= rpow[i];
+            nj *= npow[i];
+        }
+    const double r64 = rpow[5] * rpow[5], n64 = npow[5] * npow[5];
+    double P = p0, N = n0;  // shapes carried into the chunk
     double *outp = b.shape_p + static_cast<size_t>(k) * b.T;
     double *outn = b.shape_n + static_cast<size_t>(k) * b.T;
-    int32_t *cls = b.chunk_class + static_cast<size_t>(k) * b.chunks;
-    const bool scales_ok = sp > 0.0 && sn > 0.0;
-    double p = p0, n = n0, pmax = 0.0;
-    for (int t = 1; t <= b.T; ++t) {
-        outp[t - 1] = p;
-        outn[t - 1] = n;
-        if (scales_ok && p > 0.0 && n > 0.0)
-            pmax = fmax(pmax, p);
-        if (t % DENSITY_BLOCK == 0 || t == b.T) {
-            cls[(t - 1) / DENSITY_BLOCK] = cost_class(pmax);
-            pmax = 0.0;
-        }
-        const double u = b.r[t] - mu;
+    for (int c = 0; c < b.chunks; ++c) {
+        const int t = c * DENSITY_BLOCK + lane + 1;
+        const bool in = t <= b.T;
+        const double u = in ? b.r[t] - mu : 0.0;
         const double u2 = u * u;
         const bool pos = u >= 0.0;
-        p = p0 + rp * p + (pos ? ppos : pneg) * u2 * cp;
-        n = n0 + rn * n + (pos ? npos : nneg) * u2 * cn;
+        double vp = in ? p0 + (pos ? ppos : pneg) * u2 * cp : 0.0;
+        double vn = in ? n0 + (pos ? npos : nneg) * u2 * cn : 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const int d = 1 << i;
+            const double op = shfl_up_f64(vp, d), on = shfl_up_f64(vn, d);
+            if (lane >= d) {
+                vp = fma(rpow[i], op, vp);
+                vn = fma(npow[i], on, vn);
+            }
+        }
+        // exclusive value v_{j-1} and the shape meeting step t
+        const double ep = shfl_up_f64(vp, 1), en = shfl_up_f64(vn, 1);
+        const double shp = fma(rj, P, lane > 0 ? ep : 0.0);
+        const double shn = fma(nj, N, lane > 0 ? en : 0.0);
+        if (in) {
+            outp[t - 1] = shp;
+            outn[t - 1] = shn;
+        }
+        // carry: p at the chunk's last step = rho^64 P + v_63
+        const double last_p = __shfl(vp, 63, 64), last_n = __shfl(vn, 63, 64);
+        P = fma(r64, P, last_p);
+        N = fma(n64, N, last_n);
+        // cost class from the largest valid shape of the chunk
+        double pm = (in && scales_ok && shp > 0.0 && shn > 0.0) ? shp : 0.0;
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1)
+            pm = fmax(pm, __shfl_xor(pm, m, 64));
+        if (lane == 0)
+            b.chunk_class[static_cast<size_t>(k) * b.chunks + c] = cost_class(pm);
     }
 }
 
@@ -382,8 +434,7 @@ int bege_chunks(int T)
 
 hipError_t launch_bege(const BegeBatch &b, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    const int shape_grid = (b.n_theta + SHAPES_BLOCK - 1) / SHAPES_BLOCK;
-    hipLaunchKernelGGL(k_bege_shapes, dim3(shape_grid), dim3(SHAPES_BLOCK), 0, s, b);
+    hipLaunchKernelGGL(k_bege_shapes, dim3(b.n_theta), dim3(SHAPES_BLOCK), 0, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
