@@ -47,14 +47,16 @@ _SRCS = [os.path.join(_HERE, "pps_oracle.c"), os.path.join(_HERE, "wip_oracle.c"
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 UNIFORM, NORMAL, LOGNORMAL, POINT = 0, 1, 2, 3
-LOGISTIC, GARCH11, NORMAL_MEAN, TOGGLE_SWITCH = 0, 1, 2, 3
+LOGISTIC, GARCH11, NORMAL_MEAN, TOGGLE_SWITCH, TB = 0, 1, 2, 3, 4
+TB_COMPLETE, TB_EXTINCT, TB_TRUNCATED = 0, 1, 2
+TB_PURPOSE_EVENT, TB_PURPOSE_SAMPLE = 0x90000000, 0x90000001
 MAX_PARAMS = 8
 EPS_FIXED, EPS_TOP_FRACTION = 0, 1
 GARCH_NSUMM = 14
 
 _FAMILY = {"uniform": UNIFORM, "normal": NORMAL, "lognormal": LOGNORMAL, "point": POINT}
 _MODEL = {"logistic": LOGISTIC, "garch11": GARCH11, "normal_mean": NORMAL_MEAN,
-          "toggle_switch": TOGGLE_SWITCH}
+          "toggle_switch": TOGGLE_SWITCH, "tb": TB}
 
 
 def build(force: bool = True) -> str:
@@ -136,6 +138,22 @@ def _load():
         lib.or_simulate.argtypes = [mp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                     ctypes.c_void_p, f64p, f64p, f64p, f64p, i32p]
         lib.or_simulate.restype = ctypes.c_int
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        lib.or_tb_select.argtypes = [u32p, ctypes.c_int, ctypes.c_uint64]
+        lib.or_tb_select.restype = ctypes.c_int
+        lib.or_tb_lowest_empty.argtypes = [u32p, ctypes.c_int]
+        lib.or_tb_lowest_empty.restype = ctypes.c_int
+        lib.or_tb_thresholds.argtypes = [f64p, ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_uint64)]
+        lib.or_tb_run.argtypes = [f64p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                  ctypes.c_uint64, u32p, ctypes.POINTER(ctypes.c_uint64),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+        lib.or_tb_run.restype = ctypes.c_int
+        lib.or_tb_summaries.argtypes = [u32p, u32p, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
+                                        ctypes.c_uint64, ctypes.c_uint64, f64p]
+        lib.or_tb_simulate.argtypes = [mp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, f64p,
+                                       i32p, u64p, u64p, f64p]
+        lib.or_tb_simulate.restype = ctypes.c_int
         lib.or_top_count.argtypes = [ctypes.c_double, ctypes.c_uint64]
         lib.or_top_count.restype = ctypes.c_uint64
         lib.or_abc.argtypes = [mp, f64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
@@ -203,7 +221,7 @@ def _model(spec: Mapping) -> _Model:
         m.prior[j].family = _FAMILY[fam]
         m.prior[j].a = float(a)
         m.prior[j].b = float(b)
-    m.constraint = 1 if spec.get("constraint") == "garch_stationary" else 0
+    m.constraint = {"garch_stationary": 1, "tb_supercritical": 2}.get(spec.get("constraint"), 0)
     m.x0 = float(spec.get("x0", 0.0))
     m.t_end = float(spec.get("t_end", 0.0))
     m.steps = int(spec.get("steps", 0))
@@ -507,3 +525,55 @@ def bege_simulate(theta, T: int, seed: int) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle: a BEGE shape became non-positive")
     return r
+
+
+# ---- tuberculosis transmission (App. B) -------------------------------------
+
+def tb_select(counts, m: int) -> int:
+    """Slot of case m in slot order (the lookup over genotype weights)."""
+    x = np.ascontiguousarray(counts, np.uint32)
+    return int(_load().or_tb_select(x, len(x), m))
+
+
+def tb_lowest_empty(counts) -> int:
+    x = np.ascontiguousarray(counts, np.uint32)
+    return int(_load().or_tb_lowest_empty(x, len(x)))
+
+
+def tb_thresholds(theta) -> tuple[int, int]:
+    tb, td = ctypes.c_uint64(), ctypes.c_uint64()
+    _load().or_tb_thresholds(np.ascontiguousarray(theta, np.float64), ctypes.byref(tb), ctypes.byref(td))
+    return tb.value, td.value
+
+
+def tb_run(theta, n_stop: int, seed: int, draw: int, max_events: int = 2**31 - 1,
+           x0: float = 1.0) -> dict:
+    """One run at theta = (alpha, delta, tau): status, events, final N and
+    the final case counts per genotype slot."""
+    X = np.zeros(n_stop, np.uint32)
+    ev, N = ctypes.c_uint64(), ctypes.c_uint64()
+    st = _load().or_tb_run(np.ascontiguousarray(theta, np.float64), n_stop, x0, max_events, seed, draw,
+                           X, ctypes.byref(ev), ctypes.byref(N))
+    return {"status": int(st), "events": int(ev.value), "n": int(N.value), "counts": X}
+
+
+def tb_summaries(counts, n_sample: int, seed: int, draw: int) -> np.ndarray:
+    X = np.array(counts, np.uint32)
+    Y = np.zeros_like(X)
+    out = np.zeros(2, np.float64)
+    _load().or_tb_summaries(X, Y, len(X), int(X.sum()), n_sample, seed, draw, out)
+    return out
+
+
+def tb_simulate(spec: Mapping, seed: int, first: int, n: int) -> dict:
+    """Per draw: theta, status, events, final N, summaries (g/n_s, H)."""
+    m = _model(spec)
+    theta = np.zeros((n, 3), np.float64)
+    status = np.zeros(n, np.int32)
+    events = np.zeros(n, np.uint64)
+    nf = np.zeros(n, np.uint64)
+    summ = np.zeros((n, 2), np.float64)
+    rc = _load().or_tb_simulate(ctypes.byref(m), seed, first, n, theta, status, events, nf, summ)
+    if rc != 0:
+        raise ValueError("oracle: invalid tuberculosis model")
+    return {"theta": theta, "status": status, "events": events, "n": nf, "summ": summ}

@@ -172,8 +172,8 @@ static double reader_next(normal_reader *r)
 /* Model description (plain data; independent of the GPU library's structs). */
 /* ------------------------------------------------------------------------ */
 enum { OR_UNIFORM = 0, OR_NORMAL = 1, OR_LOGNORMAL = 2, OR_POINT = 3 };
-enum { OR_LOGISTIC = 0, OR_GARCH11 = 1, OR_NORMAL_MEAN = 2, OR_TOGGLE_SWITCH = 3 };
-enum { OR_NO_CONSTRAINT = 0, OR_GARCH_STATIONARY = 1 };
+enum { OR_LOGISTIC = 0, OR_GARCH11 = 1, OR_NORMAL_MEAN = 2, OR_TOGGLE_SWITCH = 3, OR_TB = 4 };
+enum { OR_NO_CONSTRAINT = 0, OR_GARCH_STATIONARY = 1, OR_TB_SUPERCRITICAL = 2 };
 #define OR_MAX_PARAMS 8
 #define OR_MAX_ATTEMPTS 32
 #define OR_GARCH_LAGS 10
@@ -194,9 +194,11 @@ typedef struct {
     int32_t steps;    /* logistic, toggle switch: Euler-Maruyama steps S;
                          GARCH: series length */
     int32_t n_obs;    /* logistic: observations; normal-mean: sample size;
-                         toggle switch: number of quantiles */
+                         toggle switch: number of quantiles; tuberculosis:
+                         cases sampled at the end */
     double noise_sd;  /* normal-mean: observation sd */
-    int32_t n_cells;  /* toggle switch: cells C */
+    int32_t n_cells;  /* toggle switch: cells C; tuberculosis: the population
+                         size at which a run stops */
 } or_model;
 
 /* One prior value from PRIOR block (8*attempt + j): uniform from word 0,
@@ -232,9 +234,12 @@ int or_prior_draw(const or_model *m, uint64_t seed, uint64_t draw, double *theta
     for (;;) {
         for (int j = 0; j < m->n_params; ++j)
             theta[j] = prior_value(&m->prior[j], seed, draw, j, attempt);
-        if (m->constraint != OR_GARCH_STATIONARY)
-            return attempt + 1;
-        if (theta[1] + theta[2] < 1.0 || attempt + 1 == OR_MAX_ATTEMPTS)
+        int ok = 1;
+        if (m->constraint == OR_GARCH_STATIONARY)
+            ok = theta[1] + theta[2] < 1.0;
+        else if (m->constraint == OR_TB_SUPERCRITICAL)
+            ok = theta[0] > theta[1] && theta[2] > 0.0;
+        if (ok || attempt + 1 == OR_MAX_ATTEMPTS)
             return attempt + 1;
         ++attempt;
     }
@@ -410,10 +415,198 @@ static void simulate_toggle(const or_model *m, const double *theta, uint64_t see
 }
 
 /* Number of summaries (the "data" D of one draw) a model produces.          */
+/* ------------------------------------------------------------------------ */
+/* Tuberculosis transmission (App. B): a birth-death process of cases with  */
+/* mutation to new genotypes, simulated event by event by the Gillespie     */
+/* direct method.                                                           */
+/* ------------------------------------------------------------------------ */
+enum { OR_PURPOSE_TB_EVENT = 0x90000000u, OR_PURPOSE_TB_SAMPLE = 0x90000001u };
+enum { OR_TB_COMPLETE = 0, OR_TB_EXTINCT = 1, OR_TB_TRUNCATED = 2 };
+
+/* The genotype holding case m (0 <= m < sum X) in slot order: the lookup
+ * over the genotype weights, i.e. the smallest i with X_0 + ... + X_i > m.   */
+int or_tb_select(const uint32_t *X, int S, uint64_t m)
+{
+    uint64_t acc = 0;
+    for (int i = 0; i < S; ++i) {
+        acc += X[i];
+        if (acc > m)
+            return i;
+    }
+    return -1;
+}
+
+/* The lowest slot holding no case (where a new genotype is founded).        */
+int or_tb_lowest_empty(const uint32_t *X, int S)
+{
+    for (int i = 0; i < S; ++i)
+        if (X[i] == 0)
+            return i;
+    return -1;
+}
+
+/* A uniform integer in [0, n) from a 32-bit word: floor(w n / 2^32).       */
+static uint64_t tb_scale(uint32_t w, uint64_t n)
+{
+    return ((uint64_t)w * n) >> 32;
+}
+
+/* Event-type thresholds on a 32-bit word: birth below floor(2^32 alpha/R),
+ * death below floor(2^32 (alpha + delta)/R), mutation above; R = alpha +
+ * delta + tau.  The sums and quotients are single IEEE FP64 operations.      */
+void or_tb_thresholds(const double *theta, uint64_t *t_birth, uint64_t *t_death)
+{
+    const double ad = theta[0] + theta[1];
+    const double r = ad + theta[2];
+    *t_birth = (uint64_t)floor(ldexp(theta[0] / r, 32));
+    *t_death = (uint64_t)floor(ldexp(ad / r, 32));
+}
+
+/* One run at theta = (alpha, delta, tau) (event rates per case: birth,
+ * death, mutation).  X (n_stop slots, zeroed here) receives the final case
+ * counts per genotype slot.  Start: x0 cases of one genotype in slot 0.
+ * While 0 < N < n_stop and fewer than max_events events have happened:
+ * event e draws words (w_case, w_type) = words (2(e%2), 2(e%2)+1) of block
+ * e/2 of stream purpose 0x90000000; the case is number floor(w_case N/2^32)
+ * and its genotype the lookup above; the event type follows the thresholds;
+ * birth adds a case to the genotype, death removes one, mutation removes one
+ * and founds a new genotype with one case in the lowest empty slot (after
+ * the removal).  The waiting times of the direct method do not enter the
+ * stopped state and are not drawn.  Returns the status (complete: N reached
+ * n_stop; extinct; truncated) and the number of events.                      */
+int or_tb_run(const double *theta, int n_stop, double x0, uint64_t max_events, uint64_t seed,
+              uint64_t draw, uint32_t *X, uint64_t *events, uint64_t *n_final)
+{
+    for (int i = 0; i < n_stop; ++i)
+        X[i] = 0;
+    uint64_t tb, td;
+    or_tb_thresholds(theta, &tb, &td);
+    uint64_t N = (uint64_t)x0;
+    if (N > (uint64_t)n_stop)
+        N = (uint64_t)n_stop;
+    X[0] = (uint32_t)N;
+    uint64_t e = 0;
+    uint32_t w[4] = {0, 0, 0, 0};
+    int status;
+    for (;;) {
+        if (N >= (uint64_t)n_stop) {
+            status = OR_TB_COMPLETE;
+            break;
+        }
+        if (N == 0) {
+            status = OR_TB_EXTINCT;
+            break;
+        }
+        if (e >= max_events) {
+            status = OR_TB_TRUNCATED;
+            break;
+        }
+        if (e % 2 == 0)
+            or_stream_block(seed, draw, (uint32_t)(e / 2), OR_PURPOSE_TB_EVENT, w);
+        const uint32_t w_case = w[2 * (e % 2)], w_type = w[2 * (e % 2) + 1];
+        const int i = or_tb_select(X, n_stop, tb_scale(w_case, N));
+        if ((uint64_t)w_type < tb) {
+            X[i] += 1;
+            N += 1;
+        } else if ((uint64_t)w_type < td) {
+            X[i] -= 1;
+            N -= 1;
+        } else {
+            X[i] -= 1;
+            X[or_tb_lowest_empty(X, n_stop)] = 1;
+        }
+        ++e;
+    }
+    *events = e;
+    *n_final = N;
+    return status;
+}
+
+/* Summaries of the final population: n cases drawn without replacement
+ * (draw s: word s%4 of block s/4 of stream purpose 0x90000001, the case
+ * floor(w (N - s)/2^32) of those left, looked up as above), or all N cases
+ * when N < n; g = the number of distinct genotypes among them and
+ * H = 1 - sum_i (n_i/n_s)^2 (the gene diversity), n_s the cases taken.
+ * summ = (g/n_s, H); (0, 0) for an empty population.  X is consumed; Y
+ * (n_stop slots) is workspace.                                               */
+void or_tb_summaries(uint32_t *X, uint32_t *Y, int n_stop, uint64_t N, int n, uint64_t seed,
+                     uint64_t draw, double *summ)
+{
+    if (N == 0) {
+        summ[0] = 0.0;
+        summ[1] = 0.0;
+        return;
+    }
+    uint64_t ns;
+    if (N >= (uint64_t)n) {
+        ns = (uint64_t)n;
+        for (int i = 0; i < n_stop; ++i)
+            Y[i] = 0;
+        uint32_t w[4];
+        for (uint64_t s = 0; s < ns; ++s) {
+            if (s % 4 == 0)
+                or_stream_block(seed, draw, (uint32_t)(s / 4), OR_PURPOSE_TB_SAMPLE, w);
+            const int i = or_tb_select(X, n_stop, tb_scale(w[s % 4], N - s));
+            X[i] -= 1;
+            Y[i] += 1;
+        }
+    } else {
+        ns = N;
+        for (int i = 0; i < n_stop; ++i)
+            Y[i] = X[i];
+    }
+    uint64_t g = 0, sq = 0;
+    for (int i = 0; i < n_stop; ++i) {
+        g += Y[i] > 0;
+        sq += (uint64_t)Y[i] * Y[i];
+    }
+    summ[0] = (double)g / (double)ns;
+    summ[1] = 1.0 - (double)sq / ((double)ns * (double)ns);
+}
+
+static void simulate_tb(const or_model *m, const double *theta, uint64_t seed, uint64_t draw,
+                        double *summ, double *work)
+{
+    uint32_t *X = (uint32_t *)work;
+    uint32_t *Y = X + m->n_cells;
+    uint64_t events, N;
+    or_tb_run(theta, m->n_cells, m->x0, (uint64_t)(uint32_t)m->steps, seed, draw, X, &events, &N);
+    or_tb_summaries(X, Y, m->n_cells, N, m->n_obs, seed, draw, summ);
+}
+
+/* Per draw: theta, status, events, final N and summaries (for tests and the
+ * event-rate figures).                                                       */
+int or_tb_simulate(const or_model *m, uint64_t seed, uint64_t first, uint64_t n, double *theta,
+                   int32_t *status, uint64_t *events, uint64_t *n_final, double *summ)
+{
+    if (m->model != OR_TB || m->n_params != 3 || m->n_cells < 1 || m->n_obs < 1)
+        return -1;
+#pragma omp parallel
+    {
+        uint32_t *X = (uint32_t *)malloc(2 * (size_t)m->n_cells * sizeof(uint32_t));
+#pragma omp for schedule(dynamic, 1)
+        for (uint64_t q = 0; q < n; ++q) {
+            const uint64_t draw = first + q;
+            double *th = &theta[q * 3];
+            or_prior_draw(m, seed, draw, th);
+            uint64_t ev, N;
+            status[q] = or_tb_run(th, m->n_cells, m->x0, (uint64_t)(uint32_t)m->steps, seed, draw, X,
+                                  &ev, &N);
+            events[q] = ev;
+            n_final[q] = N;
+            or_tb_summaries(X, X + m->n_cells, m->n_cells, N, m->n_obs, seed, draw, &summ[q * 2]);
+        }
+        free(X);
+    }
+    return 0;
+}
+
 int or_n_summaries(const or_model *m)
 {
     if (m->model == OR_GARCH11)
         return OR_GARCH_NSUMM;
+    if (m->model == OR_TB)
+        return 2;
     return m->n_obs;
 }
 
@@ -430,6 +623,9 @@ static void simulate_summaries(const or_model *m, const double *theta, uint64_t 
         break;
     case OR_TOGGLE_SWITCH:
         simulate_toggle(m, theta, seed, draw, summ, work);
+        break;
+    case OR_TB:
+        simulate_tb(m, theta, seed, draw, summ, work);
         break;
     case OR_GARCH11:
     default:
@@ -470,6 +666,8 @@ static int model_ok(const or_model *m)
     if (m->model == OR_TOGGLE_SWITCH)
         return m->n_params == 7 && m->steps > 0 && m->t_end > 0.0 && m->n_cells > 0 &&
                m->n_obs > 0;
+    if (m->model == OR_TB)
+        return m->n_params == 3 && m->n_cells > 0 && m->n_obs > 0 && m->x0 >= 1.0;
     return 0;
 }
 
@@ -479,6 +677,8 @@ static size_t work_len(const or_model *m)
         return (size_t)m->steps;
     if (m->model == OR_TOGGLE_SWITCH)
         return (size_t)m->n_cells;
+    if (m->model == OR_TB)
+        return (size_t)m->n_cells;  /* two uint32 arrays of n_cells */
     return 1;
 }
 

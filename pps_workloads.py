@@ -144,6 +144,34 @@ def bege_prior_draws(n: int, seed: int = 7) -> np.ndarray:
     return lo + (hi - lo) * rng.uniform(size=(n, len(BEGE_PRIORS)))
 
 
+# Tuberculosis transmission (App. B): a linear birth-death process of cases
+# (birth rate alpha, death rate delta per case) with mutation to new genotypes
+# (rate tau per case), simulated event by event from one case until the
+# population reaches n_stop cases (the stopping size of Tanaka et al.) or dies
+# out, at most max_events events; n_sample cases are then drawn without
+# replacement (473 isolates in the San Francisco data the paper cites, not
+# available here).  Summaries: distinct genotypes / n_sample and gene
+# diversity.  Priors: alpha, delta ~ U(0, 5) with alpha > delta (a growing
+# epidemic), tau ~ N(0.198, 0.06735) with tau > 0 (Tanaka et al.'s mutation
+# rate prior); the paper prints none.
+TB_PRIORS = [("uniform", 0.0, 5.0), ("uniform", 0.0, 5.0), ("normal", 0.198, 0.06735)]
+TB_THETA_OBS = (1.0, 0.4, 0.2)
+TB_PPS = {"name": "tb_gillespie_N16000_K10000_n473", "n": 16000, "n_stop": 10000, "n_sample": 473,
+          "max_events": 1 << 20}
+
+
+def tb_spec(n_stop: int = 10000, n_sample: int = 473, max_events: int = 1 << 20, priors=None,
+            x0: float = 1.0) -> dict:
+    return {"model": "tb", "priors": list(priors or TB_PRIORS), "constraint": "tb_supercritical",
+            "x0": x0, "steps": max_events, "n_obs": n_sample, "n_cells": n_stop}
+
+
+def tb_point_spec(theta=TB_THETA_OBS, **kw) -> dict:
+    """The tuberculosis model with every prior a point mass (used to make
+    the synthetic observed summaries)."""
+    return tb_spec(priors=[("point", float(t), 0.0) for t in theta], **kw)
+
+
 def lambda_grid(n: int = 64, lo: float = 0.05, hi: float = 3.0) -> np.ndarray:
     """n log-spaced values from lo to hi (inclusive)."""
     k = np.arange(n, dtype=np.float64)

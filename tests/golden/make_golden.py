@@ -13,6 +13,10 @@ prior-predictive simulation at a fixed theta (point priors), seed 0, draw 0:
 * BEGE volatility model, theta = (0.3, 0.02, 0.9, 0.01, 0.03, 0.04, 0.02,
   0.85, 0.01, 0.3, 0.008), T = 1099, seed 11 -> the returns r_0..r_T (the
   S&P series of the paper is not available; this stands in for it);
+* tuberculosis transmission, theta = (1, 0.4, 0.2), population stop 10000,
+  473 cases sampled: the first draw (seed 0) whose epidemic reaches the stop
+  size -> (distinct genotypes / 473, gene diversity) (the San Francisco data
+  the paper cites are not available; this stands in for them);
 * the fixed tolerance of the 1e7-draw ABC workload: the 0.1% distance
   quantile of the oracle's pilot on draws [0, 1e5) of the sampling seed
   (the 100th smallest distance, type-1 inverse empirical CDF).
@@ -62,6 +66,17 @@ def main():
                                 "steps": tspec["steps"],
                                 "y_obs": [float(v) for v in ts["summ"][0]],
                                 "t_obs": float(ts["stat"][0])}
+    tspec_tb = W.tb_point_spec()
+    tb_draw = 0
+    while True:
+        tr = oracle.tb_simulate(tspec_tb, W.OBS_SEED, tb_draw, 1)
+        if tr["status"][0] == oracle.TB_COMPLETE:
+            break
+        tb_draw += 1
+    out["tb_K10000_n473"] = {"theta": list(W.TB_THETA_OBS), "seed": W.OBS_SEED, "draw": tb_draw,
+                             "n_stop": tspec_tb["n_cells"], "n_sample": tspec_tb["n_obs"],
+                             "events": int(tr["events"][0]),
+                             "y_obs": [float(v) for v in tr["summ"][0]]}
     bs = W.BEGE_SERIES
     r = oracle.bege_simulate(W.BEGE_THETA_OBS, bs["T"], bs["seed"])
     out["bege_T1099"] = {"theta": list(W.BEGE_THETA_OBS), "seed": bs["seed"], "T": bs["T"],
