@@ -60,6 +60,8 @@ extern "C" {
 #define PPS_TSW_MAX_CELLS 8192 /* toggle switch: cells per draw (one LDS sort) */
 #define PPS_GARCH_LAGS 10
 #define PPS_GARCH_NSUMM 14 /* mean, variance, skewness, kurtosis, ACF(r^2) lags 1..10 */
+#define PPS_TB_MAX_POP 16384   /* tuberculosis: largest stopping population */
+#define PPS_TB_MAX_SAMPLE 1024 /* tuberculosis: largest sample of cases */
 
 enum pps_family {
     PPS_UNIFORM = 0,   /* U(a, b) */
@@ -98,7 +100,27 @@ enum pps_model_kind {
      * paper's 19 quantiles of 8000 cells are ranks 400, 800, ..., 7600);
      * statistic: their mean.  Simulated one draw per workgroup with the
      * cells across lanes. */
-    PPS_TOGGLE_SWITCH = 3
+    PPS_TOGGLE_SWITCH = 3,
+    /* Tuberculosis transmission (App. B): cases of genotypes i with counts
+     * X_i; each case gives birth at rate alpha, dies at rate delta and
+     * mutates at rate tau (theta = (alpha, delta, tau)), a mutation moving
+     * the case to a new genotype.  Gillespie's direct method from x0 cases of
+     * one genotype until the population reaches n_cells cases (complete),
+     * dies out (extinct) or `steps` events have happened (truncated).  Event
+     * e uses words (2(e%2), 2(e%2)+1) of block e/2 of stream purpose
+     * 0x90000000: the case is number floor(w N / 2^32) in genotype-slot
+     * order (the lookup over genotype weights), the type is birth below
+     * floor(2^32 alpha/R), death below floor(2^32 (alpha + delta)/R),
+     * mutation above (R = alpha + delta + tau, FP64); a new genotype takes
+     * the lowest empty slot after the mutating case has left its own.  The
+     * waiting times do not enter the result and are not drawn.  Then n_obs
+     * cases are drawn without replacement (draw s: word s%4 of block s/4 of
+     * purpose 0x90000001, case floor(w (N - s)/2^32) of those left), or all N
+     * when N < n_obs.  Summaries: (g/n_s, H) with g the distinct genotypes
+     * among the n_s cases taken and H = 1 - sum_i (n_i/n_s)^2; (0, 0) for an
+     * extinct run.  Statistic: their mean.  One draw per 64-lane workgroup,
+     * its genotype counts in LDS. */
+    PPS_TB = 4
 };
 
 enum pps_constraint {
@@ -106,7 +128,10 @@ enum pps_constraint {
     /* GARCH: reject alpha + beta >= 1 (decided in FP64) and redraw from the
      * same draw's stream (attempt t uses prior blocks 8t + j), up to 32
      * attempts. */
-    PPS_GARCH_STATIONARY = 1
+    PPS_GARCH_STATIONARY = 1,
+    /* tuberculosis: reject alpha <= delta or tau <= 0 (a growing epidemic),
+     * redrawn as above */
+    PPS_TB_SUPERCRITICAL = 2
 };
 
 typedef struct {
@@ -122,11 +147,16 @@ typedef struct {
     double x0;          /* logistic: X(0); toggle switch: u(0) = v(0) */
     double t_end;       /* logistic, toggle switch: final time T */
     int32_t steps;      /* logistic: EM steps (multiple of n_obs); toggle switch: EM
-                           steps (>= 1); GARCH: series length (multiple of 20) */
+                           steps (>= 1); GARCH: series length (multiple of 20);
+                           tuberculosis: the event cap (>= 1) */
     int32_t n_obs;      /* logistic / normal-mean: observations; toggle switch:
-                           quantiles (1..PPS_MAX_OBS) */
+                           quantiles (1..PPS_MAX_OBS); tuberculosis: cases
+                           sampled (1..PPS_TB_MAX_SAMPLE) */
     double noise_sd;    /* normal-mean: observation sd */
-    int32_t n_cells;    /* toggle switch: cells per draw (1..PPS_TSW_MAX_CELLS) */
+    int32_t n_cells;    /* toggle switch: cells per draw (1..PPS_TSW_MAX_CELLS);
+                           tuberculosis: the stopping population
+                           (2..PPS_TB_MAX_POP); x0 is then the initial cases
+                           (an integer in [1, n_cells]) */
 } pps_model;
 
 typedef struct {
@@ -212,10 +242,17 @@ int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_famil
 
 /* Per-summary tail-area counts (the prior-predictive check of a summary
  * vector): count_ge[s] = #{i : S_s(D_i) >= obs_summ[s]} (compared in FP64),
- * s < n_summaries.  GARCH and toggle-switch models.  obs_summ, count_ge:
- * host. */
+ * s < n_summaries.  GARCH, toggle-switch and tuberculosis models.
+ * obs_summ, count_ge: host. */
 int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
                       const double *obs_summ, uint64_t *count_ge, void *stream);
+
+/* Tuberculosis runs: per draw the number of Gillespie events and the status
+ * (0 complete, 1 extinct, 2 truncated by the event cap), the same runs as
+ * every other entry point simulates for these draws.  events (n_draws u64)
+ * and status (n_draws i32): device, either may be NULL.  PPS_TB only. */
+int pps_tb_events(const pps_model *model, const pps_sampling *sampling, uint64_t *events,
+                  int32_t *status, void *stream);
 
 /* ---- jobs, batches and serving ------------------------------------------ */
 /* A job is one ABC run (Alg. 1, fixed-N form) or one prior-predictive p-value

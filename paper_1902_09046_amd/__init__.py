@@ -26,4 +26,5 @@ from ._pps import (  # noqa: F401
     Server, records, pps_autotune,
     PPS_BIO_MAX_GROUPS, PPS_SMC_MAX_PARTICLES, pps_bioassay, pps_smc_config, make_bioassay,
     make_smc_config, pps_smc_log_evidence, pps_wip_test, pps_bege_loglik, pps_bege_count_ops, BEGE_NPAR,
+    PPS_TB, PPS_TB_SUPERCRITICAL, PPS_TB_MAX_POP, PPS_TB_MAX_SAMPLE, CLASS_GILLESPIE, pps_tb_events,
 )

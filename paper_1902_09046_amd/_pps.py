@@ -21,17 +21,18 @@ LIB_PATH = os.path.join(_HERE, "libpps.so")
 PPS_OK, PPS_PENDING = 0, 1
 PPS_EINVAL, PPS_ENOMEM, PPS_EDEVICE, PPS_EBUSY, PPS_ENOTFOUND, PPS_ETRUNC = -1, -2, -3, -4, -5, -6
 PPS_UNIFORM, PPS_NORMAL, PPS_LOGNORMAL, PPS_POINT = 0, 1, 2, 3
-PPS_LOGISTIC_SDE, PPS_GARCH11, PPS_NORMAL_MEAN, PPS_TOGGLE_SWITCH = 0, 1, 2, 3
-PPS_NO_CONSTRAINT, PPS_GARCH_STATIONARY = 0, 1
+PPS_LOGISTIC_SDE, PPS_GARCH11, PPS_NORMAL_MEAN, PPS_TOGGLE_SWITCH, PPS_TB = 0, 1, 2, 3, 4
+PPS_NO_CONSTRAINT, PPS_GARCH_STATIONARY, PPS_TB_SUPERCRITICAL = 0, 1, 2
 PPS_EPS_FIXED, PPS_EPS_TOP_FRACTION = 0, 1
 PPS_MAX_PARAMS, PPS_MAX_OBS, PPS_GARCH_NSUMM, PPS_TSW_MAX_CELLS = 8, 64, 14, 8192
+PPS_TB_MAX_POP, PPS_TB_MAX_SAMPLE = 16384, 1024
 # kernel classes (pps_set_launch_shape)
-CLASS_PATH, CLASS_GARCH, CLASS_GROUP, CLASS_CELLS = 0, 1, 2, 3
+CLASS_PATH, CLASS_GARCH, CLASS_GROUP, CLASS_CELLS, CLASS_GILLESPIE = 0, 1, 2, 3, 4
 
 FAMILY = {"uniform": PPS_UNIFORM, "normal": PPS_NORMAL, "lognormal": PPS_LOGNORMAL,
           "point": PPS_POINT}
 MODEL = {"logistic": PPS_LOGISTIC_SDE, "garch11": PPS_GARCH11, "normal_mean": PPS_NORMAL_MEAN,
-         "toggle_switch": PPS_TOGGLE_SWITCH}
+         "toggle_switch": PPS_TOGGLE_SWITCH, "tb": PPS_TB}
 
 
 class PPSError(RuntimeError):
@@ -208,6 +209,8 @@ def lib():
         L.pps_wip_test.restype = ctypes.c_int
         L.pps_bege_loglik.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.pps_bege_loglik.restype = ctypes.c_int
+        L.pps_tb_events.argtypes = [mp, sp, vp, vp, vp]
+        L.pps_tb_events.restype = ctypes.c_int
         L.pps_bege_count_ops.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_double), vp]
         L.pps_bege_count_ops.restype = ctypes.c_int
@@ -237,7 +240,8 @@ def make_model(spec: Mapping) -> pps_model:
         m.prior[j].family = FAMILY[fam]
         m.prior[j].a = float(a)
         m.prior[j].b = float(b)
-    m.constraint = PPS_GARCH_STATIONARY if spec.get("constraint") == "garch_stationary" else 0
+    m.constraint = {"garch_stationary": PPS_GARCH_STATIONARY,
+                    "tb_supercritical": PPS_TB_SUPERCRITICAL}.get(spec.get("constraint"), 0)
     m.x0 = float(spec.get("x0", 0.0))
     m.t_end = float(spec.get("t_end", 0.0))
     m.steps = int(spec.get("steps", 0))
@@ -626,3 +630,15 @@ def pps_bege_count_ops(theta, r, n_omega: int = 100, device="cuda", stream=None)
     _check(lib().pps_bege_count_ops(int(th.data_ptr()), th.shape[0], int(rr.data_ptr()),
                                     rr.shape[0] - 1, n_omega, ctypes.byref(ops), _stream(stream)))
     return float(ops.value)
+
+
+def pps_tb_events(model, sampling: pps_sampling, device="cuda", stream=None) -> dict:
+    """Tuberculosis runs: per-draw Gillespie event counts (uint64 as int64)
+    and status (0 complete, 1 extinct, 2 truncated), device tensors."""
+    import torch
+    n = int(sampling.n_draws)
+    ev = torch.empty(n, dtype=torch.int64, device=device)
+    st = torch.empty(n, dtype=torch.int32, device=device)
+    _check(lib().pps_tb_events(ctypes.byref(_model_arg(model)), ctypes.byref(sampling),
+                               int(ev.data_ptr()), int(st.data_ptr()), _stream(stream)))
+    return {"events": ev, "status": st}

@@ -330,8 +330,8 @@ int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
     int ns = 0, rc;
     PPS_TRY(validate_model(model, &ns));
     PPS_TRY(validate_sampling(sampling));
-    if (model->model != PPS_GARCH11 && model->model != PPS_TOGGLE_SWITCH)
-        return fail(PPS_EINVAL, "pps_summary_tally: GARCH and toggle-switch models only");
+    if (model->model != PPS_GARCH11 && model->model != PPS_TOGGLE_SWITCH && model->model != PPS_TB)
+        return fail(PPS_EINVAL, "pps_summary_tally: GARCH, toggle-switch and tuberculosis models only");
     if (!obs_summ || !count_ge)
         return fail(PPS_EINVAL, "obs_summ and count_ge are required");
     Context *c = current_context(&rc);
@@ -353,6 +353,30 @@ int pps_summary_tally(const pps_model *model, const pps_sampling *sampling,
     PPS_TRY(run_sync(*c, plan, as_stream(stream)));
     std::memcpy(count_ge, c->engine->out_counts(0), ns * sizeof(unsigned long long));
     return PPS_OK;
+}
+
+int pps_tb_events(const pps_model *model, const pps_sampling *sampling, uint64_t *events,
+                  int32_t *status, void *stream)
+{
+    clear_error();
+    int ns = 0, rc;
+    PPS_TRY(validate_model(model, &ns));
+    PPS_TRY(validate_sampling(sampling));
+    if (model->model != PPS_TB)
+        return fail(PPS_EINVAL, "pps_tb_events: tuberculosis model only");
+    Context *c = current_context(&rc);
+    if (!c)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    const int cls = model_class(model);
+    EpochPlan plan;
+    JobDev J;
+    fill_job(J, model, sampling, ns, JOB_EVENTS);
+    J.dump_events = reinterpret_cast<unsigned long long *>(events);
+    J.dump_status = status;
+    whole_job(*c->engine, cls, J);
+    plan.rows[cls].push_back(J);
+    return run_sync(*c, plan, as_stream(stream));
 }
 
 }  // extern "C"

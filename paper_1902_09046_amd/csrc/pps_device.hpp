@@ -57,7 +57,13 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 
 // Stream purposes: prior draws, the path of a one-lane model, and cell c of a
 // multi-cell model (the toggle switch) as PURPOSE_CELL0 + c.
-enum : uint32_t { PURPOSE_PRIOR = 0, PURPOSE_PATH = 1, PURPOSE_CELL0 = 2 };
+enum : uint32_t {
+    PURPOSE_PRIOR = 0,
+    PURPOSE_PATH = 1,
+    PURPOSE_CELL0 = 2,
+    PURPOSE_TB_EVENT = 0x90000000u,   // tuberculosis: event e uses block e/2
+    PURPOSE_TB_SAMPLE = 0x90000001u,  // tuberculosis: sampled case s uses block s/4
+};
 
 struct StreamKey {
     uint32_t k0, k1;  // (lo32 seed, hi32 seed)
@@ -154,7 +160,9 @@ __device__ __attribute__((noinline)) double prior_value(const PriorDev &p, Strea
 constexpr int MAX_PRIOR_ATTEMPTS = 32;
 
 // theta ~ pi(theta); with the GARCH constraint, attempts whose
-// theta[1] + theta[2] >= 1 are redrawn (the last attempt is kept after 32).
+// theta[1] + theta[2] >= 1 are redrawn, with the tuberculosis constraint
+// those with theta[0] <= theta[1] or theta[2] <= 0 (the last attempt is kept
+// after 32).
 // MAXP is the size of `theta` (the parameters a kernel holds in registers).
 template <int MAXP>
 __device__ __forceinline__ void prior_draw(const PriorDev *prior, int n_params, int constraint,
@@ -165,10 +173,15 @@ __device__ __forceinline__ void prior_draw(const PriorDev *prior, int n_params, 
         for (int j = 0; j < MAXP; ++j)
             if (j < n_params)
                 theta[j] = prior_value(prior[j], key, draw, j, attempt);
-        if (constraint != PPS_GARCH_STATIONARY)
+        if (constraint == PPS_GARCH_STATIONARY) {
+            if (__dadd_rn(theta[1], theta[2]) < 1.0 || attempt + 1 == MAX_PRIOR_ATTEMPTS)
+                return;
+        } else if (constraint == PPS_TB_SUPERCRITICAL) {
+            if ((theta[0] > theta[1] && theta[2] > 0.0) || attempt + 1 == MAX_PRIOR_ATTEMPTS)
+                return;
+        } else {
             return;
-        if (__dadd_rn(theta[1], theta[2]) < 1.0 || attempt + 1 == MAX_PRIOR_ATTEMPTS)
-            return;
+        }
     }
 }
 

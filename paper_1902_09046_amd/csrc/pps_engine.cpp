@@ -57,6 +57,8 @@ int EpochEngine::init(int n_slots, int cu_count)
     // The cell kernel holds 32 KB of LDS per workgroup: 512 lanes per
     // workgroup reach 8 waves per SIMD, 256 would stop at 5.
     shape_.sim[CLASS_CELLS].block = 512;
+    // One tuberculosis draw per 64-lane workgroup.
+    shape_.sim[CLASS_GILLESPIE].block = 64;
     hipError_t e = hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking);
     if (e != hipSuccess)
         return fail_hip(e, "capture stream");

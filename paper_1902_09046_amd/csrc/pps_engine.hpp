@@ -45,7 +45,7 @@ class EpochEngine {
     // and interleaved draw.
     uint64_t tile_size(int cls) const
     {
-        if (cls == CLASS_CELLS)
+        if (cls == CLASS_CELLS || cls == CLASS_GILLESPIE)
             return 1;
         return static_cast<uint64_t>(shape_.sim[cls].block) * shape_.sim[cls].dpl;
     }

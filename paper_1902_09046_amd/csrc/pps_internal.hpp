@@ -15,6 +15,7 @@ enum : int32_t {
     JOB_TALLY_STAT = 1 << 1,  // count T_i >= t_obs into job.counts[0] (p-value)
     JOB_TALLY_SUMM = 1 << 2,  // count S_s(D_i) >= summ_obs[s] into job.counts[s]
     JOB_DUMP = 1 << 3,        // write theta / summaries / stat / dist per draw
+    JOB_EVENTS = 1 << 4,      // tuberculosis: write events / status per draw
 };
 
 // Model classes compiled into separate simulation kernels.  CLASS_GROUP
@@ -23,7 +24,17 @@ enum : int32_t {
 // simulates a draw under every lambda of its group from one random stream
 // (common random numbers).  CLASS_CELLS runs one draw per workgroup with the
 // draw's cells across the lanes (the toggle switch): a tile is one draw.
-enum : int { CLASS_PATH = 0, CLASS_GARCH = 1, CLASS_GROUP = 2, CLASS_CELLS = 3, N_CLASSES = 4 };
+// CLASS_GILLESPIE runs one tuberculosis draw per 64-lane workgroup (its
+// genotype counts in LDS): a tile is one draw, so a workgroup that finishes
+// a short epidemic takes the next draw at once.
+enum : int {
+    CLASS_PATH = 0,
+    CLASS_GARCH = 1,
+    CLASS_GROUP = 2,
+    CLASS_CELLS = 3,
+    CLASS_GILLESPIE = 4,
+    N_CLASSES = 5
+};
 constexpr int GROUP_LPL = 8;
 
 // Prior parameters held by the one-lane-per-draw kernels (logistic SDE,
@@ -55,8 +66,8 @@ struct alignas(16) JobDev {
     int32_t obs_stride;
     int32_t constraint;
     int32_t tile_size;
-    int32_t n_cells;       // CLASS_CELLS: cells per draw
-    int32_t pad0;
+    int32_t n_cells;       // CLASS_CELLS: cells per draw; CLASS_GILLESPIE: stop size
+    int32_t n_sample;      // CLASS_GILLESPIE: cases sampled
     uint64_t seed;
     uint64_t first_draw;
     uint64_t n_draws;
@@ -76,6 +87,8 @@ struct alignas(16) JobDev {
     float *dump_summ;
     float *dump_stat;
     float *dump_dist;
+    unsigned long long *dump_events;  // JOB_EVENTS (may be null)
+    int32_t *dump_status;
     uint32_t row_flags;          // ROW_* above
     uint32_t n_counts;           // tallies of this row (1, or 14 for GARCH)
     uint32_t out_slot;           // ROW_COPY_COUNTS: first host slot

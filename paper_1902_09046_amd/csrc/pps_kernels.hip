@@ -777,6 +777,308 @@ __global__ __launch_bounds__(BLOCK) void k_simulate_cells(const EpochHeader *__r
 }
 
 // ===========================================================================
+// Tuberculosis transmission (App. B): one draw per 64-lane workgroup.
+//
+// A Gillespie run is a sequential Markov chain, so the lanes of a wave share
+// one run: the genotype counts live in LDS as leaves (one uint16 per slot,
+// PPS_TB_MAX_POP slots) under 64-slot block sums, and the lookup of the case
+// chosen by an event is a 64-way descent -- each lane sums four block sums,
+// a wave prefix scan and a ballot find the block, and a second scan over the
+// block's 64 leaves finds the slot -- in place of the paper's linear scan
+// over the genotype weights (same slot).  The lowest empty slot for a new
+// genotype is found the same way from per-block counts of occupied slots.
+// Runs end when the population reaches the stop size, dies out or hits the
+// event cap, and the workgroup takes the next draw from the tile queue at
+// once, so runs of very different lengths balance across the machine.
+// ===========================================================================
+constexpr int TB_BLOCK = 64;
+constexpr int TB_SLOTS = PPS_TB_MAX_POP;
+constexpr int TB_NBLK = TB_SLOTS / 64;
+static_assert(TB_NBLK == 4 * TB_BLOCK, "four block sums per lane");
+enum : int32_t { TB_COMPLETE = 0, TB_EXTINCT = 1, TB_TRUNCATED = 2 };
+
+__device__ __forceinline__ int tb_scan(int v)
+{
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(v, d, 64);
+        if (lane >= d)
+            v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int tb_first(unsigned long long mask)
+{
+    return __builtin_ffsll(static_cast<long long>(mask)) - 1;
+}
+
+__device__ __forceinline__ int tb_u16(uint64_t four, int k)
+{
+    return static_cast<int>((four >> (16 * k)) & 0xffffu);
+}
+
+struct TbPick {
+    int slot;   // the chosen slot
+    int blk;    // its block
+    int leaf;   // its count before the event
+    int bsum;   // its block sum before the event
+};
+
+// The slot holding case m (0 <= m < sum of the counts) in slot order.
+__device__ __forceinline__ TbPick tb_select(const uint16_t *leaf, const uint16_t *bsum, uint32_t m)
+{
+    const int lane = threadIdx.x;
+    const uint64_t four = reinterpret_cast<const uint64_t *>(bsum)[lane];
+    const int c0 = tb_u16(four, 0), c1 = tb_u16(four, 1), c2 = tb_u16(four, 2), c3 = tb_u16(four, 3);
+    const int s4 = c0 + c1 + c2 + c3;
+    const int incl = tb_scan(s4);
+    // (the clamps only keep every index in range; with consistent counts the
+    // ballots are never empty)
+    const int L = max(tb_first(__ballot(incl > static_cast<int>(m))), 0);
+    // lane L's four blocks and the cases before them (uniform)
+    const uint64_t fL = __shfl(four, L, 64);
+    int before = __shfl(incl - s4, L, 64);
+    int k = 0, cb = tb_u16(fL, 0);
+    while (k < 3 && static_cast<int>(m) >= before + cb) {
+        before += cb;
+        ++k;
+        cb = tb_u16(fL, k);
+    }
+    const int b = 4 * L + k;
+    const int m1 = static_cast<int>(m) - before;
+    const int v = leaf[64 * b + lane];
+    const int incl2 = tb_scan(v);
+    const int L2 = max(tb_first(__ballot(incl2 > m1)), 0);
+    TbPick r;
+    r.slot = 64 * b + L2;
+    r.blk = b;
+    r.leaf = __shfl(v, L2, 64);
+    r.bsum = cb;
+    return r;
+}
+
+// The lowest slot holding no case.
+__device__ __forceinline__ int tb_lowest_empty(const uint16_t *leaf, const uint16_t *occ)
+{
+    const int lane = threadIdx.x;
+    const uint64_t four = reinterpret_cast<const uint64_t *>(occ)[lane];
+    const bool has = tb_u16(four, 0) < 64 || tb_u16(four, 1) < 64 || tb_u16(four, 2) < 64 ||
+                     tb_u16(four, 3) < 64;
+    const int L = max(tb_first(__ballot(has)), 0);
+    const uint64_t fL = __shfl(four, L, 64);
+    int k = 0;
+    while (k < 3 && tb_u16(fL, k) >= 64)
+        ++k;
+    const int b = 4 * L + k;
+    const int L2 = max(tb_first(__ballot(leaf[64 * b + lane] == 0)), 0);
+    return 64 * b + L2;
+}
+
+__global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__restrict__ hdr,
+                                                        const JobDev *__restrict__ rows,
+                                                        LaunchState *__restrict__ states)
+{
+    __shared__ __align__(16) uint16_t s_leaf[TB_SLOTS];
+    __shared__ __align__(16) uint16_t s_bsum[TB_NBLK];
+    __shared__ __align__(16) uint16_t s_occ[TB_NBLK];
+    __shared__ float s_samp[PPS_TB_MAX_SAMPLE];
+    const int lane = threadIdx.x;
+    const int n_jobs = static_cast<int>(hdr->class_rows[CLASS_GILLESPIE]);
+    const uint64_t total_tiles = hdr->class_tiles[CLASS_GILLESPIE];
+    const JobDev *__restrict__ jobs = rows + hdr->class_first[CLASS_GILLESPIE];
+    LaunchState *__restrict__ state = states + CLASS_GILLESPIE;
+    for (;;) {
+        unsigned long long tl = 0;
+        if (lane == 0)
+            tl = atomicAdd(&state->next_tile, 1ull);
+        const uint64_t t = uniform_u64(__shfl(tl, 0, 64));
+        if (t >= total_tiles)
+            break;
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const JobDev *__restrict__ J = jobs + lo;
+        const int flags = J->flags;
+        const uint64_t n = J->n_draws;
+        const uint64_t q = t - J->tile_begin + J->tile_offset;  // one draw per tile
+        const uint64_t draw = J->first_draw + q;
+        const StreamKey key = make_key(J->seed);
+        double theta[3];
+        prior_draw<3>(J->prior, 3, J->constraint, key, draw, theta);
+        // event-type thresholds: single IEEE FP64 operations (as the oracle)
+        const double ad = __dadd_rn(theta[0], theta[1]);
+        const double rate = __dadd_rn(ad, theta[2]);
+        const uint64_t t_birth = static_cast<uint64_t>(floor(ldexp(__ddiv_rn(theta[0], rate), 32)));
+        const uint64_t t_death = static_cast<uint64_t>(floor(ldexp(__ddiv_rn(ad, rate), 32)));
+        const uint32_t n_stop = static_cast<uint32_t>(J->n_cells);
+        const uint64_t max_events = static_cast<uint64_t>(static_cast<uint32_t>(J->steps));
+        const int nb_used = static_cast<int>((n_stop + 63) / 64);
+        // empty population of one genotype with x0 cases in slot 0
+        for (int i = lane; i < nb_used * 64; i += TB_BLOCK)
+            s_leaf[i] = 0;
+        for (int i = lane; i < TB_NBLK; i += TB_BLOCK) {
+            s_bsum[i] = 0;
+            s_occ[i] = i < nb_used ? 0 : 64;
+        }
+        __syncthreads();
+        uint32_t N = static_cast<uint32_t>(J->x0);
+        if (lane == 0) {
+            s_leaf[0] = static_cast<uint16_t>(N);
+            s_bsum[0] = static_cast<uint16_t>(N);
+            s_occ[0] = 1;
+        }
+        __syncthreads();
+        uint64_t e = 0;
+        Words4 w{};
+        while (N > 0 && N < n_stop && e < max_events) {
+            if ((e & 1) == 0)
+                w = stream_block(key, draw, static_cast<uint32_t>(e >> 1), PURPOSE_TB_EVENT);
+            const uint32_t wc = (e & 1) ? w.z : w.x;
+            const uint32_t wt = (e & 1) ? w.w : w.y;
+            const uint32_t m = static_cast<uint32_t>((static_cast<uint64_t>(wc) * N) >> 32);
+            const TbPick pk = tb_select(s_leaf, s_bsum, m);
+            if (static_cast<uint64_t>(wt) < t_birth) {
+                if (lane == 0) {
+                    s_leaf[pk.slot] = static_cast<uint16_t>(pk.leaf + 1);
+                    s_bsum[pk.blk] = static_cast<uint16_t>(pk.bsum + 1);
+                }
+                ++N;
+                __syncthreads();
+            } else {
+                // death or mutation: the case leaves its genotype
+                if (lane == 0) {
+                    s_leaf[pk.slot] = static_cast<uint16_t>(pk.leaf - 1);
+                    s_bsum[pk.blk] = static_cast<uint16_t>(pk.bsum - 1);
+                    if (pk.leaf == 1)
+                        s_occ[pk.blk] = static_cast<uint16_t>(s_occ[pk.blk] - 1);
+                }
+                __syncthreads();
+                if (static_cast<uint64_t>(wt) < t_death) {
+                    --N;
+                } else {
+                    // mutation: a new genotype in the lowest empty slot
+                    const int ns = tb_lowest_empty(s_leaf, s_occ);
+                    if (lane == 0) {
+                        s_leaf[ns] = 1;
+                        s_bsum[ns >> 6] = static_cast<uint16_t>(s_bsum[ns >> 6] + 1);
+                        s_occ[ns >> 6] = static_cast<uint16_t>(s_occ[ns >> 6] + 1);
+                    }
+                    __syncthreads();
+                }
+            }
+            ++e;
+        }
+        const int32_t status = N >= n_stop ? TB_COMPLETE : (N == 0 ? TB_EXTINCT : TB_TRUNCATED);
+        // summaries: n_sample cases without replacement (all when fewer)
+        const uint32_t n_sample = static_cast<uint32_t>(J->n_sample);
+        uint64_t g = 0, sq = 0, n_taken = 0;
+        if (N >= n_sample) {
+            n_taken = n_sample;
+            Words4 ws{};
+            for (uint32_t si = 0; si < n_sample; ++si) {
+                if ((si & 3) == 0)
+                    ws = stream_block(key, draw, si >> 2, PURPOSE_TB_SAMPLE);
+                const uint32_t wv = (si & 3) == 0 ? ws.x : ((si & 3) == 1 ? ws.y : ((si & 3) == 2 ? ws.z : ws.w));
+                const uint32_t m = static_cast<uint32_t>((static_cast<uint64_t>(wv) * (N - si)) >> 32);
+                const TbPick pk = tb_select(s_leaf, s_bsum, m);
+                if (lane == 0) {
+                    s_leaf[pk.slot] = static_cast<uint16_t>(pk.leaf - 1);
+                    s_bsum[pk.blk] = static_cast<uint16_t>(pk.bsum - 1);
+                    s_samp[si] = static_cast<float>(pk.slot);
+                }
+                __syncthreads();
+            }
+            unsigned n2 = 1;
+            while (n2 < n_sample)
+                n2 <<= 1;
+            for (unsigned i = n_sample + lane; i < n2; i += TB_BLOCK)
+                s_samp[i] = __builtin_inff();
+            __syncthreads();
+            lds_bitonic_sort<TB_BLOCK>(s_samp, n2);
+            // runs of equal slots: g runs, sum of squared run lengths (every
+            // lane walks the sorted slots: broadcast reads, uniform control)
+            uint64_t run = 0;
+            float prev = -1.0f;
+            for (uint32_t i = 0; i < n_sample; ++i) {
+                const float v = s_samp[i];
+                if (v != prev) {
+                    sq += run * run;
+                    run = 0;
+                    ++g;
+                    prev = v;
+                }
+                ++run;
+            }
+            sq += run * run;
+        } else if (N > 0) {
+            n_taken = N;
+            uint64_t gl = 0, sl = 0;
+            for (int i = lane; i < nb_used * 64; i += TB_BLOCK) {
+                const uint64_t v = s_leaf[i];
+                gl += v > 0;
+                sl += v * v;
+            }
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) {
+                gl += __shfl_xor(gl, d, 64);
+                sl += __shfl_xor(sl, d, 64);
+            }
+            g = gl;
+            sq = sl;
+        }
+        double s0 = 0.0, s1 = 0.0;
+        if (n_taken > 0) {
+            const double nt = static_cast<double>(n_taken);
+            s0 = static_cast<double>(g) / nt;
+            s1 = 1.0 - static_cast<double>(sq) / (nt * nt);
+        }
+        if (lane == 0) {
+            if ((flags & JOB_EVENTS) && J->dump_events)
+                J->dump_events[q] = e;
+            if ((flags & JOB_EVENTS) && J->dump_status)
+                J->dump_status[q] = status;
+            const double d0 = s0 - static_cast<double>(J->y_obs[0]);
+            const double d1 = s1 - static_cast<double>(J->y_obs[1]);
+            const float dist = static_cast<float>(sqrt(d0 * d0 + d1 * d1));
+            const double stat = 0.5 * (s0 + s1);
+            if (flags & JOB_WRITE_DIST)
+                J->dist[q] = dist;
+            if (flags & JOB_DUMP) {
+                if (J->dump_theta) {
+                    J->dump_theta[q] = static_cast<float>(theta[0]);
+                    J->dump_theta[n + q] = static_cast<float>(theta[1]);
+                    J->dump_theta[2 * n + q] = static_cast<float>(theta[2]);
+                }
+                if (J->dump_summ) {
+                    J->dump_summ[q] = static_cast<float>(s0);
+                    J->dump_summ[n + q] = static_cast<float>(s1);
+                }
+                if (J->dump_stat)
+                    J->dump_stat[q] = static_cast<float>(stat);
+                if (J->dump_dist)
+                    J->dump_dist[q] = dist;
+            }
+            if (flags & JOB_TALLY_SUMM) {
+                if (s0 >= J->summ_obs[0])
+                    atomicAdd(&J->counts[0], 1ull);
+                if (s1 >= J->summ_obs[1])
+                    atomicAdd(&J->counts[1], 1ull);
+            }
+            if ((flags & JOB_TALLY_STAT) && stat >= J->t_obs)
+                atomicAdd(&J->counts[0], 1ull);
+        }
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
 // Epoch staging: tables in, results out (mapped pinned host memory).
 // ===========================================================================
 __global__ void k_stage_in(const EpochHeader *__restrict__ h_hdr, const JobDev *__restrict__ h_rows,
@@ -1359,6 +1661,8 @@ static SimKernel sim_kernel(int cls, const SimShape &sh)
         default: return nullptr;
         }
     }
+    if (cls == CLASS_GILLESPIE)
+        return sh.block == TB_BLOCK && sh.dpl == 1 && sh.unroll == 1 ? k_simulate_tb : nullptr;
     if (cls == CLASS_GROUP) {
         if (sh.dpl != 1 || sh.unroll != 1)
             return nullptr;

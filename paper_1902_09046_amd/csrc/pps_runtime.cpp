@@ -100,6 +100,8 @@ int model_class(const pps_model *m)
         return CLASS_GARCH;
     if (m->model == PPS_TOGGLE_SWITCH)
         return CLASS_CELLS;
+    if (m->model == PPS_TB)
+        return CLASS_GILLESPIE;
     return CLASS_PATH;
 }
 
@@ -131,8 +133,11 @@ int validate_model(const pps_model *m, int *n_summ)
             return fail(PPS_EINVAL, "prior %d: unknown family %d", j, p.family);
         }
     }
-    if (m->constraint != PPS_NO_CONSTRAINT && m->constraint != PPS_GARCH_STATIONARY)
+    if (m->constraint != PPS_NO_CONSTRAINT && m->constraint != PPS_GARCH_STATIONARY &&
+        m->constraint != PPS_TB_SUPERCRITICAL)
         return fail(PPS_EINVAL, "unknown constraint %d", m->constraint);
+    if (m->constraint == PPS_TB_SUPERCRITICAL && m->model != PPS_TB)
+        return fail(PPS_EINVAL, "the supercritical constraint only applies to tuberculosis");
     switch (m->model) {
     case PPS_LOGISTIC_SDE:
         if (m->n_params != 3)
@@ -183,6 +188,23 @@ int validate_model(const pps_model *m, int *n_summ)
             return fail(PPS_EINVAL, "constraint only applies to GARCH");
         *n_summ = m->n_obs;
         return PPS_OK;
+    case PPS_TB:
+        if (m->n_params != 3)
+            return fail(PPS_EINVAL, "tuberculosis needs 3 parameters (alpha, delta, tau)");
+        if (m->n_cells < 2 || m->n_cells > PPS_TB_MAX_POP)
+            return fail(PPS_EINVAL, "stopping population %d out of range [2, %d]", m->n_cells,
+                        PPS_TB_MAX_POP);
+        if (m->n_obs < 1 || m->n_obs > PPS_TB_MAX_SAMPLE)
+            return fail(PPS_EINVAL, "sample size %d out of range [1, %d]", m->n_obs,
+                        PPS_TB_MAX_SAMPLE);
+        if (m->steps < 1)
+            return fail(PPS_EINVAL, "tuberculosis needs an event cap (steps) >= 1");
+        if (!(m->x0 >= 1.0) || !(m->x0 <= m->n_cells) || m->x0 != std::floor(m->x0))
+            return fail(PPS_EINVAL, "initial cases x0 must be an integer in [1, n_cells]");
+        if (m->constraint == PPS_GARCH_STATIONARY)
+            return fail(PPS_EINVAL, "the GARCH constraint does not apply to tuberculosis");
+        *n_summ = 2;
+        return PPS_OK;
     default:
         return fail(PPS_EINVAL, "unknown model %d", m->model);
     }
@@ -219,6 +241,11 @@ void fill_job(JobDev &J, const pps_model *m, const pps_sampling *s, int n_summ, 
         J.obs_stride = 1;
         J.dt = m->t_end / static_cast<double>(m->steps);
         J.n_cells = m->n_cells;
+    } else if (m->model == PPS_TB) {
+        J.steps = m->steps;
+        J.obs_stride = 1;
+        J.n_cells = m->n_cells;
+        J.n_sample = m->n_obs;
     } else {
         J.steps = m->n_obs;
         J.obs_stride = 1;

@@ -265,3 +265,28 @@ def test_bege_count_ops_validation_without_device(P):
     assert L.pps_bege_count_ops(1, 4, 1, 10, 100, None, None) == P.PPS_EINVAL
     assert L.pps_bege_count_ops(1, 0, 1, 10, 100, C.byref(ops), None) == P.PPS_EINVAL
     assert L.pps_bege_count_ops(None, 4, 1, 10, 100, C.byref(ops), None) == P.PPS_EINVAL
+
+
+def test_tb_validation_without_device(P):
+    import pps_workloads as W
+    assert P.pps_n_summaries(W.tb_spec()) == 2
+    bad = [W.tb_spec(n_stop=1), W.tb_spec(n_stop=P.PPS_TB_MAX_POP + 1), W.tb_spec(n_sample=0),
+           W.tb_spec(n_sample=P.PPS_TB_MAX_SAMPLE + 1), W.tb_spec(max_events=0), W.tb_spec(x0=0.0),
+           W.tb_spec(x0=2.5), W.tb_spec(n_stop=100, x0=101.0)]
+    two = W.tb_spec()
+    two["priors"] = two["priors"][:2]
+    garch_c = W.tb_spec()
+    garch_c["constraint"] = "garch_stationary"
+    bad += [two, garch_c]
+    for spec in bad:
+        with pytest.raises(P.PPSError):
+            P.pps_n_summaries(spec)
+    logistic_tb = W.logistic_spec()
+    logistic_tb["constraint"] = "tb_supercritical"
+    with pytest.raises(P.PPSError):
+        P.pps_n_summaries(logistic_tb)
+    L = P.lib()
+    m = P.make_model(W.logistic_spec())
+    s = P.make_sampling(10, 0, 1)
+    import ctypes as C
+    assert L.pps_tb_events(C.byref(m), C.byref(s), None, None, None) == P.PPS_EINVAL
