@@ -446,6 +446,43 @@ def main():
                             "sample": f"the first {bs} of the {bb['n_theta']} vectors (FP64, "
                                       "the same quadrature)"}
         workloads[bb["name"]] = bw
+        # Tuberculosis prior predictive (App. B, Tables B.1/B.2's largest
+        # run: N = 16000 samples): Gillespie runs to a population of 10000
+        # cases (cap 2^20 events), 473 cases sampled, ABC keeps the closest
+        # 1 %.  One run per 64-lane workgroup, runs from the tile queue.
+        tb = W.TB_PPS
+        tspec_tb = W.tb_spec(n_stop=tb["n_stop"], n_sample=tb["n_sample"], max_events=tb["max_events"])
+        ty_tb = np.array(golden["tb_K10000_n473"]["y_obs"])
+        print(f"bench: tuberculosis {tb['n']} runs to {tb['n_stop']} cases", file=sys.stderr, flush=True)
+        tsamp_tb = P.make_sampling(tb["n"], 0, W.SAMPLING_SEED)
+        tcap_tb = 256
+        tidx_tb = torch.empty(tcap_tb, dtype=torch.int64, device="cuda")
+        tth_tb = torch.empty((3, tcap_tb), dtype=torch.float32, device="cuda")
+        tdd_tb = torch.empty(tcap_tb, dtype=torch.float32, device="cuda")
+        ev_tb = P.pps_tb_events(tspec_tb, tsamp_tb)
+        events_tb = int(ev_tb["events"].sum().item())
+        status_tb = np.bincount(ev_tb["status"].cpu().numpy(), minlength=3).tolist()
+        wall, kms = time_calls(P, torch, lambda: P.abc_sample(
+            tspec_tb, ty_tb, tsamp_tb, P.PPS_EPS_TOP_FRACTION, 0.01, tcap_tb, tidx_tb, tth_tb, tdd_tb), 1, 3)
+        tbw = {"sims_per_s": round(tb["n"] / wall, 1), "events_per_s": round(events_tb / wall, 1),
+               "ms": round(wall * 1e3, 3), "kernel_ms": round(kms, 3), "events": events_tb,
+               "complete_extinct_truncated": status_tb,
+               "kernel": "k_simulate_tb<64> (one run per workgroup, counts in LDS)",
+               "cycles_per_event_per_workgroup": round(kms * 1e-3 * CLOCK * 4 * CUS / events_tb, 1),
+               "paper_context": {"table": "B.2", "seconds": 183.0, "cpu": "Xeon Gold 6140",
+                                 "threads": 4, "code": "C, AVX512",
+                                 "note": "the paper's runs stop and sample by rules it does not print"}}
+        if args.cpu_sample > 0:
+            import oracle
+            tbs = 256
+            c0 = time.perf_counter()
+            oo = oracle.tb_simulate(tspec_tb, W.SAMPLING_SEED, 0, tbs)
+            c1 = time.perf_counter()
+            tbw["oracle"] = {"sims_per_s": round(tbs / (c1 - c0), 2),
+                             "events_per_s": round(float(oo["events"].sum()) / (c1 - c0), 1),
+                             "cores": oracle.threads(),
+                             "sample": f"draws [0, {tbs}) (the same runs, linear genotype lookup)"}
+        workloads[tb["name"]] = tbw
         if args.serving_jobs > 0:
             workloads["serving_mix"] = serving_bench(P, torch, W, golden, args.serving_jobs,
                                                      W.SERVING_MIX["rate_hz"])

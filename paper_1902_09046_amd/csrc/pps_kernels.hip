@@ -780,38 +780,42 @@ __global__ __launch_bounds__(BLOCK) void k_simulate_cells(const EpochHeader *__r
 // Tuberculosis transmission (App. B): one draw per 64-lane workgroup.
 //
 // A Gillespie run is a sequential Markov chain, so the lanes of a wave share
-// one run: the genotype counts live in LDS as leaves (one uint16 per slot,
-// PPS_TB_MAX_POP slots) under 64-slot block sums, and the lookup of the case
-// chosen by an event is a 64-way descent -- each lane sums four block sums,
-// a wave prefix scan and a ballot find the block, and a second scan over the
-// block's 64 leaves finds the slot -- in place of the paper's linear scan
-// over the genotype weights (same slot).  The lowest empty slot for a new
-// genotype is found the same way from per-block counts of occupied slots.
-// Runs end when the population reaches the stop size, dies out or hits the
-// event cap, and the workgroup takes the next draw from the tile queue at
-// once, so runs of very different lengths balance across the machine.
+// one run.  The genotype counts live in LDS as leaves (one uint16 per slot,
+// PPS_TB_MAX_POP slots); the counts of cases per block of 64 slots and of
+// occupied slots per block live in registers, four blocks per lane.  The
+// lookup of the case chosen by an event is a 64-way descent -- a wave
+// prefix scan (DPP) of the lanes' block sums and a ballot find the block,
+// one LDS read and a second scan over its 64 leaves find the slot -- in place
+// of the paper's linear scan over the genotype weights (same slot).  The
+// lowest empty slot for a new genotype is found the same way from the
+// occupied counts.  Runs end when the population reaches the stop size, dies
+// out or hits the event cap, and the workgroup takes the next draw from the
+// tile queue at once, so runs of very different lengths balance across the
+// machine.  The workgroup is one wave: LDS updates are ordered for the next
+// event by wave barriers (the wave's LDS operations complete in order).
 // ===========================================================================
 constexpr int TB_BLOCK = 64;
 constexpr int TB_SLOTS = PPS_TB_MAX_POP;
 constexpr int TB_NBLK = TB_SLOTS / 64;
-static_assert(TB_NBLK == 4 * TB_BLOCK, "four block sums per lane");
+static_assert(TB_NBLK == 4 * TB_BLOCK, "four blocks per lane");
 enum : int32_t { TB_COMPLETE = 0, TB_EXTINCT = 1, TB_TRUNCATED = 2 };
 
-__device__ __forceinline__ int tb_scan(int v)
+// Inclusive prefix sum over the 64 lanes: shifts within rows of 16 lanes,
+// then the row totals broadcast to the rows above (DPP).
+__device__ __forceinline__ int tb_scan(int x)
 {
-    const int lane = threadIdx.x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int o = __shfl_up(v, d, 64);
-        if (lane >= d)
-            v += o;
-    }
-    return v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
 }
 
 __device__ __forceinline__ int tb_first(unsigned long long mask)
 {
-    return __builtin_ffsll(static_cast<long long>(mask)) - 1;
+    return max(__builtin_ffsll(static_cast<long long>(mask)) - 1, 0);
 }
 
 __device__ __forceinline__ int tb_u16(uint64_t four, int k)
@@ -819,27 +823,29 @@ __device__ __forceinline__ int tb_u16(uint64_t four, int k)
     return static_cast<int>((four >> (16 * k)) & 0xffffu);
 }
 
+__device__ __forceinline__ uint64_t tb_readlane64(uint64_t v, int lane)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), lane);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), lane);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 struct TbPick {
-    int slot;   // the chosen slot
-    int blk;    // its block
-    int leaf;   // its count before the event
-    int bsum;   // its block sum before the event
+    int slot;  // the chosen slot
+    int leaf;  // its count before the event
 };
 
-// The slot holding case m (0 <= m < sum of the counts) in slot order.
-__device__ __forceinline__ TbPick tb_select(const uint16_t *leaf, const uint16_t *bsum, uint32_t m)
+// The slot holding case m (0 <= m < sum of the counts) in slot order; bs4
+// holds this lane's four block sums.  (The clamps only keep every index in
+// range; with consistent counts the ballots are never empty.)
+__device__ __forceinline__ TbPick tb_select(const uint16_t *leaf, uint64_t bs4, uint32_t m)
 {
     const int lane = threadIdx.x;
-    const uint64_t four = reinterpret_cast<const uint64_t *>(bsum)[lane];
-    const int c0 = tb_u16(four, 0), c1 = tb_u16(four, 1), c2 = tb_u16(four, 2), c3 = tb_u16(four, 3);
-    const int s4 = c0 + c1 + c2 + c3;
+    const int s4 = tb_u16(bs4, 0) + tb_u16(bs4, 1) + tb_u16(bs4, 2) + tb_u16(bs4, 3);
     const int incl = tb_scan(s4);
-    // (the clamps only keep every index in range; with consistent counts the
-    // ballots are never empty)
-    const int L = max(tb_first(__ballot(incl > static_cast<int>(m))), 0);
-    // lane L's four blocks and the cases before them (uniform)
-    const uint64_t fL = __shfl(four, L, 64);
-    int before = __shfl(incl - s4, L, 64);
+    const int L = tb_first(__ballot(incl > static_cast<int>(m)));
+    const uint64_t fL = tb_readlane64(bs4, L);
+    int before = __builtin_amdgcn_readlane(incl - s4, L);
     int k = 0, cb = tb_u16(fL, 0);
     while (k < 3 && static_cast<int>(m) >= before + cb) {
         before += cb;
@@ -847,33 +853,38 @@ __device__ __forceinline__ TbPick tb_select(const uint16_t *leaf, const uint16_t
         cb = tb_u16(fL, k);
     }
     const int b = 4 * L + k;
-    const int m1 = static_cast<int>(m) - before;
     const int v = leaf[64 * b + lane];
     const int incl2 = tb_scan(v);
-    const int L2 = max(tb_first(__ballot(incl2 > m1)), 0);
+    const int L2 = tb_first(__ballot(incl2 > static_cast<int>(m) - before));
     TbPick r;
     r.slot = 64 * b + L2;
-    r.blk = b;
-    r.leaf = __shfl(v, L2, 64);
-    r.bsum = cb;
+    r.leaf = __builtin_amdgcn_readlane(v, L2);
     return r;
 }
 
-// The lowest slot holding no case.
-__device__ __forceinline__ int tb_lowest_empty(const uint16_t *leaf, const uint16_t *occ)
+// The lowest slot holding no case; oc4 holds this lane's four occupied counts.
+__device__ __forceinline__ int tb_lowest_empty(const uint16_t *leaf, uint64_t oc4)
 {
     const int lane = threadIdx.x;
-    const uint64_t four = reinterpret_cast<const uint64_t *>(occ)[lane];
-    const bool has = tb_u16(four, 0) < 64 || tb_u16(four, 1) < 64 || tb_u16(four, 2) < 64 ||
-                     tb_u16(four, 3) < 64;
-    const int L = max(tb_first(__ballot(has)), 0);
-    const uint64_t fL = __shfl(four, L, 64);
+    const bool has = tb_u16(oc4, 0) < 64 || tb_u16(oc4, 1) < 64 || tb_u16(oc4, 2) < 64 ||
+                     tb_u16(oc4, 3) < 64;
+    const int L = tb_first(__ballot(has));
+    const uint64_t fL = tb_readlane64(oc4, L);
     int k = 0;
     while (k < 3 && tb_u16(fL, k) >= 64)
         ++k;
     const int b = 4 * L + k;
-    const int L2 = max(tb_first(__ballot(leaf[64 * b + lane] == 0)), 0);
+    const int L2 = tb_first(__ballot(leaf[64 * b + lane] == 0));
     return 64 * b + L2;
+}
+
+// +d (d = +1 or -1) to block b's field of the lane that holds it.
+__device__ __forceinline__ void tb_bump(uint64_t &four, int b, int d)
+{
+    if (static_cast<int>(threadIdx.x) == (b >> 2)) {
+        const uint64_t one = 1ull << (16 * (b & 3));
+        four = d > 0 ? four + one : four - one;
+    }
 }
 
 __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__restrict__ hdr,
@@ -881,8 +892,6 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
                                                         LaunchState *__restrict__ states)
 {
     __shared__ __align__(16) uint16_t s_leaf[TB_SLOTS];
-    __shared__ __align__(16) uint16_t s_bsum[TB_NBLK];
-    __shared__ __align__(16) uint16_t s_occ[TB_NBLK];
     __shared__ float s_samp[PPS_TB_MAX_SAMPLE];
     const int lane = threadIdx.x;
     const int n_jobs = static_cast<int>(hdr->class_rows[CLASS_GILLESPIE]);
@@ -893,7 +902,7 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         unsigned long long tl = 0;
         if (lane == 0)
             tl = atomicAdd(&state->next_tile, 1ull);
-        const uint64_t t = uniform_u64(__shfl(tl, 0, 64));
+        const uint64_t t = tb_readlane64(tl, 0);
         if (t >= total_tiles)
             break;
         int lo = 0, hi = n_jobs - 1;
@@ -920,61 +929,62 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         const uint32_t n_stop = static_cast<uint32_t>(J->n_cells);
         const uint64_t max_events = static_cast<uint64_t>(static_cast<uint32_t>(J->steps));
         const int nb_used = static_cast<int>((n_stop + 63) / 64);
-        // empty population of one genotype with x0 cases in slot 0
+        // one genotype with x0 cases in slot 0; blocks past the population
+        // count as full so that no new genotype goes there
+        uint32_t N = static_cast<uint32_t>(J->x0);
         for (int i = lane; i < nb_used * 64; i += TB_BLOCK)
             s_leaf[i] = 0;
-        for (int i = lane; i < TB_NBLK; i += TB_BLOCK) {
-            s_bsum[i] = 0;
-            s_occ[i] = i < nb_used ? 0 : 64;
+        uint64_t bs4 = 0, oc4 = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (4 * lane + k >= nb_used)
+                oc4 |= 64ull << (16 * k);
+        if (lane == 0) {
+            bs4 = N;
+            oc4 |= 1;
         }
         __syncthreads();
-        uint32_t N = static_cast<uint32_t>(J->x0);
-        if (lane == 0) {
+        if (lane == 0)
             s_leaf[0] = static_cast<uint16_t>(N);
-            s_bsum[0] = static_cast<uint16_t>(N);
-            s_occ[0] = 1;
-        }
         __syncthreads();
         uint64_t e = 0;
         Words4 w{};
         while (N > 0 && N < n_stop && e < max_events) {
             if ((e & 1) == 0)
-                w = stream_block(key, draw, static_cast<uint32_t>(e >> 1), PURPOSE_TB_EVENT);
+                w = stream_block_uniform(key, draw, static_cast<uint32_t>(e >> 1), PURPOSE_TB_EVENT);
             const uint32_t wc = (e & 1) ? w.z : w.x;
             const uint32_t wt = (e & 1) ? w.w : w.y;
             const uint32_t m = static_cast<uint32_t>((static_cast<uint64_t>(wc) * N) >> 32);
-            const TbPick pk = tb_select(s_leaf, s_bsum, m);
+            const TbPick pk = tb_select(s_leaf, bs4, m);
+            const int bk = pk.slot >> 6;
             if (static_cast<uint64_t>(wt) < t_birth) {
-                if (lane == 0) {
+                if (lane == 0)
                     s_leaf[pk.slot] = static_cast<uint16_t>(pk.leaf + 1);
-                    s_bsum[pk.blk] = static_cast<uint16_t>(pk.bsum + 1);
-                }
+                tb_bump(bs4, bk, +1);
                 ++N;
-                __syncthreads();
             } else {
                 // death or mutation: the case leaves its genotype
-                if (lane == 0) {
+                if (lane == 0)
                     s_leaf[pk.slot] = static_cast<uint16_t>(pk.leaf - 1);
-                    s_bsum[pk.blk] = static_cast<uint16_t>(pk.bsum - 1);
-                    if (pk.leaf == 1)
-                        s_occ[pk.blk] = static_cast<uint16_t>(s_occ[pk.blk] - 1);
-                }
-                __syncthreads();
+                tb_bump(bs4, bk, -1);
+                if (pk.leaf == 1)
+                    tb_bump(oc4, bk, -1);
                 if (static_cast<uint64_t>(wt) < t_death) {
                     --N;
                 } else {
                     // mutation: a new genotype in the lowest empty slot
-                    const int ns = tb_lowest_empty(s_leaf, s_occ);
-                    if (lane == 0) {
+                    __builtin_amdgcn_wave_barrier();
+                    const int ns = tb_lowest_empty(s_leaf, oc4);
+                    if (lane == 0)
                         s_leaf[ns] = 1;
-                        s_bsum[ns >> 6] = static_cast<uint16_t>(s_bsum[ns >> 6] + 1);
-                        s_occ[ns >> 6] = static_cast<uint16_t>(s_occ[ns >> 6] + 1);
-                    }
-                    __syncthreads();
+                    tb_bump(bs4, ns >> 6, +1);
+                    tb_bump(oc4, ns >> 6, +1);
                 }
             }
+            __builtin_amdgcn_wave_barrier();
             ++e;
         }
+        __syncthreads();
         const int32_t status = N >= n_stop ? TB_COMPLETE : (N == 0 ? TB_EXTINCT : TB_TRUNCATED);
         // summaries: n_sample cases without replacement (all when fewer)
         const uint32_t n_sample = static_cast<uint32_t>(J->n_sample);
@@ -984,16 +994,16 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
             Words4 ws{};
             for (uint32_t si = 0; si < n_sample; ++si) {
                 if ((si & 3) == 0)
-                    ws = stream_block(key, draw, si >> 2, PURPOSE_TB_SAMPLE);
+                    ws = stream_block_uniform(key, draw, si >> 2, PURPOSE_TB_SAMPLE);
                 const uint32_t wv = (si & 3) == 0 ? ws.x : ((si & 3) == 1 ? ws.y : ((si & 3) == 2 ? ws.z : ws.w));
                 const uint32_t m = static_cast<uint32_t>((static_cast<uint64_t>(wv) * (N - si)) >> 32);
-                const TbPick pk = tb_select(s_leaf, s_bsum, m);
+                const TbPick pk = tb_select(s_leaf, bs4, m);
                 if (lane == 0) {
                     s_leaf[pk.slot] = static_cast<uint16_t>(pk.leaf - 1);
-                    s_bsum[pk.blk] = static_cast<uint16_t>(pk.bsum - 1);
                     s_samp[si] = static_cast<float>(pk.slot);
                 }
-                __syncthreads();
+                tb_bump(bs4, pk.slot >> 6, -1);
+                __builtin_amdgcn_wave_barrier();
             }
             unsigned n2 = 1;
             while (n2 < n_sample)
