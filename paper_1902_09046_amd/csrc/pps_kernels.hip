@@ -924,14 +924,18 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         // event-type thresholds: single IEEE FP64 operations (as the oracle)
         const double ad = __dadd_rn(theta[0], theta[1]);
         const double rate = __dadd_rn(ad, theta[2]);
-        const uint64_t t_birth = static_cast<uint64_t>(floor(ldexp(__ddiv_rn(theta[0], rate), 32)));
-        const uint64_t t_death = static_cast<uint64_t>(floor(ldexp(__ddiv_rn(ad, rate), 32)));
+        // (equal in every lane: moved to scalar registers so that the event
+        // loop's branches and counters stay on the scalar unit)
+        const uint64_t t_birth =
+            tb_readlane64(static_cast<uint64_t>(floor(ldexp(__ddiv_rn(theta[0], rate), 32))), 0);
+        const uint64_t t_death =
+            tb_readlane64(static_cast<uint64_t>(floor(ldexp(__ddiv_rn(ad, rate), 32))), 0);
         const uint32_t n_stop = static_cast<uint32_t>(J->n_cells);
         const uint64_t max_events = static_cast<uint64_t>(static_cast<uint32_t>(J->steps));
         const int nb_used = static_cast<int>((n_stop + 63) / 64);
         // one genotype with x0 cases in slot 0; blocks past the population
         // count as full so that no new genotype goes there
-        uint32_t N = static_cast<uint32_t>(J->x0);
+        uint32_t N = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(J->x0));
         for (int i = lane; i < nb_used * 64; i += TB_BLOCK)
             s_leaf[i] = 0;
         uint64_t bs4 = 0, oc4 = 0;
