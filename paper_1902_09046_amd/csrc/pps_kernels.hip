@@ -780,48 +780,31 @@ __global__ __launch_bounds__(BLOCK) void k_simulate_cells(const EpochHeader *__r
 // Tuberculosis transmission (App. B): one draw per 64-lane workgroup.
 //
 // A Gillespie run is a sequential Markov chain, so the lanes of a wave share
-// one run.  The genotype counts live in LDS as leaves (one uint16 per slot,
-// PPS_TB_MAX_POP slots); the counts of cases per block of 64 slots and of
-// occupied slots per block live in registers, four blocks per lane.  The
-// lookup of the case chosen by an event is a 64-way descent -- a wave
-// prefix scan (DPP) of the lanes' block sums and a ballot find the block,
-// one LDS read and a second scan over its 64 leaves find the slot -- in place
-// of the paper's linear scan over the genotype weights (same slot).  The
-// lowest empty slot for a new genotype is found the same way from the
-// occupied counts.  Runs end when the population reaches the stop size, dies
-// out or hits the event cap, and the workgroup takes the next draw from the
-// tile queue at once, so runs of very different lengths balance across the
-// machine.  The workgroup is one wave: LDS updates are ordered for the next
-// event by wave barriers (the wave's LDS operations complete in order).
+// one run.  The genotype slots (PPS_TB_MAX_POP of them) are cut into rows of
+// 64; LDS holds each row as the inclusive prefix sums of its slots' counts
+// (uint16), and registers hold, four rows per lane, the rows' case totals and
+// occupied-slot counts, plus each lane's exclusive prefix of the totals over
+// the lanes before it.  The case chosen by an event is found by a 64-way
+// descent: a ballot over the lane prefixes picks the lane, a scalar compare
+// over its four totals the row, and a ballot over the row's prefixes the slot
+// -- the same slot as the paper's linear scan over the genotype weights.  An
+// update adds +-1 to the row's prefixes from the slot on (one LDS row
+// read-modify-write) and to the register totals.  The lowest empty slot for
+// a new genotype is found the same way from the occupied counts.  The event
+// words of 64 Philox blocks (128 events) are drawn at once, one block per
+// lane, and read out by lane index.  Runs end when the population reaches the
+// stop size, dies out or hits the event cap, and the workgroup takes the next
+// draw from the tile queue at once, so runs of very different lengths balance
+// across the machine.  The workgroup is one wave: its LDS operations complete
+// in order, and wave barriers keep the compiler from reordering them.
 // ===========================================================================
 constexpr int TB_BLOCK = 64;
 constexpr int TB_SLOTS = PPS_TB_MAX_POP;
-constexpr int TB_NBLK = TB_SLOTS / 64;
-static_assert(TB_NBLK == 4 * TB_BLOCK, "four blocks per lane");
+constexpr int TB_NROW = TB_SLOTS / 64;
+static_assert(TB_NROW == 4 * TB_BLOCK, "four rows per lane");
 enum : int32_t { TB_COMPLETE = 0, TB_EXTINCT = 1, TB_TRUNCATED = 2 };
-
-// Inclusive prefix sum over the 64 lanes: shifts within rows of 16 lanes,
-// then the row totals broadcast to the rows above (DPP).
-__device__ __forceinline__ int tb_scan(int x)
-{
-    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
-    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
-    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
-    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
-    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
-    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
-    return x;
-}
-
-__device__ __forceinline__ int tb_first(unsigned long long mask)
-{
-    return max(__builtin_ffsll(static_cast<long long>(mask)) - 1, 0);
-}
-
-__device__ __forceinline__ int tb_u16(uint64_t four, int k)
-{
-    return static_cast<int>((four >> (16 * k)) & 0xffffu);
-}
+// bit 6 of every 16-bit field: set exactly when a row's occupied count is 64
+constexpr uint64_t TB_FULL_BITS = 0x0040004000400040ull;
 
 __device__ __forceinline__ uint64_t tb_readlane64(uint64_t v, int lane)
 {
@@ -830,68 +813,96 @@ __device__ __forceinline__ uint64_t tb_readlane64(uint64_t v, int lane)
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-struct TbPick {
-    int slot;  // the chosen slot
-    int leaf;  // its count before the event
+// Lowest set lane of a ballot (63 for an empty one: only keeps indices in
+// range; the ballots below are never empty with consistent counts).
+__device__ __forceinline__ int tb_first(unsigned long long mask)
+{
+    return __builtin_ctzll(mask | (1ull << 63));
+}
+
+// Register half of the counts: rows 4 lane + j, j = 0..3, in 16-bit fields.
+struct TbRegs {
+    uint64_t tot4;  // cases per row
+    uint64_t occ4;  // occupied slots per row (rows past the population: 64)
+    int excl;       // cases in the rows of lower lanes
 };
 
-// The slot holding case m (0 <= m < sum of the counts) in slot order; bs4
-// holds this lane's four block sums.  (The clamps only keep every index in
-// range; with consistent counts the ballots are never empty.)
-__device__ __forceinline__ TbPick tb_select(const uint16_t *leaf, uint64_t bs4, uint32_t m)
+struct TbHit {
+    int grp;   // lane holding the row's totals
+    int fld;   // the row's field in that lane
+    int row;   // 4 grp + fld
+    int col;   // slot within the row
+    int leaf;  // the slot's count before the event
+    int pre;   // this lane's prefix in the row
+};
+
+// The slot holding case m (0 <= m < number of cases) in slot order.
+__device__ __forceinline__ TbHit tb_find(const uint16_t *pre, const TbRegs &c, uint32_t m)
 {
     const int lane = threadIdx.x;
-    const int s4 = tb_u16(bs4, 0) + tb_u16(bs4, 1) + tb_u16(bs4, 2) + tb_u16(bs4, 3);
-    const int incl = tb_scan(s4);
-    const int L = tb_first(__ballot(incl > static_cast<int>(m)));
-    const uint64_t fL = tb_readlane64(bs4, L);
-    int before = __builtin_amdgcn_readlane(incl - s4, L);
-    int k = 0, cb = tb_u16(fL, 0);
-    while (k < 3 && static_cast<int>(m) >= before + cb) {
-        before += cb;
-        ++k;
-        cb = tb_u16(fL, k);
-    }
-    const int b = 4 * L + k;
-    const int v = leaf[64 * b + lane];
-    const int incl2 = tb_scan(v);
-    const int L2 = tb_first(__ballot(incl2 > static_cast<int>(m) - before));
-    TbPick r;
-    r.slot = 64 * b + L2;
-    r.leaf = __builtin_amdgcn_readlane(v, L2);
-    return r;
+    TbHit h;
+    // the last lane whose lower lanes hold at most m cases (lane 0 always)
+    h.grp = 63 - __builtin_clzll(__ballot(c.excl <= static_cast<int>(m)) | 1ull);
+    const int r = static_cast<int>(m) - __builtin_amdgcn_readlane(c.excl, h.grp);
+    const uint64_t f = tb_readlane64(c.tot4, h.grp);
+    const int f0 = static_cast<int>(f & 0xffffu);
+    const int f1 = static_cast<int>((f >> 16) & 0xffffu);
+    const int f2 = static_cast<int>((f >> 32) & 0xffffu);
+    // all ones when r >= the cases of the lane's first 1, 2, 3 rows (the
+    // sign of a difference of values below 2^15; no branches)
+    const int m0 = (f0 - 1 - r) >> 31;
+    const int m1 = (f0 + f1 - 1 - r) >> 31;
+    const int m2 = (f0 + f1 + f2 - 1 - r) >> 31;
+    h.fld = -(m0 + m1 + m2);
+    const int before = (f0 & m0) + (f1 & m1) + (f2 & m2);
+    h.row = 4 * h.grp + h.fld;
+    h.pre = pre[64 * h.row + lane];
+    h.col = tb_first(__ballot(h.pre > r - before));
+    // the slot's count: its prefix minus the one before it (two lane reads
+    // of the row itself; a lane read of a DPP result issued right after the
+    // DPP instruction was seen to return stale values on gfx950)
+    const int below = __builtin_amdgcn_readlane(h.pre, (h.col + 63) & 63);
+    h.leaf = __builtin_amdgcn_readlane(h.pre, h.col) - (h.col > 0 ? below : 0);
+    return h;
 }
 
-// The lowest slot holding no case; oc4 holds this lane's four occupied counts.
-__device__ __forceinline__ int tb_lowest_empty(const uint16_t *leaf, uint64_t oc4)
+// Adds d to slot (row, col) whose prefix row this lane holds as p, and d
+// cases / o occupied slots to the row's register totals.
+__device__ __forceinline__ void tb_add(uint16_t *pre, TbRegs &c, int grp, int fld, int row, int col,
+                                       int p, int d, int o)
 {
     const int lane = threadIdx.x;
-    const bool has = tb_u16(oc4, 0) < 64 || tb_u16(oc4, 1) < 64 || tb_u16(oc4, 2) < 64 ||
-                     tb_u16(oc4, 3) < 64;
-    const int L = tb_first(__ballot(has));
-    const uint64_t fL = tb_readlane64(oc4, L);
-    int k = 0;
-    while (k < 3 && tb_u16(fL, k) >= 64)
-        ++k;
-    const int b = 4 * L + k;
-    const int L2 = tb_first(__ballot(leaf[64 * b + lane] == 0));
-    return 64 * b + L2;
+    pre[64 * row + lane] = static_cast<uint16_t>(p + (lane >= col ? d : 0));
+    const int sh = 16 * fld;
+    const uint64_t dd = static_cast<uint64_t>(static_cast<int64_t>(d)) << sh;
+    const uint64_t od = static_cast<uint64_t>(static_cast<int64_t>(o)) << sh;
+    if (lane == grp) {
+        c.tot4 += dd;
+        c.occ4 += od;
+    }
+    c.excl += lane > grp ? d : 0;
 }
 
-// +d (d = +1 or -1) to block b's field of the lane that holds it.
-__device__ __forceinline__ void tb_bump(uint64_t &four, int b, int d)
+// A new genotype: one case in the lowest empty slot.
+__device__ __forceinline__ void tb_new_genotype(uint16_t *pre, TbRegs &c)
 {
-    if (static_cast<int>(threadIdx.x) == (b >> 2)) {
-        const uint64_t one = 1ull << (16 * (b & 3));
-        four = d > 0 ? four + one : four - one;
-    }
+    const int lane = threadIdx.x;
+    const int grp = tb_first(__ballot((c.occ4 & TB_FULL_BITS) != TB_FULL_BITS));
+    const uint64_t f = tb_readlane64(c.occ4, grp);
+    // bit 6 + 16 j of ~f: row j of the lane is not full
+    const int fld = __builtin_ctzll((~f & TB_FULL_BITS) | (1ull << 63)) >> 4;
+    const int row = 4 * grp + fld;
+    const int p = pre[64 * row + lane];
+    const int cnt = p - __builtin_amdgcn_update_dpp(0, p, 0x138, 0xF, 0xF, false);
+    const int col = tb_first(__ballot(cnt == 0));
+    tb_add(pre, c, grp, fld, row, col, p, 1, 1);
 }
 
 __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__restrict__ hdr,
                                                         const JobDev *__restrict__ rows,
                                                         LaunchState *__restrict__ states)
 {
-    __shared__ __align__(16) uint16_t s_leaf[TB_SLOTS];
+    __shared__ __align__(16) uint16_t s_pre[TB_SLOTS];
     __shared__ float s_samp[PPS_TB_MAX_SAMPLE];
     const int lane = threadIdx.x;
     const int n_jobs = static_cast<int>(hdr->class_rows[CLASS_GILLESPIE]);
@@ -921,72 +932,69 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         const StreamKey key = make_key(J->seed);
         double theta[3];
         prior_draw<3>(J->prior, 3, J->constraint, key, draw, theta);
-        // event-type thresholds: single IEEE FP64 operations (as the oracle)
+        // event-type thresholds: single IEEE FP64 operations (as the oracle),
+        // floor(2^32 alpha/R) and floor(2^32 (alpha + delta)/R), at most 2^32
         const double ad = __dadd_rn(theta[0], theta[1]);
         const double rate = __dadd_rn(ad, theta[2]);
-        // (equal in every lane: moved to scalar registers so that the event
-        // loop's branches and counters stay on the scalar unit)
         const uint64_t t_birth =
             tb_readlane64(static_cast<uint64_t>(floor(ldexp(__ddiv_rn(theta[0], rate), 32))), 0);
         const uint64_t t_death =
             tb_readlane64(static_cast<uint64_t>(floor(ldexp(__ddiv_rn(ad, rate), 32))), 0);
+        // word < threshold as 32-bit compares: a threshold of 2^32 takes every word
+        const uint32_t tb32 = static_cast<uint32_t>(min(t_birth, 0xffffffffull));
+        const uint32_t td32 = static_cast<uint32_t>(min(t_death, 0xffffffffull));
+        const bool b_all = t_birth > 0xffffffffull, d_all = t_death > 0xffffffffull;
         const uint32_t n_stop = static_cast<uint32_t>(J->n_cells);
-        const uint64_t max_events = static_cast<uint64_t>(static_cast<uint32_t>(J->steps));
-        const int nb_used = static_cast<int>((n_stop + 63) / 64);
-        // one genotype with x0 cases in slot 0; blocks past the population
+        const uint32_t max_events = static_cast<uint32_t>(J->steps);
+        const int nr_used = static_cast<int>((n_stop + 63) / 64);
+        // one genotype with x0 cases in slot 0; rows past the population
         // count as full so that no new genotype goes there
         uint32_t N = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(J->x0));
-        for (int i = lane; i < nb_used * 64; i += TB_BLOCK)
-            s_leaf[i] = 0;
-        uint64_t bs4 = 0, oc4 = 0;
+        for (int i = lane; i < nr_used * 64; i += TB_BLOCK)
+            s_pre[i] = i < 64 ? static_cast<uint16_t>(N) : 0;
+        TbRegs c;
+        c.tot4 = lane == 0 ? N : 0;
+        c.occ4 = lane == 0 ? 1 : 0;
+        c.excl = lane == 0 ? 0 : static_cast<int>(N);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (4 * lane + k >= nb_used)
-                oc4 |= 64ull << (16 * k);
-        if (lane == 0) {
-            bs4 = N;
-            oc4 |= 1;
-        }
+            if (4 * lane + k >= nr_used)
+                c.occ4 |= 64ull << (16 * k);
         __syncthreads();
-        if (lane == 0)
-            s_leaf[0] = static_cast<uint16_t>(N);
-        __syncthreads();
-        uint64_t e = 0;
-        Words4 w{};
-        while (N > 0 && N < n_stop && e < max_events) {
-            if ((e & 1) == 0)
-                w = stream_block_uniform(key, draw, static_cast<uint32_t>(e >> 1), PURPOSE_TB_EVENT);
-            const uint32_t wc = (e & 1) ? w.z : w.x;
-            const uint32_t wt = (e & 1) ? w.w : w.y;
-            const uint32_t m = static_cast<uint32_t>((static_cast<uint64_t>(wc) * N) >> 32);
-            const TbPick pk = tb_select(s_leaf, bs4, m);
-            const int bk = pk.slot >> 6;
-            if (static_cast<uint64_t>(wt) < t_birth) {
-                if (lane == 0)
-                    s_leaf[pk.slot] = static_cast<uint16_t>(pk.leaf + 1);
-                tb_bump(bs4, bk, +1);
-                ++N;
-            } else {
-                // death or mutation: the case leaves its genotype
-                if (lane == 0)
-                    s_leaf[pk.slot] = static_cast<uint16_t>(pk.leaf - 1);
-                tb_bump(bs4, bk, -1);
-                if (pk.leaf == 1)
-                    tb_bump(oc4, bk, -1);
-                if (static_cast<uint64_t>(wt) < t_death) {
-                    --N;
-                } else {
-                    // mutation: a new genotype in the lowest empty slot
-                    __builtin_amdgcn_wave_barrier();
-                    const int ns = tb_lowest_empty(s_leaf, oc4);
-                    if (lane == 0)
-                        s_leaf[ns] = 1;
-                    tb_bump(bs4, ns >> 6, +1);
-                    tb_bump(oc4, ns >> 6, +1);
-                }
+        // one event with words (wc, wt); false once the run has ended
+        uint32_t e = 0;
+        auto event = [&](uint32_t wc, uint32_t wt) {
+            const uint32_t m = __umulhi(wc, N);
+            const TbHit h = tb_find(s_pre, c, m);
+            const bool birth = b_all || wt < tb32;
+            const bool death = !birth && (d_all || wt < td32);
+            const int d = birth ? 1 : -1;
+            const int o = (!birth && h.leaf == 1) ? -1 : 0;
+            tb_add(s_pre, c, h.grp, h.fld, h.row, h.col, h.pre, d, o);
+            N = birth ? N + 1 : (death ? N - 1 : N);
+            if (!birth && !death) {
+                // mutation: the case leaves its genotype for a new one in
+                // the lowest empty slot (after the parent's count dropped)
+                __builtin_amdgcn_wave_barrier();
+                tb_new_genotype(s_pre, c);
             }
             __builtin_amdgcn_wave_barrier();
             ++e;
+        };
+        // running: 0 < N < n_stop and e < max_events
+        auto running = [&]() { return N - 1 < n_stop - 1 && e < max_events; };
+        while (running()) {
+            // events e .. e + 127: block e/2 + j in lane j (e is even here)
+            const Words4 wv = stream_block(key, draw, (e >> 1) + static_cast<uint32_t>(lane),
+                                           PURPOSE_TB_EVENT);
+            for (int j = 0; j < 64; ++j) {
+                event(__builtin_amdgcn_readlane(wv.x, j), __builtin_amdgcn_readlane(wv.y, j));
+                if (!running())
+                    break;
+                event(__builtin_amdgcn_readlane(wv.z, j), __builtin_amdgcn_readlane(wv.w, j));
+                if (!running())
+                    break;
+            }
         }
         __syncthreads();
         const int32_t status = N >= n_stop ? TB_COMPLETE : (N == 0 ? TB_EXTINCT : TB_TRUNCATED);
@@ -995,19 +1003,22 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         uint64_t g = 0, sq = 0, n_taken = 0;
         if (N >= n_sample) {
             n_taken = n_sample;
-            Words4 ws{};
-            for (uint32_t si = 0; si < n_sample; ++si) {
-                if ((si & 3) == 0)
-                    ws = stream_block_uniform(key, draw, si >> 2, PURPOSE_TB_SAMPLE);
-                const uint32_t wv = (si & 3) == 0 ? ws.x : ((si & 3) == 1 ? ws.y : ((si & 3) == 2 ? ws.z : ws.w));
-                const uint32_t m = static_cast<uint32_t>((static_cast<uint64_t>(wv) * (N - si)) >> 32);
-                const TbPick pk = tb_select(s_leaf, bs4, m);
-                if (lane == 0) {
-                    s_leaf[pk.slot] = static_cast<uint16_t>(pk.leaf - 1);
-                    s_samp[si] = static_cast<float>(pk.slot);
+            // sample s: word s%4 of block s/4; 64 blocks (256 samples) at a time
+            for (uint32_t s0 = 0; s0 < n_sample; s0 += 256) {
+                const Words4 ws = stream_block(key, draw, (s0 >> 2) + static_cast<uint32_t>(lane),
+                                               PURPOSE_TB_SAMPLE);
+                const uint32_t s_end = min(n_sample, s0 + 256);
+                for (uint32_t si = s0; si < s_end; ++si) {
+                    const int j = static_cast<int>((si - s0) >> 2);
+                    const int wsel = static_cast<int>(si & 3);
+                    const uint32_t wv = __builtin_amdgcn_readlane(
+                        wsel == 0 ? ws.x : (wsel == 1 ? ws.y : (wsel == 2 ? ws.z : ws.w)), j);
+                    const TbHit h = tb_find(s_pre, c, __umulhi(wv, N - si));
+                    tb_add(s_pre, c, h.grp, h.fld, h.row, h.col, h.pre, -1, 0);
+                    if (lane == 0)
+                        s_samp[si] = static_cast<float>(64 * h.row + h.col);
+                    __builtin_amdgcn_wave_barrier();
                 }
-                tb_bump(bs4, pk.slot >> 6, -1);
-                __builtin_amdgcn_wave_barrier();
             }
             unsigned n2 = 1;
             while (n2 < n_sample)
@@ -1034,8 +1045,10 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         } else if (N > 0) {
             n_taken = N;
             uint64_t gl = 0, sl = 0;
-            for (int i = lane; i < nb_used * 64; i += TB_BLOCK) {
-                const uint64_t v = s_leaf[i];
+            for (int r = 0; r < nr_used; ++r) {
+                const int p = s_pre[64 * r + lane];
+                const uint64_t v = static_cast<uint32_t>(
+                    p - __builtin_amdgcn_update_dpp(0, p, 0x138, 0xF, 0xF, false));
                 gl += v > 0;
                 sl += v * v;
             }
