@@ -461,6 +461,7 @@ def main():
         tdd_tb = torch.empty(tcap_tb, dtype=torch.float32, device="cuda")
         ev_tb = P.pps_tb_events(tspec_tb, tsamp_tb)
         events_tb = int(ev_tb["events"].sum().item())
+        longest_tb = int(ev_tb["events"].max().item())
         status_tb = np.bincount(ev_tb["status"].cpu().numpy(), minlength=3).tolist()
         wall, kms = time_calls(P, torch, lambda: P.abc_sample(
             tspec_tb, ty_tb, tsamp_tb, P.PPS_EPS_TOP_FRACTION, 0.01, tcap_tb, tidx_tb, tth_tb, tdd_tb), 1, 3)
@@ -469,6 +470,11 @@ def main():
                "complete_extinct_truncated": status_tb,
                "kernel": "k_simulate_tb<64> (one run per workgroup, counts in LDS)",
                "cycles_per_event_per_workgroup": round(kms * 1e-3 * CLOCK * 4 * CUS / events_tb, 1),
+               # a run is a serial chain: the batch cannot end before its
+               # longest run, so the latency view is the kernel time per
+               # event of that run (an upper bound on one event's latency)
+               "longest_run_events": longest_tb,
+               "cycles_per_event_longest_run": round(kms * 1e-3 * CLOCK / max(longest_tb, 1), 1),
                "paper_context": {"table": "B.2", "seconds": 183.0, "cpu": "Xeon Gold 6140",
                                  "threads": 4, "code": "C, AVX512",
                                  "note": "the paper's runs stop and sample by rules it does not print"}}
