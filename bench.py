@@ -332,6 +332,24 @@ def main():
             "kernel_ms": round(kms, 3), "valu_frac": round(pops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
             "kernel": "k_simulate_group<256,8>",
             "traffic": measured_traffic("k_simulate_group_pvalue_64x1e6")}
+        if args.cpu_sample > 0:
+            # the oracle on the first 1e4 draws of every lambda, timed, and the
+            # device's counts on the same draws: equal for lambda <= 1; above,
+            # draws in the chaotic regime of the logistic map may flip
+            import oracle
+            psn = 10_000
+            c0 = time.perf_counter()
+            po = oracle.pvalue(pspec, 0, "lognormal", lam, W.SAMPLING_SEED, 0, psn, t_obs)
+            c1 = time.perf_counter()
+            pc, _ = P.prior_pred_pvalue(pspec, 0, P.PPS_LOGNORMAL, lam,
+                                        P.make_sampling(psn, 0, W.SAMPLING_SEED), t_obs)
+            pdiff = np.abs(np.asarray(pc, np.int64) - po["count_ge"].astype(np.int64))
+            small = np.asarray(lam) <= 1.0
+            workloads["pvalue_logistic_64lambda_n1e6"]["oracle"] = {
+                "sims_per_s": round(64 * psn / (c1 - c0), 1), "cores": oracle.threads(),
+                "sample": f"draws [0, {psn}) of each of the 64 lambda values (FP64)",
+                "count_diff_lambda_le_1": int(pdiff[small].max()),
+                "count_diff_lambda_gt_1_max": int(pdiff[~small].max())}
         # GARCH(1,1) prior-predictive check: 1e6 series of length 2000,
         # 14 summaries per draw written out, then tail-area tallies.
         gspec = W.garch_spec(series_len=2000)
@@ -347,6 +365,28 @@ def main():
             "valu_frac": round(gops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
             "kernel": "k_simulate<256,garch>",
             "traffic": measured_traffic("k_simulate_garch_L2000_n1e6")}
+        if args.cpu_sample > 0:
+            # the device's FP32 streaming summaries of the first 1e4 draws
+            # against the oracle's FP64 two-pass ones: the mean relative to
+            # the series sd, variance and kurtosis relative, skewness and the
+            # ten squared-return ACFs absolute (they sit near 0)
+            import oracle
+            gsn = 10_000
+            c0 = time.perf_counter()
+            go = oracle.simulate(gspec, W.SAMPLING_SEED, 0, gsn)["summ"]
+            c1 = time.perf_counter()
+            gd = gsm[:, :gsn].cpu().numpy().T.astype(np.float64)
+            gerr = {"mean": np.abs(gd[:, 0] - go[:, 0]) / np.sqrt(go[:, 1]),
+                    "var": np.abs(gd[:, 1] - go[:, 1]) / np.abs(go[:, 1]),
+                    "skew": np.abs(gd[:, 2] - go[:, 2]),
+                    "kurt": np.abs(gd[:, 3] - go[:, 3]) / np.abs(go[:, 3]),
+                    "acf": np.abs(gd[:, 4:] - go[:, 4:]).max(axis=1)}
+            workloads["garch11_L2000_n1e6_summaries"]["error_vs_oracle"] = {
+                k: {"max": float(f"{v.max():.3g}"), "median": float(f"{np.median(v):.3g}")}
+                for k, v in gerr.items()}
+            workloads["garch11_L2000_n1e6_summaries"]["oracle"] = {
+                "sims_per_s": round(gsn / (c1 - c0), 1), "cores": oracle.threads(),
+                "sample": f"draws [0, {gsn}), two-pass FP64 summaries"}
         # The paper's own prior-predictive run (Sec. 3.2, Table A.1): the
         # genetic toggle switch, N = 8064 draws x 8000 cells x 599 steps,
         # each draw reduced to 19 quantiles; ABC keeps the closest 1 %.
