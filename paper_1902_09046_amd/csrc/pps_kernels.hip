@@ -795,7 +795,8 @@ __global__ __launch_bounds__(BLOCK) void k_simulate_cells(const EpochHeader *__r
 // lane, and read out by lane index.  Runs end when the population reaches the
 // stop size, dies out or hits the event cap, and the workgroup takes the next
 // draw from the tile queue at once, so runs of very different lengths balance
-// across the machine.  The workgroup is one wave: its LDS operations complete
+// across the machine; the queue is walked twice, the runs predicted from theta
+// to be long first.  The workgroup is one wave: its LDS operations complete
 // in order, and wave barriers keep the compiler from reordering them.
 // ===========================================================================
 constexpr int TB_BLOCK = 64;
@@ -909,13 +910,19 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
     const uint64_t total_tiles = hdr->class_tiles[CLASS_GILLESPIE];
     const JobDev *__restrict__ jobs = rows + hdr->class_first[CLASS_GILLESPIE];
     LaunchState *__restrict__ state = states + CLASS_GILLESPIE;
+    // Two passes over the tiles: the first runs the draws whose run is
+    // predicted to be long, the second the rest, so that the long runs start
+    // at once and the short ones fill the machine around them (the order of
+    // the runs changes no result: every draw writes its own outputs).
     for (;;) {
         unsigned long long tl = 0;
         if (lane == 0)
             tl = atomicAdd(&state->next_tile, 1ull);
-        const uint64_t t = tb_readlane64(tl, 0);
-        if (t >= total_tiles)
+        const uint64_t t2 = tb_readlane64(tl, 0);
+        if (t2 >= 2 * total_tiles)
             break;
+        const bool long_pass = t2 < total_tiles;
+        const uint64_t t = long_pass ? t2 : t2 - total_tiles;
         int lo = 0, hi = n_jobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -932,6 +939,21 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         const StreamKey key = make_key(J->seed);
         double theta[3];
         prior_draw<3>(J->prior, 3, J->constraint, key, draw, theta);
+        const uint32_t n_stop = static_cast<uint32_t>(J->n_cells);
+        const uint32_t max_events = static_cast<uint32_t>(J->steps);
+        // predicted length: a supercritical run that survives grows at rate
+        // (alpha - delta) per case against (alpha + delta + tau) events per
+        // case, so it takes about n_stop (alpha + delta + tau)/(alpha - delta)
+        // events; long means at least a quarter of the event cap, and runs
+        // that are not supercritical count as long
+        const double gap = theta[0] - theta[1];
+        const bool is_long =
+            __builtin_amdgcn_readfirstlane(
+                !(gap > 0.0) ||
+                static_cast<double>(n_stop) * (theta[0] + theta[1] + theta[2]) >=
+                    gap * (static_cast<double>(max_events) * 0.25)) != 0;
+        if (is_long != long_pass)
+            continue;
         // event-type thresholds: single IEEE FP64 operations (as the oracle),
         // floor(2^32 alpha/R) and floor(2^32 (alpha + delta)/R), at most 2^32
         const double ad = __dadd_rn(theta[0], theta[1]);
@@ -944,8 +966,6 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         const uint32_t tb32 = static_cast<uint32_t>(min(t_birth, 0xffffffffull));
         const uint32_t td32 = static_cast<uint32_t>(min(t_death, 0xffffffffull));
         const bool b_all = t_birth > 0xffffffffull, d_all = t_death > 0xffffffffull;
-        const uint32_t n_stop = static_cast<uint32_t>(J->n_cells);
-        const uint32_t max_events = static_cast<uint32_t>(J->steps);
         const int nr_used = static_cast<int>((n_stop + 63) / 64);
         // one genotype with x0 cases in slot 0; rows past the population
         // count as full so that no new genotype goes there
