@@ -55,28 +55,6 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     return {c0, c1, c2, c3};
 }
 
-// The same generator for a counter that is equal in every lane (a draw that
-// a whole workgroup simulates): plain xors keep it on the scalar unit, where
-// a 32x32 multiply costs one instruction instead of a quarter-rate vector one.
-__device__ __forceinline__ Words4 philox4x32_10_uniform(uint32_t c0, uint32_t c1, uint32_t c2,
-                                                        uint32_t c3, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
-        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-        const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
-        const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
-        c0 = hi1 ^ c1 ^ k0;
-        c2 = hi0 ^ c3 ^ k1;
-        c1 = lo1;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return {c0, c1, c2, c3};
-}
-
 // Stream purposes: prior draws, the path of a one-lane model, and cell c of a
 // multi-cell model (the toggle switch) as PURPOSE_CELL0 + c.
 enum : uint32_t {
@@ -100,14 +78,6 @@ __device__ __forceinline__ Words4 stream_block(StreamKey key, uint64_t draw, uin
                                                uint32_t purpose)
 {
     return philox4x32_10(block, purpose, static_cast<uint32_t>(draw),
-                         static_cast<uint32_t>(draw >> 32), key.k0, key.k1);
-}
-
-// stream_block for wave-uniform arguments (scalar unit).
-__device__ __forceinline__ Words4 stream_block_uniform(StreamKey key, uint64_t draw, uint32_t block,
-                                               uint32_t purpose)
-{
-    return philox4x32_10_uniform(block, purpose, static_cast<uint32_t>(draw),
                          static_cast<uint32_t>(draw >> 32), key.k0, key.k1);
 }
 
