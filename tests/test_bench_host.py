@@ -1,0 +1,61 @@
+"""Host-side contract of bench.py (no GPU): the one-GPU refusal, the operation
+counts behind the roofline figures, and the rule that measured HBM traffic is
+reported only for the kernel sources it was measured on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "8"], {}),
+                                      ([], {"WORLD_SIZE": "2"})])
+def test_more_than_one_gpu_is_refused_with_a_message(argv, env):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv],
+                       capture_output=True, text=True, env={**os.environ, **env}, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_operation_counts_of_the_roofline():
+    # per EM step: a quarter Philox call (60), half a Box-Muller pair per
+    # normal (2 x 12 per call of four normals), the EM update (4)
+    assert bench.ops_per_draw(1000, 20) == 1000 * ((60 + 24) / 4 + 4) + 20 * 9 + 250 == 25430
+    # a draw-group of 8 lambda values: one normal per step, 8 EM updates,
+    # 8 Kahan means per observation, 7 extra lambda'd prior values
+    assert bench.ops_per_group_draw(1000, 20) == 1000 * (21 + 32) + 20 * 32 + 250 + 7 * 160 == 55010
+    # toggle switch: 62 per cell-step, 15 per cell, 600 per draw
+    assert bench.toggle_ops_per_draw(8000, 599) == 8000 * (599 * 62 + 15) + 600
+    assert bench.VALU_PEAK_OPS == 256 * 128 * 2.4e9
+
+
+def test_kernel_source_families_exist():
+    csrc = os.path.join(ROOT, "paper_1902_09046_amd", "csrc")
+    for fam, names in bench.KERNEL_SOURCES.items():
+        for n in names:
+            assert os.path.exists(os.path.join(csrc, n)), (fam, n)
+        assert len(bench.kernel_source_digest(fam)) == 64
+
+
+def test_traffic_is_reported_only_for_the_measured_sources(monkeypatch):
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+        table = json.load(f)
+    entries = {k: e for k, e in table.items() if isinstance(e, dict) and "bytes_per_launch" in e}
+    assert entries
+    for key, e in entries.items():
+        # the recorded digest: the measured bytes
+        monkeypatch.setattr(bench, "kernel_source_digest", lambda fam, d=e["kernel_source_sha256"]: d)
+        assert bench.measured_traffic(key) == e["bytes_per_launch"]
+        # any other source text: nothing
+        monkeypatch.setattr(bench, "kernel_source_digest", lambda fam: "0" * 64)
+        assert bench.measured_traffic(key) is None
+        # the bytes are the scaled counters of the entry
+        assert e["bytes_per_launch"] == round((e["fetch_kib"] * e["fetch_scale"] +
+                                               e["write_kib"] * e["write_scale"]) * 1024)
+    assert bench.measured_traffic("no such kernel") is None
