@@ -218,7 +218,7 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
     if (e == hipSuccess)
         e = hipEventRecord(s.sim_stop, stream);
     if (e == hipSuccess && H.n_fins > 0)
-        e = hipGraphLaunch(s.exec[EPOCH_FINALIZE], stream);
+        e = hipGraphLaunch(s.exec[H.any_top ? EPOCH_FINALIZE : EPOCH_FINALIZE_FIXED], stream);
     if (e == hipSuccess)
         e = hipGraphLaunch(s.exec[EPOCH_STAGE_OUT], stream);
     if (e != hipSuccess)

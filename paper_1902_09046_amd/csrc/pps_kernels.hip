@@ -1289,15 +1289,20 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_sel_hist(const EpochHeader *__res
             h[i] = 0;
         __syncthreads();
         const uint64_t base = (b - F->block_begin) * static_cast<uint64_t>(FIN_TILE);
-        const uint32_t *d = reinterpret_cast<const uint32_t *>(F->dist);
-#pragma unroll 4
+        const uint32_t *__restrict__ d = reinterpret_cast<const uint32_t *>(F->dist);
+        const uint64_t n = F->n;
+        // all rows' loads in flight before the first histogram update
+        uint32_t dv[FIN_ROWS];
+#pragma unroll
         for (int r = 0; r < FIN_ROWS; ++r) {
             const uint64_t e = base + static_cast<uint64_t>(r) * FIN_BLOCK + threadIdx.x;
-            if (e < F->n) {
-                const uint32_t v = d[e];
-                if ((v & pmask) == prefix)
-                    atomicAdd(&h[(v >> shift) & dmask], 1u);
-            }
+            dv[r] = e < n ? d[e] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < FIN_ROWS; ++r) {
+            const uint64_t e = base + static_cast<uint64_t>(r) * FIN_BLOCK + threadIdx.x;
+            if (e < n && (dv[r] & pmask) == prefix)
+                atomicAdd(&h[(dv[r] >> shift) & dmask], 1u);
         }
         __syncthreads();
         for (int i = threadIdx.x; i <= static_cast<int>(dmask); i += FIN_BLOCK)
@@ -1361,21 +1366,30 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_sel_pick(const EpochHeader *__res
     }
 }
 
-__device__ __forceinline__ void fin_pred(const FinJob *F, uint32_t thresh, uint64_t e, bool &lt,
-                                         bool &eq, float &d)
+// A wave's FIN_ROWS distances (rows of 64 from wbase), loaded before any of
+// them is used so that the loads are in flight together; past n reads 0.
+__device__ __forceinline__ void fin_rows(const float *__restrict__ dist, uint64_t n, uint64_t wbase,
+                                         float (&dv)[FIN_ROWS])
 {
-    lt = false;
-    eq = false;
-    d = 0.0f;
-    if (e >= F->n)
-        return;
-    d = F->dist[e];
-    if (F->mode == PPS_EPS_FIXED) {
-        lt = static_cast<double>(d) <= F->eps;
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int r = 0; r < FIN_ROWS; ++r) {
+        const uint64_t e = wbase + static_cast<uint64_t>(r) * 64 + lane;
+        dv[r] = e < n ? dist[e] : 0.0f;
+    }
+}
+
+// fin_pred on a loaded distance (valid: the element is below n).
+__device__ __forceinline__ void fin_pred_d(int mode, double eps, uint32_t thresh, bool valid, float d,
+                                           bool &lt, bool &eq)
+{
+    if (mode == PPS_EPS_FIXED) {
+        lt = valid && static_cast<double>(d) <= eps;
+        eq = false;
     } else {
         const uint32_t v = __float_as_uint(d);
-        lt = v < thresh;
-        eq = v == thresh;
+        lt = valid && v < thresh;
+        eq = valid && v == thresh;
     }
 }
 
@@ -1391,13 +1405,17 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_count(const EpochHeader *
         const FinJob *F = fins + fin_locate(fins, n_fins, b);
         const uint64_t lb = b - F->block_begin;
         const uint32_t thresh = F->result->thresh_bits;
+        const uint64_t n = F->n;
+        const int mode = F->mode;
+        const double eps = F->eps;
         const uint64_t wbase = lb * FIN_TILE + static_cast<uint64_t>(wave) * (FIN_ROWS * 64);
+        float dv[FIN_ROWS];
+        fin_rows(F->dist, n, wbase, dv);
         unsigned clt = 0, ceq = 0;
-#pragma unroll 4
+#pragma unroll
         for (int r = 0; r < FIN_ROWS; ++r) {
             bool lt, eq;
-            float d;
-            fin_pred(F, thresh, wbase + r * 64 + lane_id(), lt, eq, d);
+            fin_pred_d(mode, eps, thresh, wbase + r * 64 + lane_id() < n, dv[r], lt, eq);
             clt += __popcll(__ballot(lt));
             ceq += __popcll(__ballot(eq));
         }
@@ -1510,6 +1528,9 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *
     constexpr int NW = FIN_BLOCK / 64;
     __shared__ unsigned s_lt[NW], s_eq[NW];
     __shared__ Moments s_mom[NW];
+    // each wave's distances for the second pass (each lane reads back only
+    // what it wrote, so no barrier is needed)
+    __shared__ float s_dv[NW][FIN_ROWS][64];
     const int n_fins = static_cast<int>(hdr->n_fins);
     const uint64_t total = hdr->fin_blocks;
     const int wave = threadIdx.x >> 6;
@@ -1523,14 +1544,26 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *
         const uint64_t quota = F->mode == PPS_EPS_FIXED ? 0 : R->quota;
         const uint64_t wbase = lb * FIN_TILE + static_cast<uint64_t>(wave) * (FIN_ROWS * 64);
         const int np = F->n_params;
+        // the job's fields in registers (the record stores below could
+        // otherwise alias them and force reloads)
+        const uint64_t n = F->n;
+        const int mode = F->mode;
+        const double eps = F->eps;
+        const uint64_t first = F->first_draw, capacity = F->capacity;
+        uint64_t *__restrict__ acc_idx = F->acc_idx;
+        float *__restrict__ acc_dist = F->acc_dist;
+        float *__restrict__ acc_theta = F->acc_theta;
+        float dv[FIN_ROWS];
+        fin_rows(F->dist, n, wbase, dv);
         // pass 1: this wave's totals, for the prefix over the block's waves
         unsigned clt = 0, ceq = 0;
+#pragma unroll
         for (int r = 0; r < FIN_ROWS; ++r) {
             bool lt, eq;
-            float d;
-            fin_pred(F, thresh, wbase + r * 64 + lane, lt, eq, d);
+            fin_pred_d(mode, eps, thresh, wbase + r * 64 + lane < n, dv[r], lt, eq);
             clt += __popcll(__ballot(lt));
             ceq += __popcll(__ballot(eq));
+            s_dv[wave][r][lane] = dv[r];
         }
         if (lane == 0) {
             s_lt[wave] = clt;
@@ -1555,8 +1588,8 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *
         for (int r = 0; r < FIN_ROWS; ++r) {
             const uint64_t e = wbase + r * 64 + lane;
             bool lt, eq;
-            float d;
-            fin_pred(F, thresh, e, lt, eq, d);
+            const float d = s_dv[wave][r][lane];
+            fin_pred_d(mode, eps, thresh, e < n, d, lt, eq);
             const uint64_t mlt = __ballot(lt);
             const uint64_t meq = __ballot(eq);
             if (mlt | meq) {
@@ -1566,14 +1599,14 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *
                 if (acc) {
                     const uint64_t pos = my_lt + (my_eq < quota ? my_eq : quota);
                     double theta[PPS_MAX_PARAMS];
-                    prior_draw<PPS_MAX_PARAMS>(F->prior, np, F->constraint, key, F->first_draw + e, theta);
-                    if (pos < F->capacity) {
-                        F->acc_idx[pos] = F->first_draw + e;
-                        F->acc_dist[pos] = d;
+                    prior_draw<PPS_MAX_PARAMS>(F->prior, np, F->constraint, key, first + e, theta);
+                    if (pos < capacity) {
+                        acc_idx[pos] = first + e;
+                        acc_dist[pos] = d;
 #pragma unroll
                         for (int j = 0; j < PPS_MAX_PARAMS; ++j)
                             if (j < np)
-                                F->acc_theta[static_cast<uint64_t>(j) * F->capacity + pos] =
+                                acc_theta[static_cast<uint64_t>(j) * capacity + pos] =
                                     static_cast<float>(theta[j]);
                     }
                     // Welford update in index order
@@ -1766,12 +1799,15 @@ hipError_t issue_epoch_part(int part, const EpochDevPtrs &p, const EpochShape &s
                            p.d_fins, p.h_out_fin, p.h_out_counts);
         return hipGetLastError();
     }
+    if (part != EPOCH_FINALIZE && part != EPOCH_FINALIZE_FIXED)
+        return hipErrorInvalidValue;
     const dim3 fb(FIN_BLOCK);
     hipLaunchKernelGGL(k_fin_init, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
-    for (int pass = 0; pass < 3; ++pass) {
-        hipLaunchKernelGGL(k_sel_hist, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins, pass);
-        hipLaunchKernelGGL(k_sel_pick, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins, pass);
-    }
+    if (part == EPOCH_FINALIZE)
+        for (int pass = 0; pass < 3; ++pass) {
+            hipLaunchKernelGGL(k_sel_hist, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins, pass);
+            hipLaunchKernelGGL(k_sel_pick, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins, pass);
+        }
     hipLaunchKernelGGL(k_compact_count, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins);
     hipLaunchKernelGGL(k_compact_scan, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
     hipLaunchKernelGGL(k_compact_write, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins);

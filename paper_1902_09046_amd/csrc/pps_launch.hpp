@@ -57,14 +57,17 @@ hipError_t sim_occupancy(int cls, const SimShape &sh, int *blocks_per_cu);
 
 // An epoch is issued as parts, in order, on one stream: stage-in; the
 // simulation kernel of each class that has tiles; the ABC finalisation kernels
-// (when the epoch finishes ABC jobs); stage-out.  Every launch shape is fixed
-// by `shape`, so each part is captured once into a graph and replayed with new
-// table contents; timing events bracket the simulation parts.
+// (when the epoch finishes ABC jobs: EPOCH_FINALIZE with the tolerance
+// selection passes when one of them takes the closest fraction,
+// EPOCH_FINALIZE_FIXED without them otherwise); stage-out.  Every launch shape
+// is fixed by `shape`, so each part is captured once into a graph and replayed
+// with new table contents; timing events bracket the simulation parts.
 enum {
     EPOCH_STAGE_IN = 0,
     EPOCH_SIMULATE = 1,  // + class
     EPOCH_FINALIZE = EPOCH_SIMULATE + N_CLASSES,
     EPOCH_STAGE_OUT,
+    EPOCH_FINALIZE_FIXED,
     EPOCH_PARTS
 };
 hipError_t issue_epoch_part(int part, const EpochDevPtrs &p, const EpochShape &shape, hipStream_t s);
