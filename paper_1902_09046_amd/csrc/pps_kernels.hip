@@ -1507,16 +1507,12 @@ __device__ __forceinline__ void moments_merge(Moments &a, const Moments &b, int 
     a.n = n;
 }
 
-__device__ __forceinline__ Moments moments_shfl_down(const Moments &m, int off)
+__device__ __forceinline__ double moments_readlane(double v, int l)
 {
-    Moments r;
-    r.n = __shfl_down(m.n, off);
-#pragma unroll
-    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-        r.mean[j] = __shfl_down(m.mean[j], off);
-        r.m2[j] = __shfl_down(m.m2[j], off);
-    }
-    return r;
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(b), l);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(b >> 32), l);
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
 
 constexpr int PARTIAL_STRIDE = 1 + 2 * PPS_MAX_PARAMS;
@@ -1625,14 +1621,28 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *
                 eq_before += __popcll(meq);
             }
         }
-        // lanes -> wave (fixed tree order), waves -> block
-        for (int off = 1; off < 64; off <<= 1) {
-            const Moments other = moments_shfl_down(mom, off);
-            if ((lane & (2 * off - 1)) == 0)
-                moments_merge(mom, other, np);
+        // lanes -> wave: the lanes holding accepted draws (usually none or
+        // one: acceptance is rare), merged in lane order; waves -> block
+        Moments wm;
+        wm.n = 0.0;
+#pragma unroll
+        for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+            wm.mean[j] = 0.0;
+            wm.m2[j] = 0.0;
+        }
+        for (unsigned long long has = __ballot(mom.n > 0.0); has != 0; has &= has - 1) {
+            const int l = __builtin_ctzll(has);
+            Moments o;
+            o.n = moments_readlane(mom.n, l);
+#pragma unroll
+            for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+                o.mean[j] = moments_readlane(mom.mean[j], l);
+                o.m2[j] = moments_readlane(mom.m2[j], l);
+            }
+            moments_merge(wm, o, np);
         }
         if (lane == 0)
-            s_mom[wave] = mom;
+            s_mom[wave] = wm;
         __syncthreads();
         if (threadIdx.x == 0) {
             Moments acc = s_mom[0];
