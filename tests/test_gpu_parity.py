@@ -46,6 +46,14 @@ def test_philox_bit_exact(P, torch):
         np.testing.assert_array_equal(got, ref)
 
 
+def test_philox_known_answers(P, torch):
+    from test_oracle_rng import PHILOX_KAT
+    for ctr, key, expect in PHILOX_KAT:
+        out = torch.empty(4, dtype=torch.int32, device="cuda")
+        P.pps_philox(key[0] | (key[1] << 32), ctr[2] | (ctr[3] << 32), 1, ctr[0], ctr[1], out)
+        assert out.cpu().numpy().view(np.uint32).tolist() == list(expect)
+
+
 def test_path_normals_fp32_vs_fp64(P, torch):
     seed, first, n, m = 3, 2**32 - 37, 1500, 22  # draw indices cross the 2^32 boundary
     out = torch.empty((m, n), dtype=torch.float32, device="cuda")

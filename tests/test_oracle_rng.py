@@ -1,7 +1,9 @@
 """Pins of the oracle's random streams (CPU only).
 
 * Philox4x32-10 against rocRAND's implementation of the same generator
-  (Salmon et al., SC'11), compiled here for the host from its header;
+  (Salmon et al., SC'11), compiled here for the host from its header, and
+  against the known-answer vectors published with the generator's reference
+  implementation (Random123) for 10 rounds;
 * the uniform lattice (exact values);
 * Box-Muller: the polar identities fix which word is the radius and which the
   angle; the normals are N(0,1) by a KS test.
@@ -129,3 +131,26 @@ def test_path_normal_block_layout():
         a0, a1 = oracle.box_muller(int(w[0]), int(w[1]))
         a2, a3 = oracle.box_muller(int(w[2]), int(w[3]))
         assert z == [a0, a1, a2, a3]
+
+
+# Known-answer vectors of Philox4x32 with 10 rounds (counter, key, output),
+# as published with the generator's reference implementation (Random123).
+PHILOX_KAT = [
+    ((0x00000000, 0x00000000, 0x00000000, 0x00000000), (0x00000000, 0x00000000),
+     (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+    ((0xffffffff, 0xffffffff, 0xffffffff, 0xffffffff), (0xffffffff, 0xffffffff),
+     (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+    ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+]
+
+
+@pytest.mark.parametrize("ctr,key,expect", PHILOX_KAT)
+def test_philox_known_answers(ctr, key, expect):
+    assert [int(v) for v in oracle.philox(ctr, key)] == list(expect)
+    # the same block through the stream layout: counter (block, purpose,
+    # lo32 draw, hi32 draw), key (lo32 seed, hi32 seed)
+    seed = key[0] | (key[1] << 32)
+    draw = ctr[2] | (ctr[3] << 32)
+    assert [int(v) for v in oracle.stream_block(seed, draw, ctr[0], ctr[1])] == list(expect)
+
