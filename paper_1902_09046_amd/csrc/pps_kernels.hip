@@ -833,7 +833,7 @@ struct TbHit {
     int fld;   // the row's field in that lane
     int row;   // 4 grp + fld
     int col;   // slot within the row
-    int leaf;  // the slot's count before the event
+    bool one;  // the slot held exactly one case before the event
     int pre;   // this lane's prefix in the row
 };
 
@@ -859,11 +859,12 @@ __device__ __forceinline__ TbHit tb_find(const uint16_t *pre, const TbRegs &c, u
     h.row = 4 * h.grp + h.fld;
     h.pre = pre[64 * h.row + lane];
     h.col = tb_first(__ballot(h.pre > r - before));
-    // the slot's count: its prefix minus the one before it (two lane reads
-    // of the row itself; a lane read of a DPP result issued right after the
-    // DPP instruction was seen to return stale values on gfx950)
+    // whether the slot held one case: its prefix minus the one before it, two
+    // lane reads of the row itself (the difference formed by a DPP subtract
+    // that shifts the row by one lane, wave_shr:1, into its own register gave
+    // wrong counts on gfx950, read either by v_readlane or by a compare)
     const int below = __builtin_amdgcn_readlane(h.pre, (h.col + 63) & 63);
-    h.leaf = __builtin_amdgcn_readlane(h.pre, h.col) - (h.col > 0 ? below : 0);
+    h.one = __builtin_amdgcn_readlane(h.pre, h.col) - (h.col > 0 ? below : 0) == 1;
     return h;
 }
 
@@ -983,13 +984,14 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         __syncthreads();
         // one event with words (wc, wt); false once the run has ended
         uint32_t e = 0;
-        auto event = [&](uint32_t wc, uint32_t wt) {
+        // one event: case word wc; birth, and type word below the death
+        // threshold (birth implies it; neither is a mutation)
+        auto event = [&](uint32_t wc, bool birth, bool below_td) {
             const uint32_t m = __umulhi(wc, N);
             const TbHit h = tb_find(s_pre, c, m);
-            const bool birth = b_all || wt < tb32;
-            const bool death = !birth && (d_all || wt < td32);
+            const bool death = !birth && below_td;
             const int d = birth ? 1 : -1;
-            const int o = (!birth && h.leaf == 1) ? -1 : 0;
+            const int o = (!birth && h.one) ? -1 : 0;
             tb_add(s_pre, c, h.grp, h.fld, h.row, h.col, h.pre, d, o);
             N = birth ? N + 1 : (death ? N - 1 : N);
             if (!birth && !death) {
@@ -1007,11 +1009,17 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
             // events e .. e + 127: block e/2 + j in lane j (e is even here)
             const Words4 wv = stream_block(key, draw, (e >> 1) + static_cast<uint32_t>(lane),
                                            PURPOSE_TB_EVENT);
+            // the types of all 128 events at once: lane j's type words are
+            // those of events e + 2j (word y) and e + 2j + 1 (word w)
+            const unsigned long long birth_y = __ballot(b_all || wv.y < tb32);
+            const unsigned long long below_y = __ballot(d_all || wv.y < td32);
+            const unsigned long long birth_w = __ballot(b_all || wv.w < tb32);
+            const unsigned long long below_w = __ballot(d_all || wv.w < td32);
             for (int j = 0; j < 64; ++j) {
-                event(__builtin_amdgcn_readlane(wv.x, j), __builtin_amdgcn_readlane(wv.y, j));
+                event(__builtin_amdgcn_readlane(wv.x, j), (birth_y >> j) & 1ull, (below_y >> j) & 1ull);
                 if (!running())
                     break;
-                event(__builtin_amdgcn_readlane(wv.z, j), __builtin_amdgcn_readlane(wv.w, j));
+                event(__builtin_amdgcn_readlane(wv.z, j), (birth_w >> j) & 1ull, (below_w >> j) & 1ull);
                 if (!running())
                     break;
             }
