@@ -265,7 +265,8 @@ enum pps_job_kind { PPS_JOB_ABC = 0, PPS_JOB_PVALUE = 1 };
 
 typedef struct {
     int32_t kind;           /* enum pps_job_kind */
-    pps_model model;        /* logistic SDE or normal-mean */
+    pps_model model;        /* ABC: any model; p-value: logistic SDE or
+                               normal-mean (others: PPS_EINVAL) */
     pps_sampling sampling;
     /* ABC */
     double y_obs[PPS_MAX_OBS]; /* observed summaries (n_summaries values) */

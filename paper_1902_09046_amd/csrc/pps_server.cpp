@@ -97,7 +97,8 @@ struct Job {
     JobDev row;             // template of the job's rows (whole-job fields)
     FinJob fin;             // ABC finalisation
     uint64_t n_tiles = 0, next_tile = 0;
-    uint64_t cost_per_tile = 0;  // draw-steps
+    int cls = CLASS_PATH;        // simulation kernel class of the job's rows
+    uint64_t cost_per_tile = 0;  // in logistic-step units (draw_cost)
     pps_job_result result;
 };
 
@@ -133,13 +134,13 @@ static int validate_job(const pps_job *j, int *n_summ)
         return rc;
     if ((rc = validate_sampling(&j->sampling)) != PPS_OK)
         return rc;
-    if (j->model.model != PPS_LOGISTIC_SDE && j->model.model != PPS_NORMAL_MEAN)
-        return fail(PPS_EINVAL, "jobs run the logistic SDE or normal-mean models");
     if (j->kind == PPS_JOB_ABC)
         return validate_abc(&j->model, j->y_obs, *n_summ, &j->sampling, j->eps_mode,
                             j->eps_or_frac);
     if (j->kind != PPS_JOB_PVALUE)
         return fail(PPS_EINVAL, "unknown job kind %d", j->kind);
+    if (j->model.model != PPS_LOGISTIC_SDE && j->model.model != PPS_NORMAL_MEAN)
+        return fail(PPS_EINVAL, "p-value jobs run the logistic SDE or normal-mean models");
     if (j->lambda_param < 0 || j->lambda_param >= j->model.n_params)
         return fail(PPS_EINVAL, "lambda_param %d out of range", j->lambda_param);
     pps_model m = j->model;
@@ -238,7 +239,7 @@ class Scheduler {
         std::vector<Job *> finishing;
         std::vector<int> fin_index;     // ABC: index in the slot's results
         std::vector<uint32_t> count_at; // p-value: index in the slot's counts
-        uint64_t draw_steps;
+        uint64_t cost;  // logistic-step units planned
     };
 
     bool can_launch() const
@@ -323,10 +324,32 @@ class Scheduler {
             row.counts = reinterpret_cast<unsigned long long *>(base);
             row.n_counts = 1;
         }
-        j->n_tiles = eng_->tiles_for(CLASS_PATH, s.sampling.n_draws);
+        j->cls = s.kind == PPS_JOB_ABC ? model_class(&s.model) : CLASS_PATH;
+        j->n_tiles = eng_->tiles_for(j->cls, s.sampling.n_draws);
         j->next_tile = 0;
+        j->cost_per_tile = eng_->tile_size(j->cls) * draw_cost(j->cls, row);
+    }
+
+    // Cost of one draw in units of one logistic-SDE Euler step of the whole
+    // machine, from the classes' measured throughputs: a GARCH step costs
+    // about 2.5, a toggle-switch cell-step 3.3, a tuberculosis event 2700 (its
+    // run is one serial chain per workgroup), and a tuberculosis run takes
+    // about 1.5 n_stop events.  The epoch budget and the measured rate are in
+    // these units, so epochs of any mix of classes take about epoch_ms.
+    static uint64_t draw_cost(int cls, const JobDev &row)
+    {
         const uint64_t steps = static_cast<uint64_t>(row.steps > 0 ? row.steps : 1);
-        j->cost_per_tile = eng_->tile_size(CLASS_PATH) * steps;
+        const uint64_t cells = static_cast<uint64_t>(row.n_cells > 0 ? row.n_cells : 1);
+        switch (cls) {
+        case CLASS_GARCH:
+            return (steps * 5 + 1) / 2;
+        case CLASS_CELLS:
+            return (cells * steps * 10 + 2) / 3;
+        case CLASS_GILLESPIE:
+            return cells * 4050;
+        default:
+            return steps;
+        }
     }
 
     int plan_and_launch(bool *launched)
@@ -336,7 +359,7 @@ class Scheduler {
             return PPS_OK;
         EpochPlan plan;
         InFlight fl;
-        fl.draw_steps = 0;
+        fl.cost = 0;
         double budget = cfg_.epoch_ms * 1e-3 * rate_;
         std::vector<std::pair<uint64_t, size_t>> order;  // (cost per tile, row index)
         std::vector<JobDev> rows;
@@ -362,7 +385,7 @@ class Scheduler {
             }
             j->next_tile += take;
             budget -= static_cast<double>(take * j->cost_per_tile);
-            fl.draw_steps += take * j->cost_per_tile;
+            fl.cost += take * j->cost_per_tile;
             order.push_back({j->cost_per_tile, rows.size()});
             rows.push_back(r);
             row_job.push_back(j);
@@ -386,9 +409,13 @@ class Scheduler {
         std::stable_sort(order.begin(), order.end(),
                          [](const auto &a, const auto &b) { return a.first > b.first; });
         std::vector<Job *> ordered_job;
+        // (rows keep this order within each class; p-value rows are all in
+        // the path class, and ordered_job lists that class's jobs)
         for (const auto &o : order) {
-            plan.rows[CLASS_PATH].push_back(rows[o.second]);
-            ordered_job.push_back(row_job[o.second]);
+            const int cls = row_job[o.second]->cls;
+            plan.rows[cls].push_back(rows[o.second]);
+            if (cls == CLASS_PATH)
+                ordered_job.push_back(row_job[o.second]);
         }
         const int slot = free_slot();
         int rc = eng_->launch(slot, plan, stream_);
@@ -443,8 +470,8 @@ class Scheduler {
             const float ms = eng_->sim_ms(f.slot);
             if (ms > 0.0f) {
                 busy_s_ += ms * 1e-3;
-                const double r = static_cast<double>(f.draw_steps) / (ms * 1e-3);
-                if (f.draw_steps > 0 && r > 0.0)
+                const double r = static_cast<double>(f.cost) / (ms * 1e-3);
+                if (f.cost > 0 && r > 0.0)
                     rate_ = 0.8 * rate_ + 0.2 * r;
             }
             const FinResult *fins = eng_->out_fin(f.slot);
@@ -495,7 +522,7 @@ class Scheduler {
     uint64_t completed_ = 0;
     std::vector<double> latencies_;
     double busy_s_ = 0.0;
-    double rate_ = 1.5e12;  // draw-steps per second (updated from measurements)
+    double rate_ = 1.5e12;  // logistic-step units per second (updated from measurements)
 };
 
 static int validate_config(const pps_server_config *c)

@@ -132,6 +132,109 @@ def test_server_mix_equals_alone(P, torch, arena):
             srv.poll(ids[0])
 
 
+def every_model_jobs(P):
+    """Closest-fraction and fixed-eps ABC jobs of the toggle-switch and
+    tuberculosis models, with logistic ABC and p-value jobs between them:
+    (job, (spec, y_obs, sampling, mode, eps_or_frac, capacity)) pairs."""
+    g = observed()
+    models = [
+        (W.toggle_spec(n_cells=400, steps=100), g["toggle_C8000_T600"]["y_obs"], 300),
+        (W.tb_spec(n_stop=300, n_sample=100, max_events=20000), g["tb_K10000_n473"]["y_obs"], 700),
+    ]
+    out = []
+    for k, (spec, y, n) in enumerate(models):
+        s = P.make_sampling(n, 1000 * k, 40 + k)
+        out.append((P.make_abc_job(spec, y, s, P.PPS_EPS_TOP_FRACTION, 0.05),
+                    (spec, y, s, P.PPS_EPS_TOP_FRACTION, 0.05, None)))
+        # a tolerance that keeps about a third of the job's draws
+        s2 = P.make_sampling(n // 2, 77, 50 + k)
+        eps = P.abc(spec, y, s2.seed, s2.first_draw, s2.n_draws, P.PPS_EPS_TOP_FRACTION,
+                    0.3)["eps_used"]
+        out.append((P.make_abc_job(spec, y, s2, P.PPS_EPS_FIXED, eps, capacity=n),
+                    (spec, y, s2, P.PPS_EPS_FIXED, eps, n)))
+    jobs, meta = mixed_jobs(P, n_jobs=4, seed=13)
+    ob = observed()["logistic_S1000"]["y_obs"]
+    mixed = []
+    for j, m in zip(jobs, meta):
+        if m[0] == "pvalue":
+            mixed.append((j, m))
+        else:
+            mode = P.PPS_EPS_TOP_FRACTION if m[0] == "abc_top" else P.PPS_EPS_FIXED
+            mixed.append((j, (m[1], ob, m[2], mode, m[3], None if m[0] == "abc_top" else 4000)))
+    # interleaved: the scheduler sees the classes in no particular order
+    return out[:2] + mixed[:2] + out[2:] + mixed[2:]
+
+
+def every_model_alone(P, pairs):
+    ref = []
+    for _, m in pairs:
+        if m[0] == "pvalue":
+            ob = observed()["logistic_S1000"]
+            c, _ = P.prior_pred_pvalue(m[1], 0, P.PPS_LOGNORMAL, [m[3]], m[2], ob["t_obs"])
+            ref.append(({"count_ge": int(c[0])}, 0))
+            continue
+        spec, y, s, mode, arg, cap = m
+        ref.append((P.abc(spec, y, s.seed, s.first_draw, s.n_draws, mode, arg, capacity=cap),
+                    len(spec["priors"])))
+    return ref
+
+
+def assert_same_n(P, res, ref, n_params, arena):
+    if "count_ge" in ref:
+        assert res.status == P.PPS_OK and res.count_ge == ref["count_ge"]
+        return
+    assert res.status == P.PPS_OK
+    assert res.abc.n_accepted == ref["n_accepted"] > 0
+    assert res.abc.eps_used == ref["eps_used"]
+    np.testing.assert_array_equal(np.array(res.abc.mean[:n_params]), ref["mean"][:n_params])
+    np.testing.assert_array_equal(np.array(res.abc.var[:n_params]), ref["var"][:n_params])
+    idx, th, d = P.records(res, arena, n_params)
+    np.testing.assert_array_equal(idx, ref["idx"].cpu().numpy().astype(np.uint64))
+    np.testing.assert_array_equal(th, ref["theta"].cpu().numpy())
+    np.testing.assert_array_equal(d, ref["dist"].cpu().numpy())
+
+
+@pytest.mark.parametrize("policy", ["batched", "plain"])
+def test_every_model_batched_equals_alone(P, torch, arena, policy):
+    """Toggle-switch and tuberculosis ABC jobs in one batch with
+    logistic jobs: each job's records, tolerance and moments equal its
+    synchronous run (jobs split over epochs, classes mixed within one)."""
+    pairs = every_model_jobs(P)
+    ref = every_model_alone(P, pairs)
+    pol = P.PPS_POLICY_BATCHED if policy == "batched" else P.PPS_POLICY_PLAIN
+    res = P.pps_run_batch([j for j, _ in pairs], P.make_server_config(arena, epoch_ms=0.5, policy=pol))
+    for r, (f, n_params) in zip(res, ref):
+        assert_same_n(P, r, f, n_params, arena)
+
+
+def test_every_model_served_equals_alone(P, torch, arena):
+    pairs = every_model_jobs(P)
+    ref = every_model_alone(P, pairs)
+    with P.Server(P.make_server_config(arena, epoch_ms=1.0)) as srv:
+        ids = [srv.submit(j) for j, _ in pairs]
+        deadline = time.time() + 60
+        done = {}
+        while len(done) < len(ids) and time.time() < deadline:
+            for i, jid in enumerate(ids):
+                if i not in done:
+                    rc, r = srv.poll(jid)
+                    if rc != P.PPS_PENDING:
+                        done[i] = r
+            time.sleep(0.001)
+        assert len(done) == len(ids)
+        for i, (f, n_params) in enumerate(ref):
+            assert_same_n(P, done[i], f, n_params, arena)
+            assert srv.release(ids[i]) == P.PPS_OK
+        # p-value jobs stay with the logistic SDE and normal-mean models, and
+        # GARCH has tallies, not ABC
+        garch = W.garch_spec(series_len=100)
+        for bad in (P.make_pvalue_job(garch, 0, P.PPS_UNIFORM, 1e-4, P.make_sampling(100, 0, 1), 0.0),
+                    P.make_abc_job(garch, observed()["garch_L2000"]["summaries"],
+                                   P.make_sampling(100, 0, 1), P.PPS_EPS_TOP_FRACTION, 0.1)):
+            with pytest.raises(P.PPSError):
+                srv.submit(bad)
+
+
 def test_server_small_arena_admission(P, torch):
     """An arena that holds about one ABC job: jobs wait for memory, run as
     releases free it, and still equal their results alone."""
