@@ -317,7 +317,11 @@ typedef struct {
     double epoch_ms;        /* target GPU time of one epoch (planning budget) */
     int32_t policy;         /* enum pps_policy */
     void *stream;           /* HIP stream of the epochs; NULL: a stream of the
-                               server's own (default priority) */
+                               server's own (default priority).  Epochs alternate
+                               between it and a second stream of the library's
+                               (default priority); results are read through
+                               pps_poll / the returned results, never by
+                               ordering on this stream */
 } pps_server_config;
 
 /* Bytes of arena a job needs while admitted (ABC: distances, finalisation

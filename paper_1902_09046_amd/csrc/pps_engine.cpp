@@ -46,6 +46,8 @@ EpochEngine::~EpochEngine()
         for (hipEvent_t ev : {s.sim_start, s.sim_stop, s.done})
             if (ev)
                 (void)hipEventDestroy(ev);
+        if (s.own_stream)
+            (void)hipStreamDestroy(s.own_stream);
     }
     if (capture_stream_)
         (void)hipStreamDestroy(capture_stream_);
@@ -103,6 +105,9 @@ int EpochEngine::init(int n_slots, int cu_count)
             (e = hipEventCreate(&s.sim_start)) != hipSuccess ||
             (e = hipEventCreate(&s.sim_stop)) != hipSuccess)
             return fail_hip(e, "epoch events");
+        if (&s != &slots_[0] &&
+            (e = hipStreamCreateWithFlags(&s.own_stream, hipStreamNonBlocking)) != hipSuccess)
+            return fail_hip(e, "epoch stream");
     }
     return PPS_OK;
 }
@@ -209,7 +214,11 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
     }
     H.n_fins = static_cast<uint32_t>(plan.fins.size());
     H.fin_blocks = fb;
-    hipError_t e = hipGraphLaunch(s.exec[EPOCH_STAGE_IN], stream);
+    hipError_t e = hipSuccess;
+    if (last_slot_ >= 0 && last_stream_ != stream)
+        e = hipStreamWaitEvent(stream, slots_[last_slot_].sim_stop, 0);
+    if (e == hipSuccess)
+        e = hipGraphLaunch(s.exec[EPOCH_STAGE_IN], stream);
     if (e == hipSuccess)
         e = hipEventRecord(s.sim_start, stream);
     for (int c = 0; c < N_CLASSES && e == hipSuccess; ++c)
@@ -227,6 +236,8 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
     if (e != hipSuccess)
         return fail_hip(e, "epoch event");
     s.in_flight = true;
+    last_slot_ = slot;
+    last_stream_ = stream;
     return PPS_OK;
 }
 

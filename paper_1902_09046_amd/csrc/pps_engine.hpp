@@ -55,8 +55,18 @@ class EpochEngine {
     }
 
     // Stages `plan` into `slot` and launches the epoch graph on `stream`.
-    // The slot must be idle (see wait / ready).
+    // The slot must be idle (see wait / ready).  When the previous epoch was
+    // launched on another stream, this one starts after that epoch's
+    // simulation kernels have ended (a job's tiles can span both epochs and
+    // its finalisation reads all of them); its finalisation and stage-out
+    // still overlap this epoch.
     int launch(int slot, EpochPlan &plan, hipStream_t stream);
+    // The stream of a slot: `primary` for slot 0, a stream of the engine for
+    // the others (so that epochs alternate between two streams).
+    hipStream_t slot_stream(int slot, hipStream_t primary) const
+    {
+        return slot == 0 ? primary : slots_[slot].own_stream;
+    }
     // Blocks until the slot's epoch has finished.
     int wait(int slot);
     // Non-blocking: PPS_OK when the slot has no epoch in flight (the last one
@@ -82,6 +92,7 @@ class EpochEngine {
         bool have_exec = false;
         EpochShape exec_shape;
         hipEvent_t sim_start = nullptr, sim_stop = nullptr, done = nullptr;
+        hipStream_t own_stream = nullptr;  // slots after the first
         bool in_flight = false;
         float sim_ms = -1.0f;
     };
@@ -92,6 +103,8 @@ class EpochEngine {
     EpochShape shape_;
     int cu_count_ = 0;
     hipStream_t capture_stream_ = nullptr;
+    int last_slot_ = -1;  // slot and stream of the last launched epoch
+    hipStream_t last_stream_ = nullptr;
 };
 
 }  // namespace pps

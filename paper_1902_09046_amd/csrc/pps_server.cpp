@@ -2,9 +2,10 @@
 //
 // Jobs of different kind, size, step count and lambda are admitted in FIFO
 // order while arena memory and active slots allow, then their tiles are packed
-// into epochs of a target GPU time.  Up to two epochs are in flight on one
-// stream: while the GPU runs epoch e the host plans e + 1 and admits new
-// arrivals, so requests that arrive while others run join the next epoch.  A
+// into epochs of a target GPU time.  Up to two epochs are in flight, on two
+// streams: while the GPU runs epoch e the host plans e + 1 and admits new
+// arrivals, so requests that arrive while others run join the next epoch, and
+// e + 1's simulation starts as soon as e's ends, beside e's finalisation.  A
 // job's finalisation (ABC select / compaction / moments, or the copy-out of a
 // p-value tally) rides in the epoch that holds its last tile.
 #include <algorithm>
@@ -418,7 +419,7 @@ class Scheduler {
                 ordered_job.push_back(row_job[o.second]);
         }
         const int slot = free_slot();
-        int rc = eng_->launch(slot, plan, stream_);
+        int rc = eng_->launch(slot, plan, eng_->slot_stream(slot, stream_));
         if (rc != PPS_OK)
             return rc;
         // Where each finishing p-value job's tally lands in the slot's counts.
@@ -452,8 +453,8 @@ class Scheduler {
         return 0;
     }
 
-    // Harvests finished epochs in launch order (one stream, so they finish
-    // in order).  With `wait` it blocks for the oldest one.
+    // Harvests finished epochs in launch order.  With `wait` it blocks for
+    // the oldest one.
     int harvest(bool wait)
     {
         while (!inflight_.empty()) {
