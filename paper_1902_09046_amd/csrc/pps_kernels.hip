@@ -1446,6 +1446,9 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_count(const EpochHeader *
 }
 
 // One workgroup per job: exclusive scan of the per-block (lt, eq) counts.
+// Thread t owns the consecutive blocks [t c, (t + 1) c): it sums them (loads
+// independent of each other), the workgroup scans the 256 sums once, and the
+// thread rewrites its blocks as running offsets from its scanned start.
 __global__ __launch_bounds__(FIN_BLOCK) void k_compact_scan(const EpochHeader *__restrict__ hdr,
                                                              const FinJob *__restrict__ fins)
 {
@@ -1454,30 +1457,36 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_scan(const EpochHeader *_
         return;
     const FinJob *F = fins + blockIdx.x;
     FinResult *R = F->result;
-    unsigned long long carry_a = 0, carry_b = 0;
-    for (uint64_t c0 = 0; c0 < F->n_blocks; c0 += FIN_BLOCK) {
-        const uint64_t i = c0 + threadIdx.x;
-        const unsigned long long a = i < F->n_blocks ? F->block_counts[2 * i] : 0ull;
-        const unsigned long long b = i < F->n_blocks ? F->block_counts[2 * i + 1] : 0ull;
-        s_a[threadIdx.x] = a;
-        s_b[threadIdx.x] = b;
+    const uint64_t nb = F->n_blocks;
+    const uint64_t chunk = (nb + FIN_BLOCK - 1) / FIN_BLOCK;
+    const uint64_t b0 = threadIdx.x * chunk;
+    const uint64_t b1 = b0 + chunk < nb ? b0 + chunk : nb;
+    unsigned long long *__restrict__ bc = F->block_counts;
+    unsigned long long sa = 0, sb = 0;
+    for (uint64_t i = b0; i < b1; ++i) {
+        sa += bc[2 * i];
+        sb += bc[2 * i + 1];
+    }
+    s_a[threadIdx.x] = sa;
+    s_b[threadIdx.x] = sb;
+    __syncthreads();
+    for (int off = 1; off < FIN_BLOCK; off <<= 1) {
+        const unsigned long long va = threadIdx.x >= off ? s_a[threadIdx.x - off] : 0ull;
+        const unsigned long long vb = threadIdx.x >= off ? s_b[threadIdx.x - off] : 0ull;
         __syncthreads();
-        for (int off = 1; off < FIN_BLOCK; off <<= 1) {
-            const unsigned long long va = threadIdx.x >= off ? s_a[threadIdx.x - off] : 0ull;
-            const unsigned long long vb = threadIdx.x >= off ? s_b[threadIdx.x - off] : 0ull;
-            __syncthreads();
-            s_a[threadIdx.x] += va;
-            s_b[threadIdx.x] += vb;
-            __syncthreads();
-        }
-        if (i < F->n_blocks) {
-            F->block_counts[2 * i] = carry_a + s_a[threadIdx.x] - a;
-            F->block_counts[2 * i + 1] = carry_b + s_b[threadIdx.x] - b;
-        }
-        carry_a += s_a[FIN_BLOCK - 1];
-        carry_b += s_b[FIN_BLOCK - 1];
+        s_a[threadIdx.x] += va;
+        s_b[threadIdx.x] += vb;
         __syncthreads();
     }
+    unsigned long long ra = s_a[threadIdx.x] - sa, rb = s_b[threadIdx.x] - sb;
+    for (uint64_t i = b0; i < b1; ++i) {
+        const unsigned long long a = bc[2 * i], b = bc[2 * i + 1];
+        bc[2 * i] = ra;
+        bc[2 * i + 1] = rb;
+        ra += a;
+        rb += b;
+    }
+    const unsigned long long carry_a = s_a[FIN_BLOCK - 1], carry_b = s_b[FIN_BLOCK - 1];
     if (threadIdx.x == 0) {
         R->lt_total = carry_a;
         R->eq_total = carry_b;
@@ -1535,6 +1544,10 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *
     // each wave's distances for the second pass (each lane reads back only
     // what it wrote, so no barrier is needed)
     __shared__ float s_dv[NW][FIN_ROWS][64];
+    // per wave: accepted draws waiting for their records (tile offset and
+    // record position); at most 63 + 64 at once
+    __shared__ uint16_t s_qoff[NW][128];
+    __shared__ uint64_t s_qpos[NW][128];
     const int n_fins = static_cast<int>(hdr->n_fins);
     const uint64_t total = hdr->fin_blocks;
     const int wave = threadIdx.x >> 6;
@@ -1588,7 +1601,51 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *
             mom.m2[j] = 0.0;
         }
         const StreamKey key = make_key(F->seed);
-        // pass 2: ranks and writes
+        // Accepted draws of queue slots [0, k): lane l < k takes slot l,
+        // recomputes its theta from the stream, writes the record and adds
+        // it to its running moments (lane l sees slots l, 64 + l, ... of the
+        // wave's accepted draws: a fixed order).
+        auto flush = [&](int k) {
+            // the queue slots were written by other lanes of this wave: LDS
+            // operations of one wave complete in order, and this keeps the
+            // compiler from moving them
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (static_cast<int>(lane) < k) {
+                const uint32_t off = s_qoff[wave][lane];
+                const uint64_t pos = s_qpos[wave][lane];
+                const uint64_t e = wbase + off;
+                double theta[PPS_MAX_PARAMS];
+                prior_draw<PPS_MAX_PARAMS>(F->prior, np, F->constraint, key, first + e, theta);
+                if (pos < capacity) {
+                    acc_idx[pos] = first + e;
+                    acc_dist[pos] = s_dv[wave][off >> 6][off & 63];
+#pragma unroll
+                    for (int j = 0; j < PPS_MAX_PARAMS; ++j)
+                        if (j < np)
+                            acc_theta[static_cast<uint64_t>(j) * capacity + pos] =
+                                static_cast<float>(theta[j]);
+                }
+                // Welford update
+                mom.n += 1.0;
+                const double inv_n = 1.0 / mom.n;
+#pragma unroll
+                for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+                    if (j < np) {
+                        const double delta = theta[j] - mom.mean[j];
+                        mom.mean[j] += delta * inv_n;
+                        mom.m2[j] += delta * (theta[j] - mom.mean[j]);
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        };
+        // pass 2: ranks; accepted draws queue up in index order and are
+        // written 64 at a time, so that the prior recomputation (three Philox
+        // calls and FP64 work per draw) runs on whole waves rather than once
+        // per row for its one or two accepted lanes
+        int q = 0;  // queue length (wave-uniform, below 64 between rows)
         for (int r = 0; r < FIN_ROWS; ++r) {
             const uint64_t e = wbase + r * 64 + lane;
             bool lt, eq;
@@ -1600,35 +1657,36 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *
                 const uint64_t my_lt = lt_before + __popcll(mlt & below);
                 const uint64_t my_eq = eq_before + __popcll(meq & below);
                 const bool acc = lt || (eq && my_eq < quota);
+                const uint64_t macc = __ballot(acc);
                 if (acc) {
-                    const uint64_t pos = my_lt + (my_eq < quota ? my_eq : quota);
-                    double theta[PPS_MAX_PARAMS];
-                    prior_draw<PPS_MAX_PARAMS>(F->prior, np, F->constraint, key, first + e, theta);
-                    if (pos < capacity) {
-                        acc_idx[pos] = first + e;
-                        acc_dist[pos] = d;
-#pragma unroll
-                        for (int j = 0; j < PPS_MAX_PARAMS; ++j)
-                            if (j < np)
-                                acc_theta[static_cast<uint64_t>(j) * capacity + pos] =
-                                    static_cast<float>(theta[j]);
-                    }
-                    // Welford update in index order
-                    mom.n += 1.0;
-                    const double inv_n = 1.0 / mom.n;
-#pragma unroll
-                    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-                        if (j < np) {
-                            const double delta = theta[j] - mom.mean[j];
-                            mom.mean[j] += delta * inv_n;
-                            mom.m2[j] += delta * (theta[j] - mom.mean[j]);
-                        }
-                    }
+                    const int slot = q + __popcll(macc & below);
+                    s_qoff[wave][slot] = static_cast<uint16_t>(r * 64 + lane);
+                    s_qpos[wave][slot] = my_lt + (my_eq < quota ? my_eq : quota);
                 }
+                q += __popcll(macc);
                 lt_before += __popcll(mlt);
                 eq_before += __popcll(meq);
+                if (q >= 64) {
+                    flush(64);
+                    q -= 64;
+                    // the rest (fewer than 64) moves to the queue's front
+                    uint16_t off = 0;
+                    uint64_t pos = 0;
+                    if (static_cast<int>(lane) < q) {
+                        off = s_qoff[wave][64 + lane];
+                        pos = s_qpos[wave][64 + lane];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    if (static_cast<int>(lane) < q) {
+                        s_qoff[wave][lane] = off;
+                        s_qpos[wave][lane] = pos;
+                    }
+                }
             }
         }
+        if (q > 0)
+            flush(q);
         // lanes -> wave: the lanes holding accepted draws (usually none or
         // one: acceptance is rare), merged in lane order; waves -> block
         Moments wm;
