@@ -28,9 +28,12 @@ template <class T> static T *dev_view(T *host)
 
 EpochEngine::~EpochEngine()
 {
-    for (Slot &s : slots_) {
+    // every epoch ends before anything is freed (an epoch on one slot's
+    // stream may wait on another slot's event)
+    for (Slot &s : slots_)
         if (s.in_flight && s.done)
             (void)hipEventSynchronize(s.done);
+    for (Slot &s : slots_) {
         for (hipGraphExec_t &x : s.exec)
             if (x)
                 (void)hipGraphExecDestroy(x);
