@@ -34,9 +34,8 @@ EpochEngine::~EpochEngine()
         if (s.in_flight && s.done)
             (void)hipEventSynchronize(s.done);
     for (Slot &s : slots_) {
-        for (hipGraphExec_t &x : s.exec)
-            if (x)
-                (void)hipGraphExecDestroy(x);
+        for (auto &kv : s.execs)
+            (void)hipGraphExecDestroy(kv.second);
         for (void *h : {static_cast<void *>(s.h_hdr), static_cast<void *>(s.h_rows),
                         static_cast<void *>(s.h_fins), static_cast<void *>(s.h_out_fin),
                         static_cast<void *>(s.h_out_counts)})
@@ -115,7 +114,7 @@ int EpochEngine::init(int n_slots, int cu_count)
     return PPS_OK;
 }
 
-int EpochEngine::build_graph(Slot &s)
+int EpochEngine::set_graph_shape(Slot &s)
 {
     EpochShape want = shape_;
     for (int c = 0; c < N_CLASSES; ++c) {
@@ -128,37 +127,82 @@ int EpochEngine::build_graph(Slot &s)
         want.sim_grid[c] = static_cast<unsigned>(per_cu * cu_count_);
     }
     want.fin_grid = static_cast<unsigned>(8 * cu_count_);
-    if (s.have_exec && s.exec_shape == want)
+    if (s.have_shape && s.exec_shape == want)
         return PPS_OK;
-    for (hipGraphExec_t &x : s.exec) {
-        if (x)
-            (void)hipGraphExecDestroy(x);
-        x = nullptr;
-    }
-    s.have_exec = false;
-    for (int part = 0; part < EPOCH_PARTS; ++part) {
-        hipError_t e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess)
-            return fail_hip(e, "graph capture begin");
-        hipError_t ei = issue_epoch_part(part, s.dev, want, capture_stream_);
-        hipGraph_t graph = nullptr;
-        e = hipStreamEndCapture(capture_stream_, &graph);
-        if (ei != hipSuccess) {
-            if (graph)
-                (void)hipGraphDestroy(graph);
-            return fail_hip(ei, "epoch capture");
-        }
-        if (e != hipSuccess)
-            return fail_hip(e, "graph capture end");
-        e = hipGraphInstantiate(&s.exec[part], graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            s.exec[part] = nullptr;
-            return fail_hip(e, "graph instantiate");
-        }
-    }
+    for (auto &kv : s.execs)
+        (void)hipGraphExecDestroy(kv.second);
+    s.execs.clear();
     s.exec_shape = want;
-    s.have_exec = true;
+    s.have_shape = true;
+    return PPS_OK;
+}
+
+// Adds a record of `ev` after everything captured so far on `cs` and makes
+// the work captured next follow it.  (An event recorded on a capturing stream
+// is not turned into a graph node by this runtime, so the node is added
+// explicitly.)
+static hipError_t capture_event(hipStream_t cs, hipEvent_t ev)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t n_deps = 0;
+    hipError_t e = hipStreamGetCaptureInfo_v2(cs, &st, &id, &g, &deps, &n_deps);
+    if (e != hipSuccess)
+        return e;
+    if (st != hipStreamCaptureStatusActive || !g)
+        return hipErrorStreamCaptureInvalidated;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddEventRecordNode(&node, g, deps, n_deps, ev);
+    if (e != hipSuccess)
+        return e;
+    return hipStreamUpdateCaptureDependencies(cs, &node, 1, hipStreamSetCaptureDependencies);
+}
+
+// Form bits: bit c = class c has tiles; bits N_CLASSES.. = 0 no
+// finalisation, 1 with the selection passes, 2 fixed tolerances only.
+int EpochEngine::graph_for(Slot &s, unsigned form, hipGraphExec_t *out)
+{
+    auto it = s.execs.find(form);
+    if (it != s.execs.end()) {
+        *out = it->second;
+        return PPS_OK;
+    }
+    const EpochShape &sh = s.exec_shape;
+    hipError_t e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return fail_hip(e, "graph capture begin");
+    // stage-in, [sim_start], the simulation of each class with tiles,
+    // [sim_stop], the finalisation, stage-out
+    hipError_t ei = issue_epoch_part(EPOCH_STAGE_IN, s.dev, sh, capture_stream_);
+    if (ei == hipSuccess)
+        ei = capture_event(capture_stream_, s.sim_start);
+    for (int c = 0; c < N_CLASSES && ei == hipSuccess; ++c)
+        if (form & (1u << c))
+            ei = issue_epoch_part(EPOCH_SIMULATE + c, s.dev, sh, capture_stream_);
+    if (ei == hipSuccess)
+        ei = capture_event(capture_stream_, s.sim_stop);
+    const unsigned fin = form >> N_CLASSES;
+    if (ei == hipSuccess && fin != 0)
+        ei = issue_epoch_part(fin == 1 ? EPOCH_FINALIZE : EPOCH_FINALIZE_FIXED, s.dev, sh,
+                              capture_stream_);
+    if (ei == hipSuccess)
+        ei = issue_epoch_part(EPOCH_STAGE_OUT, s.dev, sh, capture_stream_);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(capture_stream_, &graph);
+    if (ei != hipSuccess || e != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return fail_hip(ei != hipSuccess ? ei : e, "epoch capture");
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+        return fail_hip(e, "graph instantiate");
+    s.execs[form] = x;
+    *out = x;
     return PPS_OK;
 }
 
@@ -173,7 +217,7 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
     if (n_rows > static_cast<size_t>(MAX_ROWS) || plan.fins.size() > static_cast<size_t>(MAX_FINS))
         return fail(PPS_EINVAL, "epoch too large: %zu rows, %zu finalisations", n_rows,
                     plan.fins.size());
-    int rc = build_graph(s);
+    int rc = set_graph_shape(s);
     if (rc != PPS_OK)
         return rc;
     EpochHeader &H = *s.h_hdr;
@@ -217,22 +261,20 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
     }
     H.n_fins = static_cast<uint32_t>(plan.fins.size());
     H.fin_blocks = fb;
+    unsigned form = 0;
+    for (int c = 0; c < N_CLASSES; ++c)
+        if (H.class_tiles[c] > 0)
+            form |= 1u << c;
+    if (H.n_fins > 0)
+        form |= (H.any_top ? 1u : 2u) << N_CLASSES;
+    hipGraphExec_t x = nullptr;
+    if ((rc = graph_for(s, form, &x)) != PPS_OK)
+        return rc;
     hipError_t e = hipSuccess;
     if (last_slot_ >= 0 && last_stream_ != stream)
         e = hipStreamWaitEvent(stream, slots_[last_slot_].sim_stop, 0);
     if (e == hipSuccess)
-        e = hipGraphLaunch(s.exec[EPOCH_STAGE_IN], stream);
-    if (e == hipSuccess)
-        e = hipEventRecord(s.sim_start, stream);
-    for (int c = 0; c < N_CLASSES && e == hipSuccess; ++c)
-        if (H.class_tiles[c] > 0)
-            e = hipGraphLaunch(s.exec[EPOCH_SIMULATE + c], stream);
-    if (e == hipSuccess)
-        e = hipEventRecord(s.sim_stop, stream);
-    if (e == hipSuccess && H.n_fins > 0)
-        e = hipGraphLaunch(s.exec[H.any_top ? EPOCH_FINALIZE : EPOCH_FINALIZE_FIXED], stream);
-    if (e == hipSuccess)
-        e = hipGraphLaunch(s.exec[EPOCH_STAGE_OUT], stream);
+        e = hipGraphLaunch(x, stream);
     if (e != hipSuccess)
         return fail_hip(e, "epoch graph launch");
     e = hipEventRecord(s.done, stream);

@@ -1,13 +1,14 @@
 // Epoch engine: runs batches of job rows (and the finalisation of ABC jobs)
-// as one captured hipGraph per staging slot.  A slot owns mapped pinned host
+// as one captured hipGraph launch per epoch.  A slot owns mapped pinned host
 // tables (written by the host before each epoch, copied in by the stage-in
 // kernel), device tables, result areas written back by the stage-out kernel,
-// and the instantiated graph of the whole epoch.
+// and the instantiated graphs of the epoch forms it has run.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <vector>
 
 #include "pps_internal.hpp"
@@ -88,15 +89,19 @@ class EpochEngine {
         FinResult *h_out_fin = nullptr;
         unsigned long long *h_out_counts = nullptr;
         EpochDevPtrs dev;
-        hipGraphExec_t exec[EPOCH_PARTS] = {};
-        bool have_exec = false;
+        // one graph per epoch form: the classes with tiles (a bit each) and
+        // the finalisation (none / with the selection passes / fixed
+        // tolerance only), built on first use for the current shape
+        std::map<unsigned, hipGraphExec_t> execs;
+        bool have_shape = false;
         EpochShape exec_shape;
         hipEvent_t sim_start = nullptr, sim_stop = nullptr, done = nullptr;
         hipStream_t own_stream = nullptr;  // slots after the first
         bool in_flight = false;
         float sim_ms = -1.0f;
     };
-    int build_graph(Slot &s);
+    int set_graph_shape(Slot &s);
+    int graph_for(Slot &s, unsigned form, hipGraphExec_t *out);
     int finish(Slot &s);
 
     std::vector<Slot> slots_;

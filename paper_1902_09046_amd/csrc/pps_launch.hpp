@@ -60,8 +60,9 @@ hipError_t sim_occupancy(int cls, const SimShape &sh, int *blocks_per_cu);
 // (when the epoch finishes ABC jobs: EPOCH_FINALIZE with the tolerance
 // selection passes when one of them takes the closest fraction,
 // EPOCH_FINALIZE_FIXED without them otherwise); stage-out.  Every launch shape
-// is fixed by `shape`, so each part is captured once into a graph and replayed
-// with new table contents; timing events bracket the simulation parts.
+// is fixed by `shape`, so the parts an epoch needs are captured once into one
+// graph per epoch form and replayed with new table contents; timing events,
+// record nodes of that graph, bracket the simulation parts.
 enum {
     EPOCH_STAGE_IN = 0,
     EPOCH_SIMULATE = 1,  // + class
