@@ -188,9 +188,13 @@ def serving_bench(P, torch, W, golden, n_jobs: int, rate_hz: float):
                         "mean_ms": round(float(lat.mean()) * 1e3, 3), "wall_s": round(wall, 3),
                         "epochs": int(st.epochs), "gpu_busy_s": round(st.busy_s, 3)}
 
-    # saturated: all jobs at t = 0, continuous batching vs one job per launch
+    # saturated: all jobs at t = 0, continuous batching vs one job per launch;
+    # each policy first runs the first 64 jobs untimed (the batch runner's
+    # epoch graphs are built on first use of each epoch form)
     sat = {}
     for name, pol in (("batched", P.PPS_POLICY_BATCHED), ("plain", P.PPS_POLICY_PLAIN)):
+        P.pps_run_batch(jobs[:64], P.make_server_config(arena, epoch_ms=8.0, max_active=1024,
+                                                        policy=pol))
         print(f"bench: serving saturated {name}", file=sys.stderr, flush=True)
         cfg = P.make_server_config(arena, epoch_ms=8.0, max_active=1024, policy=pol)
         torch.cuda.synchronize()
