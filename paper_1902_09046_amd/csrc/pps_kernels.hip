@@ -1504,7 +1504,30 @@ struct Moments {
 };
 
 // Chan et al. pairwise update: a <- a (+) b (a first in index order).
+// Branch-free: an empty side (n = 0, zero mean and m2) leaves the other
+// exactly as it is (weights 0 or 1), so the result equals the form that
+// copies or skips, and the loads of b are never made conditional on b.n.
 __device__ __forceinline__ void moments_merge(Moments &a, const Moments &b, int np)
+{
+    const double n = a.n + b.n;
+    const double wb = n > 0.0 ? b.n / n : 0.0;
+    const double wab = n > 0.0 ? a.n * b.n / n : 0.0;
+#pragma unroll
+    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+        if (j < np) {
+            const double delta = b.mean[j] - a.mean[j];
+            a.mean[j] += delta * wb;
+            a.m2[j] += b.m2[j] + delta * delta * wab;
+        }
+    }
+    a.n = n;
+}
+
+// The same result, skipping the arithmetic when a side is empty: cheaper
+// where most operands are empty (the tail of a small job's fold tree);
+// elsewhere the branch-free form keeps the instruction stream free of waits
+// on the operands.
+__device__ __forceinline__ void moments_merge_skip(Moments &a, const Moments &b, int np)
 {
     if (b.n == 0.0)
         return;
@@ -1512,16 +1535,7 @@ __device__ __forceinline__ void moments_merge(Moments &a, const Moments &b, int 
         a = b;
         return;
     }
-    const double n = a.n + b.n;
-#pragma unroll
-    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-        if (j < np) {
-            const double delta = b.mean[j] - a.mean[j];
-            a.mean[j] += delta * (b.n / n);
-            a.m2[j] += b.m2[j] + delta * delta * (a.n * b.n / n);
-        }
-    }
-    a.n = n;
+    moments_merge(a, b, np);
 }
 
 __device__ __forceinline__ double moments_readlane(double v, int l)
@@ -1533,6 +1547,7 @@ __device__ __forceinline__ double moments_readlane(double v, int l)
 }
 
 constexpr int PARTIAL_STRIDE = 1 + 2 * PPS_MAX_PARAMS;
+constexpr unsigned MOMENTS_GRID = 256;  // workgroups of k_moments_final
 
 // Writes accepted records in draw-index order and per-block moment partials.
 __global__ __launch_bounds__(FIN_BLOCK) void k_compact_write(const EpochHeader *__restrict__ hdr,
@@ -1731,45 +1746,57 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_moments_final(const EpochHeader *
                                                               const FinJob *__restrict__ fins)
 {
     __shared__ Moments s_m[FIN_BLOCK];
-    if (blockIdx.x >= hdr->n_fins)
-        return;
-    const FinJob *F = fins + blockIdx.x;
-    FinResult *R = F->result;
-    const int np = F->n_params;
-    const uint64_t nb = F->n_blocks;
-    const uint64_t chunk = (nb + FIN_BLOCK - 1) / FIN_BLOCK;
-    Moments m;
-    m.n = 0.0;
-#pragma unroll
-    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-        m.mean[j] = 0.0;
-        m.m2[j] = 0.0;
-    }
-    for (uint64_t b = threadIdx.x * chunk; b < (threadIdx.x + 1) * chunk && b < nb; ++b) {
-        const double *p = F->partials + b * PARTIAL_STRIDE;
-        Moments o;
-        o.n = p[0];
+    const int n_fins = static_cast<int>(hdr->n_fins);
+    for (int f = blockIdx.x; f < n_fins; f += gridDim.x) {
+        const FinJob *F = fins + f;
+        FinResult *R = F->result;
+        const int np = F->n_params;
+        const uint64_t nb = F->n_blocks;
+        const uint64_t chunk = (nb + FIN_BLOCK - 1) / FIN_BLOCK;
+        Moments m;
+        m.n = 0.0;
 #pragma unroll
         for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-            o.mean[j] = p[1 + j];
-            o.m2[j] = p[1 + PPS_MAX_PARAMS + j];
+            m.mean[j] = 0.0;
+            m.m2[j] = 0.0;
         }
-        moments_merge(m, o, np);
-    }
-    s_m[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = 1; off < FIN_BLOCK; off <<= 1) {
-        if ((threadIdx.x & (2 * off - 1)) == 0 && threadIdx.x + off < FIN_BLOCK)
-            moments_merge(s_m[threadIdx.x], s_m[threadIdx.x + off], np);
+        // this thread's partials in block order, loaded four at a time
+        // before their merges (one memory round trip per four partials)
+        const uint64_t b_end = (threadIdx.x + 1) * chunk < nb ? (threadIdx.x + 1) * chunk : nb;
+        for (uint64_t b0 = threadIdx.x * chunk; b0 < b_end; b0 += 4) {
+            Moments o[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t b = b0 + u < b_end ? b0 + u : b0;
+                const double *__restrict__ p = F->partials + b * PARTIAL_STRIDE;
+                o[u].n = p[0];
+#pragma unroll
+                for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+                    o[u].mean[j] = p[1 + j];
+                    o[u].m2[j] = p[1 + PPS_MAX_PARAMS + j];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (b0 + u < b_end)
+                    moments_merge(m, o[u], np);
+        }
+        s_m[threadIdx.x] = m;
         __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const Moments &t = s_m[0];
-        const double nan = __longlong_as_double(0x7ff8000000000000ll);
-        for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-            R->mean[j] = (j < np && t.n > 0.0) ? t.mean[j] : nan;
-            R->var[j] = (j < np && t.n > 1.0) ? t.m2[j] / (t.n - 1.0) : nan;
+        for (int off = 1; off < FIN_BLOCK; off <<= 1) {
+            if ((threadIdx.x & (2 * off - 1)) == 0 && threadIdx.x + off < FIN_BLOCK)
+                moments_merge_skip(s_m[threadIdx.x], s_m[threadIdx.x + off], np);
+            __syncthreads();
         }
+        if (threadIdx.x == 0) {
+            const Moments &t = s_m[0];
+            const double nan = __longlong_as_double(0x7ff8000000000000ll);
+            for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+                R->mean[j] = (j < np && t.n > 0.0) ? t.mean[j] : nan;
+                R->var[j] = (j < np && t.n > 1.0) ? t.m2[j] / (t.n - 1.0) : nan;
+            }
+        }
+        __syncthreads();  // s_m is reused by the next job
     }
 }
 
@@ -1887,7 +1914,10 @@ hipError_t issue_epoch_part(int part, const EpochDevPtrs &p, const EpochShape &s
     hipLaunchKernelGGL(k_compact_count, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins);
     hipLaunchKernelGGL(k_compact_scan, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
     hipLaunchKernelGGL(k_compact_write, dim3(shape.fin_grid), fb, 0, s, p.d_hdr, p.d_fins);
-    hipLaunchKernelGGL(k_moments_final, dim3(MAX_FINS), fb, 0, s, p.d_hdr, p.d_fins);
+    // few workgroups, each taking jobs in turn: the kernel holds many
+    // registers, and surplus workgroups of a MAX_FINS grid cost a dispatch
+    // round of their own
+    hipLaunchKernelGGL(k_moments_final, dim3(MOMENTS_GRID), fb, 0, s, p.d_hdr, p.d_fins);
     return hipGetLastError();
 }
 
