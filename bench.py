@@ -261,7 +261,7 @@ def calibrate_copy():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: this benchmark runs on one GPU only; --gpus must be 1 "
               "(multi-GPU sharding of draw ranges is described in the design notes, not built)",
               file=sys.stderr)
         sys.exit(2)
