@@ -594,8 +594,9 @@ struct pps_server {
                 continue;
             if (sched.has_inflight())
                 // an epoch is running and nothing else can start: look again
-                // in 100 us, or at once when a job is submitted
-                cv.wait_for(lk, std::chrono::microseconds(100));
+                // in 25 us (a finished epoch's results wait at most that long
+                // to become visible), or at once when a job is submitted
+                cv.wait_for(lk, std::chrono::microseconds(25));
             else
                 // idle, or waiting for arena memory: until a submission or release
                 cv.wait(lk, [&] { return stop || !inbox.empty() || released; });
