@@ -1,6 +1,7 @@
 // Epoch engine (see pps_engine.hpp).
 #include "pps_engine.hpp"
 
+#include <chrono>
 #include <cstring>
 
 #include "pps_runtime.hpp"
@@ -303,7 +304,15 @@ int EpochEngine::wait(int slot)
     Slot &s = slots_[slot];
     if (!s.in_flight)
         return PPS_OK;
-    hipError_t e = hipEventSynchronize(s.done);
+    // poll the completion event (the caller waits on this thread anyway);
+    // hand over to the runtime's blocking wait after a long epoch
+    hipError_t e = hipErrorNotReady;
+    const auto t0 = std::chrono::steady_clock::now();
+    while ((e = hipEventQuery(s.done)) == hipErrorNotReady &&
+           std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(50)) {
+    }
+    if (e == hipErrorNotReady)
+        e = hipEventSynchronize(s.done);
     if (e != hipSuccess) {
         s.in_flight = false;
         return fail_hip(e, "epoch");
