@@ -362,3 +362,28 @@ def test_invalid_arguments_raise(P, torch):
         P.simulate(spec, 1, 0, 10)
     with pytest.raises(P.PPSError):
         P.abc(W.logistic_spec(), np.zeros(20), 1, 0, 100, P.PPS_EPS_TOP_FRACTION, 1.5)
+
+
+def test_kernel_timing_events(P, torch):
+    """The simulation kernels are timed by HIP event-record nodes of the
+    epoch's graph: with timing on, each call reports a positive kernel time
+    below the call's wall time, growing with the work."""
+    import time
+    ob = observed()["logistic_S1000"]
+    spec = W.logistic_spec(steps=1000)
+    P.pps_set_timing(True)
+    try:
+        kms = []
+        for n in (2_000_000, 8_000_000):  # both above one pass of the resident grid
+            P.abc(spec, ob["y_obs"], 1, 0, n, P.PPS_EPS_FIXED, 60.0)  # first use builds the graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.abc(spec, ob["y_obs"], 1, 0, n, P.PPS_EPS_FIXED, 60.0)
+            torch.cuda.synchronize()
+            wall_ms = (time.perf_counter() - t0) * 1e3
+            k = P.pps_last_kernel_ms()
+            assert 0.0 < k <= wall_ms, (n, k, wall_ms)
+            kms.append(k)
+        assert 2.5 * kms[0] < kms[1] < 6.0 * kms[0]
+    finally:
+        P.pps_set_timing(False)
