@@ -226,7 +226,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=10_000_000, help="prior draws per step")
-    ap.add_argument("--cpu-sample", type=int, default=2_000_000,
+    ap.add_argument("--cpu-sample", type=int, default=8_000_000,
                     help="draws of the oracle's timed sample (0 disables the CPU baseline)")
     ap.add_argument("--only-main", action="store_true",
                     help="skip the p-value batch, GARCH, toggle-switch, weak-informativity and "
