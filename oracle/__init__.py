@@ -108,6 +108,14 @@ P_DATA_BASE, P_DATA_K = 0x40000000, 0x40000001
 _lib = None
 
 
+def _check(rc: int, what: str = "invalid input") -> None:
+    """Raises for a negative oracle status (-2: a buffer could not be allocated)."""
+    if rc == -2:
+        raise MemoryError("oracle: allocation failed")
+    if rc < 0:
+        raise ValueError("oracle: " + what)
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -307,8 +315,7 @@ def simulate(spec: Mapping, seed: int, first: int, n: int, y_obs=None) -> dict:
     rc = _load().or_simulate(ctypes.byref(m), seed, first, n,
                              y.ctypes.data if y is not None else None,
                              theta, summ, stat, dist, att)
-    if rc != 0:
-        raise ValueError("oracle: invalid model")
+    _check(rc, "invalid model")
     return {"theta": theta, "summ": summ, "stat": stat, "dist": dist, "attempts": att}
 
 
@@ -330,8 +337,7 @@ def abc(spec: Mapping, y_obs, seed: int, first: int, n: int, mode: int, eps_or_f
     rc = _load().or_abc(ctypes.byref(m), np.ascontiguousarray(y_obs, np.float64), seed, first, n,
                         mode, eps_or_frac, cap, idx, th, d, ctypes.byref(nacc), ctypes.byref(eps),
                         mean, var)
-    if rc < 0:
-        raise ValueError("oracle: invalid input")
+    _check(rc, "invalid input")
     k = min(int(nacc.value), cap)
     return {"idx": idx[:k], "theta": th[:k], "dist": d[:k], "n_accepted": int(nacc.value),
             "eps_used": float(eps.value), "mean": mean[: m.n_params], "var": var[: m.n_params],
@@ -346,8 +352,7 @@ def pvalue(spec: Mapping, lambda_param: int, lambda_family: str, lambdas, seed: 
     p = np.zeros(len(lam), np.float64)
     rc = _load().or_pvalue(ctypes.byref(m), lambda_param, _FAMILY[lambda_family], lam, len(lam),
                            seed, first, n, t_obs, counts, p)
-    if rc != 0:
-        raise ValueError("oracle: invalid input")
+    _check(rc, "invalid input")
     return {"count_ge": counts, "pvalue": p}
 
 
@@ -357,8 +362,7 @@ def summary_tally(spec: Mapping, seed: int, first: int, n: int, obs_summ) -> np.
     counts = np.zeros(ns, np.uint64)
     rc = _load().or_summary_tally(ctypes.byref(m), seed, first, n,
                                   np.ascontiguousarray(obs_summ, np.float64), counts)
-    if rc != 0:
-        raise ValueError("oracle: invalid input")
+    _check(rc, "invalid input")
     return counts
 
 
@@ -574,6 +578,5 @@ def tb_simulate(spec: Mapping, seed: int, first: int, n: int) -> dict:
     nf = np.zeros(n, np.uint64)
     summ = np.zeros((n, 2), np.float64)
     rc = _load().or_tb_simulate(ctypes.byref(m), seed, first, n, theta, status, events, nf, summ)
-    if rc != 0:
-        raise ValueError("oracle: invalid tuberculosis model")
+    _check(rc, "invalid tuberculosis model")
     return {"theta": theta, "status": status, "events": events, "n": nf, "summ": summ}

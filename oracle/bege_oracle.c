@@ -111,9 +111,12 @@ double or_bege_density(double u, double p, double n, double sp, double sn, int n
  *   for t = 1..T: u_t = r_t - mu; log f(u_t | p_{t-1}, n_{t-1}); then
  *     p_t = p0 + rho_p p_{t-1} + phi_p^{+/-} u_t^2 / (2 s_p^2)  (+ for u_t >= 0),
  *     n_t = n0 + rho_n n_{t-1} + phi_n^{+/-} u_t^2 / (2 s_n^2)   (Eq. shape).
- * A non-positive shape or density estimate gives log f = -inf at that step;
- * scales that are not positive (outside the model's domain) give -inf at
- * every step.  ld (optional, T values) receives each log f.  Returns 0.      */
+ * A non-positive shape or density estimate gives log f = -inf at that step.
+ * The shocks of Eq. BEGE are s_p w_p - s_n w_n with w_p, w_n gamma variates
+ * of unit scale, so s_p and s_n are the scales of gamma laws: a law with a
+ * scale that is not positive does not exist, such a theta lies outside the
+ * model's parameter space, and its likelihood is zero (log f = -inf at every
+ * step).  ld (optional, T values) receives each log f.  Returns 0.          */
 int or_bege_loglik(const double *th, const double *r, int T, int n_omega, double *ld, double *ll)
 {
     const double p0 = th[0], sp = th[1], rp = th[2], ppos = th[3], pneg = th[4];

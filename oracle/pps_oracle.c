@@ -581,11 +581,18 @@ int or_tb_simulate(const or_model *m, uint64_t seed, uint64_t first, uint64_t n,
 {
     if (m->model != OR_TB || m->n_params != 3 || m->n_cells < 1 || m->n_obs < 1)
         return -1;
+    int oom = 0;
 #pragma omp parallel
     {
         uint32_t *X = (uint32_t *)malloc(2 * (size_t)m->n_cells * sizeof(uint32_t));
+        if (!X) {
+#pragma omp atomic write
+            oom = 1;
+        }
 #pragma omp for schedule(dynamic, 1)
         for (uint64_t q = 0; q < n; ++q) {
+            if (!X)
+                continue;
             const uint64_t draw = first + q;
             double *th = &theta[q * 3];
             or_prior_draw(m, seed, draw, th);
@@ -598,7 +605,7 @@ int or_tb_simulate(const or_model *m, uint64_t seed, uint64_t first, uint64_t n,
         }
         free(X);
     }
-    return 0;
+    return oom ? -2 : 0;
 }
 
 int or_n_summaries(const or_model *m)
@@ -697,11 +704,18 @@ int or_simulate(const or_model *m, uint64_t seed, uint64_t first, uint64_t n,
     const int np = m->n_params;
     const int ns = or_n_summaries(m);
     const size_t wl = work_len(m);
+    int oom = 0;
 #pragma omp parallel
     {
         double *work = (double *)malloc(wl * sizeof(double));
+        if (!work) {
+#pragma omp atomic write
+            oom = 1;
+        }
 #pragma omp for schedule(static)
         for (int64_t q = 0; q < (int64_t)n; ++q) {
+            if (!work)
+                continue;
             uint64_t draw = first + (uint64_t)q;
             double *th = theta + (size_t)q * np;
             double *s = summ + (size_t)q * ns;
@@ -716,7 +730,7 @@ int or_simulate(const or_model *m, uint64_t seed, uint64_t first, uint64_t n,
         }
         free(work);
     }
-    return 0;
+    return oom ? -2 : 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -776,11 +790,18 @@ int or_abc(const or_model *m, const double *y_obs, uint64_t seed, uint64_t first
     double *theta = (double *)malloc((size_t)n * np * sizeof(double));
     double *summ = (double *)malloc((size_t)n * ns * sizeof(double));
     double *dist = (double *)malloc((size_t)n * sizeof(double));
-    or_simulate(m, seed, first, n, y_obs, theta, summ, NULL, dist, NULL);
-    free(summ);
-
     /* accepted positions q (relative to first), in increasing order */
     uint64_t *acc = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    int rc = (theta && summ && dist && acc) ? or_simulate(m, seed, first, n, y_obs, theta, summ,
+                                                          NULL, dist, NULL)
+                                            : -2;
+    free(summ);
+    if (rc != 0) {
+        free(acc);
+        free(dist);
+        free(theta);
+        return -2;
+    }
     uint64_t count = 0;
     double eps;
     if (mode == OR_EPS_FIXED) {
@@ -791,6 +812,12 @@ int or_abc(const or_model *m, const double *y_obs, uint64_t seed, uint64_t first
     } else {
         uint64_t k = or_top_count(eps_or_frac, n);
         dist_index *order = (dist_index *)malloc((size_t)n * sizeof(dist_index));
+        if (!order) {
+            free(acc);
+            free(dist);
+            free(theta);
+            return -2;
+        }
         for (uint64_t q = 0; q < n; ++q) {
             order[q].d = dist[q];
             order[q].i = q;
@@ -847,8 +874,8 @@ int or_pvalue(const or_model *m, int lambda_param, int lambda_family, const doub
     if (!model_ok(m) || m->model == OR_GARCH11 || lambda_param < 0 ||
         lambda_param >= m->n_params || n_lambda < 1 || n == 0)
         return -1;
-    const int np = m->n_params;
     const int ns = or_n_summaries(m);
+    int oom = 0;
     for (int k = 0; k < n_lambda; ++k) {
         or_model mk = *m;
         mk.prior[lambda_param].family = lambda_family;
@@ -859,8 +886,15 @@ int or_pvalue(const or_model *m, int lambda_param, int lambda_family, const doub
             double theta[OR_MAX_PARAMS];
             double *summ = (double *)malloc((size_t)ns * sizeof(double));
             double *work = (double *)malloc(work_len(m) * sizeof(double));
+            const int ok = summ && work;
+            if (!ok) {
+#pragma omp atomic write
+                oom = 1;
+            }
 #pragma omp for schedule(static)
             for (int64_t q = 0; q < (int64_t)n; ++q) {
+                if (!ok)
+                    continue;
                 uint64_t draw = first + (uint64_t)q;
                 or_prior_draw(&mk, seed, draw, theta);
                 simulate_summaries(&mk, theta, seed, draw, summ, work);
@@ -870,15 +904,17 @@ int or_pvalue(const or_model *m, int lambda_param, int lambda_family, const doub
             free(work);
             free(summ);
         }
-        (void)np;
         count_ge[k] = count;
         pvalue[k] = (double)count / (double)n;
     }
-    return 0;
+    return oom ? -2 : 0;
 }
 
-/* Per-summary tail-area tallies for a summary-vector model (used for the
- * GARCH prior-predictive check): count_ge[s] = #{i : S_s(D_i) >= obs[s]}.   */
+/* Per-summary tail-area tallies for a summary-vector model (the
+ * prior-predictive check of the GARCH, toggle-switch and tuberculosis
+ * summaries; the tail-area form of Eq. pppv per summary):
+ * count_ge[s] = #{i : S_s(D_i) >= obs[s]}, the comparison inclusive.
+ * Returns 0, -1 for an invalid model, -2 when a buffer cannot be allocated. */
 int or_summary_tally(const or_model *m, uint64_t seed, uint64_t first, uint64_t n,
                      const double *obs_summ, uint64_t *count_ge)
 {
@@ -888,14 +924,22 @@ int or_summary_tally(const or_model *m, uint64_t seed, uint64_t first, uint64_t 
     const size_t wl = work_len(m);
     for (int s = 0; s < ns; ++s)
         count_ge[s] = 0;
+    int oom = 0;
 #pragma omp parallel
     {
         double theta[OR_MAX_PARAMS];
         double *summ = (double *)malloc((size_t)ns * sizeof(double));
         double *work = (double *)malloc(wl * sizeof(double));
         uint64_t *local = (uint64_t *)calloc((size_t)ns, sizeof(uint64_t));
+        const int ok = summ && work && local;
+        if (!ok) {
+#pragma omp atomic write
+            oom = 1;
+        }
 #pragma omp for schedule(static)
         for (int64_t q = 0; q < (int64_t)n; ++q) {
+            if (!ok)
+                continue;
             uint64_t draw = first + (uint64_t)q;
             or_prior_draw(m, seed, draw, theta);
             simulate_summaries(m, theta, seed, draw, summ, work);
@@ -904,13 +948,14 @@ int or_summary_tally(const or_model *m, uint64_t seed, uint64_t first, uint64_t 
                     ++local[s];
         }
 #pragma omp critical
-        for (int s = 0; s < ns; ++s)
-            count_ge[s] += local[s];
+        if (ok)
+            for (int s = 0; s < ns; ++s)
+                count_ge[s] += local[s];
         free(local);
         free(work);
         free(summ);
     }
-    return 0;
+    return oom ? -2 : 0;
 }
 
 /* The full path of one draw at every step (for convergence checks):
