@@ -343,7 +343,8 @@ int pps_server_create(const pps_server_config *config, pps_server **server);
 int pps_submit(pps_server *server, const pps_job *job, uint64_t *job_id);
 /* PPS_PENDING while the job runs; PPS_OK (or the job's error status) with
  * *out filled once its result is visible; PPS_ENOTFOUND for unknown or
- * released ids. */
+ * released ids.  After a device error the server stops: every job that had
+ * not finished completes with that error, and pps_submit returns it. */
 int pps_poll(pps_server *server, uint64_t job_id, pps_job_result *out);
 /* Frees a finished job's arena memory.  PPS_EBUSY if it has not finished,
  * PPS_ENOTFOUND if unknown or already released. */
@@ -356,9 +357,16 @@ typedef struct {
     double latency_p50_s, latency_p99_s; /* submit -> visible, completed jobs */
 } pps_server_stats;
 int pps_server_stats_get(pps_server *server, pps_server_stats *stats);
-/* Stops the server thread after the epochs in flight finish; pending jobs
- * are dropped.  The arena is not freed (it belongs to the caller). */
+/* Stops the server thread after the epochs in flight finish; queued and
+ * admitted jobs that are not in flight are dropped without running.  The
+ * arena is not freed (it belongs to the caller). */
 int pps_server_destroy(pps_server *server);
+/* Fault injection for tests of the error path (no device fault involved):
+ * once `after_epochs` epochs have been harvested, every later epoch is
+ * reported as failed with `status` (< 0) when it ends on the device.  The
+ * server then stops as after a real device error.  PPS_EINVAL for
+ * status >= 0. */
+int pps_server_inject_error(pps_server *server, uint64_t after_epochs, int status);
 
 /* ---- weak-informativity test (Sec. 4.1: Alg. 2, evidence by Alg. 3) ---- */
 /* The logistic dose-response model of Eq. bioassay: group i of n_groups has

@@ -200,6 +200,7 @@ def lib():
         L.pps_release.argtypes = [vp, u64]
         L.pps_server_stats_get.argtypes = [vp, ctypes.POINTER(pps_server_stats)]
         L.pps_server_destroy.argtypes = [vp]
+        L.pps_server_inject_error.argtypes = [vp, u64, ctypes.c_int]
         L.pps_autotune.argtypes = [mp, u64, ctypes.c_int, ctypes.POINTER(pps_tune_report), vp]
         L.pps_autotune.restype = ctypes.c_int
         bp, scp = ctypes.POINTER(pps_bioassay), ctypes.POINTER(pps_smc_config)
@@ -217,7 +218,7 @@ def lib():
         for name in ("pps_philox", "pps_normals", "pps_simulate", "pps_n_summaries", "abc_sample",
                      "prior_pred_pvalue", "pps_summary_tally", "pps_run_batch", "pps_server_create",
                      "pps_submit", "pps_poll", "pps_release", "pps_server_stats_get",
-                     "pps_server_destroy"):
+                     "pps_server_destroy", "pps_server_inject_error"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -504,6 +505,11 @@ class Server:
         s = pps_server_stats()
         _check(lib().pps_server_stats_get(self._h, ctypes.byref(s)))
         return s
+
+    def inject_error(self, after_epochs: int, status: int) -> None:
+        """Test hook: epochs harvested after the first `after_epochs` report
+        `status` (< 0) and the server stops as after a device error."""
+        _check(lib().pps_server_inject_error(self._h, after_epochs, status))
 
     def close(self):
         if self._h:

@@ -201,6 +201,42 @@ class Scheduler {
         return rc;
     }
 
+    // Waits for the epochs in flight and harvests them; admits and plans
+    // nothing.  Returns the first error met, else PPS_OK.
+    int drain()
+    {
+        int first = PPS_OK;
+        while (!inflight_.empty()) {
+            const int rc = harvest(true);
+            if (rc != PPS_OK && first == PPS_OK)
+                first = rc;
+        }
+        return first;
+    }
+
+    // Completes every job that has not finished with `status` (after an
+    // error nothing more is planned, so no such job would ever finish).
+    // Call after drain(): no epoch is in flight.
+    void fail_pending(int status)
+    {
+        for (Job *j : queue_)
+            complete(j, status);
+        queue_.clear();
+        for (Job *j : active_)
+            if (j->state != JobState::DONE)
+                complete(j, status);
+        active_.clear();
+    }
+
+    // Host-side fault injection for tests of the error path: the harvest of
+    // every epoch after the first `after_epochs` reports `status` in place of
+    // its result (the epoch itself still runs to its end on the device).
+    void inject_error(uint64_t after_epochs, int status)
+    {
+        inject_after_ = after_epochs;
+        inject_status_ = status;
+    }
+
     bool idle() const { return queue_.empty() && active_.empty() && inflight_.empty(); }
     bool has_inflight() const { return !inflight_.empty(); }
     bool can_plan() const
@@ -462,10 +498,16 @@ class Scheduler {
             int rc = wait ? eng_->wait(f.slot) : eng_->poll(f.slot);
             if (rc == PPS_PENDING)
                 return PPS_OK;
+            if (rc == PPS_OK && inject_status_ != PPS_OK && harvested_ >= inject_after_)
+                rc = fail(inject_status_, "injected error after %llu epochs",
+                          static_cast<unsigned long long>(inject_after_));
             if (rc != PPS_OK) {
-                for (Job *j : f.finishing)
+                for (Job *j : f.finishing) {
                     complete(j, rc);
+                    active_.erase(std::find(active_.begin(), active_.end(), j));
+                }
                 inflight_.pop_front();
+                ++harvested_;
                 return rc;
             }
             const float ms = eng_->sim_ms(f.slot);
@@ -524,6 +566,8 @@ class Scheduler {
     std::vector<double> latencies_;
     double busy_s_ = 0.0;
     double rate_ = 1.5e12;  // logistic-step units per second (updated from measurements)
+    uint64_t inject_after_ = 0;
+    int inject_status_ = PPS_OK;
 };
 
 static int validate_config(const pps_server_config *c)
@@ -602,9 +646,20 @@ struct pps_server {
                 cv.wait(lk, [&] { return stop || !inbox.empty() || released; });
             released = false;
         }
-        while (sched.has_inflight())
-            if (sched.step(true) != PPS_OK)
-                break;
+        // Shutdown or error: wait for the epochs in flight only; nothing is
+        // admitted or planned any more.
+        const int rc = sched.drain();
+        if (error == PPS_OK && rc != PPS_OK && !stop)
+            error = rc;
+        if (error != PPS_OK) {
+            // every job that has not finished ends with the error, so that
+            // pps_poll reports it instead of PPS_PENDING
+            while (!inbox.empty()) {
+                sched.enqueue(std::move(inbox.front()));
+                inbox.pop_front();
+            }
+            sched.fail_pending(error);
+        }
     }
     bool released = false;
 };
@@ -651,8 +706,15 @@ int pps_run_batch(const pps_job *jobs, int n_jobs, const pps_server_config *conf
     for (int i = 0; i < n_jobs; ++i)
         sched.enqueue(make_job(&jobs[i], static_cast<uint64_t>(i + 1), n_summ[i]));
     while (!sched.idle()) {
-        if ((rc = sched.step(true)) != PPS_OK)
+        if ((rc = sched.step(true)) != PPS_OK) {
+            // wait for the other epoch in flight, then report the error as
+            // the status of every job that did not finish
+            sched.drain();
+            sched.fail_pending(rc);
+            for (int i = 0; i < n_jobs; ++i)
+                results[i] = sched.find(static_cast<uint64_t>(i + 1))->result;
             return rc;
+        }
     }
     for (int i = 0; i < n_jobs; ++i)
         results[i] = sched.find(static_cast<uint64_t>(i + 1))->result;
@@ -731,11 +793,14 @@ int pps_poll(pps_server *server, uint64_t job_id, pps_job_result *out)
     if (!j) {
         for (const auto &p : server->inbox)
             if (p->id == job_id)
-                return PPS_PENDING;
+                return server->error != PPS_OK
+                           ? fail(server->error, "server stopped after an error")
+                           : PPS_PENDING;
         return fail(PPS_ENOTFOUND, "unknown job %llu", static_cast<unsigned long long>(job_id));
     }
     if (j->state != JobState::DONE)
-        return PPS_PENDING;
+        return server->error != PPS_OK ? fail(server->error, "server stopped after an error")
+                                       : PPS_PENDING;
     if (out)
         *out = j->result;
     return j->result.status;
@@ -786,6 +851,21 @@ int pps_server_stats_get(pps_server *server, pps_server_stats *stats)
         stats->latency_p50_s = q(0.50);
         stats->latency_p99_s = q(0.99);
     }
+    return PPS_OK;
+}
+
+int pps_server_inject_error(pps_server *server, uint64_t after_epochs, int status)
+{
+    clear_error();
+    if (!server)
+        return fail(PPS_EINVAL, "server is NULL");
+    if (status >= PPS_OK)
+        return fail(PPS_EINVAL, "the injected status must be an error (< 0)");
+    {
+        std::lock_guard<std::mutex> lk(server->mu);
+        server->sched.inject_error(after_epochs, status);
+    }
+    server->cv.notify_one();
     return PPS_OK;
 }
 

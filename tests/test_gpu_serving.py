@@ -292,6 +292,61 @@ def test_server_errors(P, torch):
             srv.poll(12345)
 
 
+def test_server_error_completes_every_job(P, torch, arena):
+    """After an error (injected from the host once two epochs have been
+    harvested; the device runs every epoch to its end) the server stops:
+    every job that had not finished completes with that error, pps_poll never
+    stays PENDING, and later submissions are refused with it."""
+    jobs, meta = mixed_jobs(P, n_jobs=24, seed=13)
+    ref = alone(P, meta)
+    cfg = P.make_server_config(arena, epoch_ms=0.3, max_active=4)
+    with P.Server(cfg) as srv:
+        srv.inject_error(2, P.PPS_EDEVICE)
+        ids = [srv.submit(j) for j in jobs]
+        status = {}
+        deadline = time.time() + 30
+        while len(status) < len(ids) and time.time() < deadline:
+            for i, jid in enumerate(ids):
+                if i not in status:
+                    rc, r = srv.poll(jid)
+                    if rc != P.PPS_PENDING:
+                        status[i] = rc
+                        if rc in (P.PPS_OK, P.PPS_ETRUNC):
+                            assert_same(P, r, ref[i], arena)
+            time.sleep(0.001)
+        assert len(status) == len(ids), "jobs left pending after the error"
+        failed = [i for i, rc in status.items() if rc == P.PPS_EDEVICE]
+        assert failed and all(rc in (P.PPS_OK, P.PPS_ETRUNC, P.PPS_EDEVICE) for rc in status.values())
+        print(f"{len(ids) - len(failed)} jobs finished before the error, {len(failed)} failed with it")
+        with pytest.raises(P.PPSError) as e:
+            srv.submit(jobs[0])
+        assert e.value.status == P.PPS_EDEVICE
+        for jid in ids:
+            assert srv.release(jid) == P.PPS_OK
+
+
+def test_server_destroy_drops_backlog(P, torch, arena):
+    """Destroying a server with a long backlog waits for the epochs in flight
+    only: it returns long before the backlog could have run."""
+    ob = observed()["logistic_S1000"]
+    spec = W.pvalue_spec(steps=5000)
+    job = P.make_pvalue_job(spec, 0, P.PPS_LOGNORMAL, 0.5, P.make_sampling(1_000_000, 0, 1), ob["t_obs"])
+    n_jobs = 600  # 3e12 Euler steps: over a second of GPU time
+    srv = P.Server(P.make_server_config(arena, epoch_ms=2.0))
+    try:
+        for _ in range(n_jobs):
+            srv.submit(job)
+        time.sleep(0.05)
+        st = srv.stats()
+        assert st.completed < n_jobs
+    finally:
+        t0 = time.perf_counter()
+        srv.close()
+        dt = time.perf_counter() - t0
+    print(f"destroy with {n_jobs - st.completed} jobs left took {dt * 1e3:.1f} ms")
+    assert dt < 0.3
+
+
 def test_batch_truncation_and_enomem(P, torch, arena):
     ob = observed()["logistic_S1000"]
     spec = W.logistic_spec(steps=200)
