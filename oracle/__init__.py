@@ -393,6 +393,32 @@ def garch_summaries(r) -> np.ndarray:
     return s
 
 
+def garch_bar_scales(spec: Mapping, seed: int, draws) -> np.ndarray:
+    """Per draw and GARCH summary, the magnitude an error bar is relative to
+    (test infrastructure, not part of the method).  Variance and kurtosis
+    are sums of non-negative terms: their own value.  The mean and the
+    skewness are signed sums that can lie arbitrarily close to 0, where the
+    rounding of the normals to FP32 alone moves them by far more than a fixed
+    fraction of their value: for them the scale is the same sum over
+    absolute terms, (1/L) sum |r_t| for the mean and
+    (1/L) sum |r_t - rbar|^3 / m2^1.5 for the skewness (componentwise
+    relative error).  The squared-return ACFs are normalised: scale 1."""
+    draws = np.asarray(list(draws), np.int64)
+    out = np.zeros((len(draws), GARCH_NSUMM), np.float64)
+    for q, i in enumerate(draws):
+        th, _ = prior_draw(spec, seed, int(i))
+        r = garch_series(spec, th, seed, int(i))
+        s = garch_summaries(r)
+        d = r - r.mean()
+        m2 = np.mean(d * d)
+        out[q, 0] = np.mean(np.abs(r))
+        out[q, 1] = abs(s[1])
+        out[q, 2] = np.mean(np.abs(d) ** 3) / m2 ** 1.5
+        out[q, 3] = abs(s[3])
+        out[q, 4:] = 1.0
+    return out
+
+
 def distance(x, y) -> float:
     x = np.ascontiguousarray(x, np.float64)
     y = np.ascontiguousarray(y, np.float64)

@@ -119,23 +119,26 @@ __device__ __forceinline__ void sim_normal_mean(const JobDev *__restrict__ J, St
     }
 }
 
-// GARCH(1,1) in scaled deviation form.  With sbar^2 = omega/(1-alpha-beta),
-// s_t = r_t / sbar and h_t = sigma2_t / sbar^2 = 1 + g_t, the recursion
-// sigma2_{t+1} = omega + alpha r_t^2 + beta sigma2_t becomes
-//   g_1 = 0,  s_t = sqrt(1 + g_t) z_t,  g_{t+1} = alpha (s_t^2 - 1) + beta g_t,
-// exactly; the stationary level of g is 0 whatever the FP32 rounding of alpha
-// and beta (the level of 1-alpha-beta+alpha s^2+beta h in FP32 would drift by
-// ~1e-7/(1-alpha-beta) for near-integrated draws).
+// GARCH(1,1) in scaled form.  With sbar^2 = omega/(1-alpha-beta),
+// s_t = r_t / sbar and h_t = sigma2_t / sbar^2, the recursion
+// sigma2_{t+1} = omega + alpha r_t^2 + beta sigma2_t becomes, exactly,
+//   h_1 = 1,  s_t = sqrt(h_t) z_t,  h_{t+1} = (1-alpha-beta) + alpha s_t^2 + beta h_t.
+// The variance ratio h is carried in FP64 with alpha, beta and 1-alpha-beta
+// unrounded: with persistence alpha+beta near 1 the recursion keeps an error
+// in its state for ~1/(1-alpha-beta) steps, so an FP32 state (or FP32
+// alpha, beta) moves the variance and kurtosis of near-integrated draws by
+// up to ~1e-4.  Normals, returns s_t and every summary stay FP32; the two
+// FP64 FMAs issue at the rate of non-packed FP32 ones on this chip.
 // Streaming summaries: plain FP32 sums over 20-step blocks folded into Kahan
 // totals; b_t = s_t^2 - 1 kept in a 10-deep register ring for the lag
 // products; the first 10 b_t are recomputed from the stream at the end for
 // the ACF centring terms.  The closing algebra is FP64.  Requires the length
 // to be a multiple of 20.
-__device__ __forceinline__ float garch_step(float &g, float z, float al, float be)
+__device__ __forceinline__ float garch_step(double &h, float z, double al, double be, double c)
 {
-    const float s = __builtin_amdgcn_sqrtf(1.0f + g) * z;
-    const float bt = s * s - 1.0f;
-    g = __builtin_fmaf(al, bt, be * g);
+    const float s = __builtin_amdgcn_sqrtf(static_cast<float>(h)) * z;
+    const float sq = s * s;
+    h = __builtin_fma(al, static_cast<double>(sq), __builtin_fma(be, h, c));
     return s;
 }
 
@@ -144,10 +147,8 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
 {
     const double alpha_d = theta[1], beta_d = theta[2];
     const double oab = 1.0 - alpha_d - beta_d;
-    const float al = static_cast<float>(alpha_d);
-    const float be = static_cast<float>(beta_d);
     const int len = J->steps;
-    float g = 0.0f;
+    double h = 1.0;
     Kahan K1, K2, K3, K4, KL[PPS_GARCH_LAGS];
     float ring[PPS_GARCH_LAGS];
 #pragma unroll
@@ -167,7 +168,7 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int jj = 4 * p + j;  // position in the 20-step block
-                const float s = garch_step(g, z[j], al, be);
+                const float s = garch_step(h, z[j], alpha_d, beta_d, oab);
                 const float sq = s * s;
                 s1 += s;
                 s2 += sq;
@@ -191,7 +192,7 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
     // The first 10 b_t again (same operations, so the same values).
     float head[PPS_GARCH_LAGS];
     {
-        float g0 = 0.0f;
+        double h0 = 1.0;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             float z[4];
@@ -199,7 +200,7 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (4 * p + j < PPS_GARCH_LAGS) {
-                    const float s = garch_step(g0, z[j], al, be);
+                    const float s = garch_step(h0, z[j], alpha_d, beta_d, oab);
                     head[4 * p + j] = s * s - 1.0f;
                 }
             }

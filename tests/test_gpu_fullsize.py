@@ -88,26 +88,40 @@ def test_abc_n1e7_top_fraction(P, torch):
 @pytest.mark.parametrize("k", [0, 40, 63])
 def test_pvalue_64x1e6(P, torch, k):
     """The 64-lambda batch at 1e6 draws per lambda against the full oracle run
-    for three lambda values (exact where the EM map contracts; chaotic draws
-    only under the widest lambda may flip)."""
+    for three lambda values, draw by draw: the per-draw statistic of the same
+    lambda row (the one-row kernel) decides every draw whose EM map contracts
+    (th1 dt < 2) as the oracle does; the batch's count equals the number of
+    those decisions, so it differs from the oracle's count by at most the
+    number of chaotic draws whose decision flipped."""
     spec = W.pvalue_spec(steps=1000)
     t_obs = observed()["logistic_S1000"]["t_obs"]
     lam = W.lambda_grid(64)
     n = 1_000_000
     counts, p = P.prior_pred_pvalue(spec, 0, P.PPS_LOGNORMAL, lam, P.make_sampling(n, 0, 1), t_obs)
     ref = oracle.pvalue(spec, 0, "lognormal", [lam[k]], 1, 0, n, t_obs)
+    sk = dict(spec, priors=[("lognormal", 0.0, float(lam[k]))] + spec["priors"][1:])
+    o = oracle.simulate(sk, 1, 0, n)
+    g = P.simulate(sk, 1, 0, n)
+    dec_o = o["stat"] >= t_obs
+    dec_g = g["stat"].cpu().numpy().astype(np.float64) >= t_obs
+    chaotic = o["theta"][:, 0] * spec["t_end"] / spec["steps"] >= 2.0
+    flips = int((dec_o != dec_g).sum())
     diff = abs(int(counts[k]) - int(ref["count_ge"][0]))
-    print(f"lambda {lam[k]:.4f}: gpu {counts[k]} oracle {ref['count_ge'][0]} diff {diff}")
+    print(f"lambda {lam[k]:.4f}: gpu {counts[k]} oracle {ref['count_ge'][0]} diff {diff}; "
+          f"chaotic draws {int(chaotic.sum())}, decisions flipped {flips}")
+    assert int(dec_o.sum()) == int(ref["count_ge"][0])
+    assert np.array_equal(dec_o[~chaotic], dec_g[~chaotic])
+    assert int(dec_g.sum()) == int(counts[k])
+    assert diff <= flips
     if lam[k] <= 1.0:
-        assert diff == 0
-    else:
-        assert diff <= 5e-4 * n
+        assert flips == 0 and diff == 0
+    assert p[k] == counts[k] / n
 
 
 def test_garch_n1e6_sampled(P, torch):
     """1e6 GARCH series: 300 sampled draws against the oracle's two-pass
-    summaries."""
-    from test_gpu_parity import GARCH_TOL, garch_errors
+    summaries, every summary within the 1e-5 bar."""
+    from test_gpu_parity import GARCH_TOL, garch_errors, garch_scales
     spec = W.garch_spec()
     n = 1_000_000
     g = P.simulate(spec, W.SAMPLING_SEED, 0, n)
@@ -118,7 +132,7 @@ def test_garch_n1e6_sampled(P, torch):
     o = np.array([oracle.simulate(spec, W.SAMPLING_SEED, int(i), 1)["summ"][0] for i in pick])
     ot = np.array([oracle.simulate(spec, W.SAMPLING_SEED, int(i), 1)["theta"][0] for i in pick[:20]])
     np.testing.assert_array_equal(th[:, pick[:20]].T, ot.astype(np.float32))
-    errs = garch_errors(summ[:, pick].T.astype(np.float64), o)
+    errs = garch_errors(summ[:, pick].T.astype(np.float64), o, garch_scales(spec, W.SAMPLING_SEED, pick))
     for key, e in errs.items():
         print(f"GARCH 1e6 {key}: max {e.max():.2e} median {np.median(e):.2e}")
-        assert np.median(e) <= GARCH_TOL[key]
+        assert e.max() <= GARCH_TOL, key

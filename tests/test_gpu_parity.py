@@ -238,20 +238,22 @@ def test_conjugate_normal_pvalue_gpu(P, torch):
         assert abs(p[k] - pe) <= 4 * math.sqrt(pe * (1 - pe) / n)
 
 
-GARCH_TOL = {"mean": 1e-5, "var": 1e-5, "skew": 1e-5, "kurt": 1e-5, "acf": 1e-5}
+GARCH_TOL = 1e-5
+GARCH_NAMES = ("mean", "var", "skew", "kurt", "acf")
 
 
-def garch_errors(g, o):
-    """Per-summary errors: relative for variance and kurtosis; the mean
-    relative to the series sd; skewness and ACFs absolute (they sit near 0)."""
-    errs = {}
-    sd = np.sqrt(o[:, 1])
-    errs["mean"] = np.abs(g[:, 0] - o[:, 0]) / sd
-    errs["var"] = rel_err(g[:, 1], o[:, 1])
-    errs["skew"] = np.abs(g[:, 2] - o[:, 2])
-    errs["kurt"] = rel_err(g[:, 3], o[:, 3])
-    errs["acf"] = np.abs(g[:, 4:] - o[:, 4:]).max(axis=1)
-    return errs
+def garch_scales(spec, seed, draws):
+    """Per draw and summary, the magnitude the 1e-5 bar is relative to: the
+    value for variance and kurtosis, the sum over absolute terms for the
+    signed mean and skewness, 1 for the ACFs."""
+    return oracle.garch_bar_scales(spec, seed, draws)
+
+
+def garch_errors(g, o, scale):
+    """Per-summary errors in units of the scale above (the bar is 1e-5)."""
+    e = np.abs(g - o) / scale
+    return {"mean": e[:, 0], "var": e[:, 1], "skew": e[:, 2], "kurt": e[:, 3],
+            "acf": e[:, 4:].max(axis=1)}
 
 
 def test_garch_summaries(P, torch):
@@ -261,21 +263,26 @@ def test_garch_summaries(P, torch):
     o = oracle.simulate(spec, 1, 0, n)
     np.testing.assert_array_equal(g["theta"].cpu().numpy().T, o["theta"].astype(np.float32))
     gs = g["summ"].cpu().numpy().T.astype(np.float64)
-    errs = garch_errors(gs, o["summ"])
+    errs = garch_errors(gs, o["summ"], garch_scales(spec, 1, range(n)))
     for k, e in errs.items():
         print(f"GARCH {k}: max {e.max():.2e} median {np.median(e):.2e} p99 {np.quantile(e, 0.99):.2e}")
     for k, e in errs.items():
-        assert np.median(e) <= GARCH_TOL[k], k
+        assert e.max() <= GARCH_TOL, k
 
 
 def test_garch_tally(P, torch):
+    """Tail-area tallies equal the oracle's except for draws whose oracle
+    summary lies within the summary bar of the observed value."""
     spec = W.garch_spec()
-    obs = observed()["garch_L2000"]["summaries"]
+    obs = np.array(observed()["garch_L2000"]["summaries"])
     n = 3000
     counts = P.pps_summary_tally(spec, P.make_sampling(n, 0, 1), obs)
     ref = oracle.summary_tally(spec, 1, 0, n, obs)
-    print("GARCH tallies", counts, ref)
-    assert np.abs(counts.astype(np.int64) - ref.astype(np.int64)).max() <= 2
+    summ = oracle.simulate(spec, 1, 0, n)["summ"]
+    near = (np.abs(summ - obs[None, :]) <= GARCH_TOL * garch_scales(spec, 1, range(n))).sum(axis=0)
+    diff = np.abs(counts.astype(np.int64) - ref.astype(np.int64))
+    print("GARCH tallies", counts, ref, "near ties", near)
+    assert np.all(diff <= near), (diff, near)
 
 
 def test_sharding_invariance(P, torch):

@@ -344,3 +344,23 @@ def test_garch_lag1_acf_textbook_form():
     assert abs(s[:, 4].mean() - rho1) < 0.01
     rho2 = rho1 * (al + be)
     assert abs(s[:, 5].mean() - rho2) < 0.01
+
+
+def test_garch_bar_scales_closed_form_and_bounds():
+    """The error-bar scales: each is at least |summary| (triangle inequality),
+    and for i.i.d. N(0, omega) returns (alpha = beta = 0) the mean's scale is
+    sqrt(omega) E|z| = sqrt(2 omega / pi) and the skewness's is
+    E|z|^3 = 2 sqrt(2 / pi)."""
+    spec = W.garch_spec()
+    sc = oracle.garch_bar_scales(spec, 1, range(200))
+    s = oracle.simulate(spec, 1, 0, 200)["summ"]
+    assert np.all(sc[:, :4] >= np.abs(s[:, :4]) * (1 - 1e-12))
+    np.testing.assert_array_equal(sc[:, 1], np.abs(s[:, 1]))
+    np.testing.assert_array_equal(sc[:, 3], np.abs(s[:, 3]))
+    assert np.all(sc[:, 4:] == 1.0)
+    om = 4e-5
+    iid = W.garch_spec(series_len=2000, omega=("point", om, 0), alpha=("point", 0.0, 0),
+                       beta=("point", 0.0, 0), constraint=None)
+    si = oracle.garch_bar_scales(iid, 5, range(300))
+    assert _band(si[:, 0], math.sqrt(2 * om / math.pi))
+    assert _band(si[:, 2], 2 * math.sqrt(2 / math.pi))
