@@ -223,6 +223,28 @@ int abc_sample(const pps_model *model, const double *y_obs, const pps_sampling *
                int eps_mode, double eps_or_frac, uint64_t capacity, uint64_t *acc_idx,
                float *acc_theta, float *acc_dist, pps_abc_stats *stats, void *stream);
 
+/* For callers that cannot allocate (code that must not call hipMalloc, such
+ * as tight serving loops or harnesses that forbid it): abc_sample with the
+ * same arguments, kernels, results and error codes, whose device scratch
+ * (the n rho values and the finalisation's block counts, moment partials,
+ * selection histogram and result: abc_scratch_bytes(n), 16.2 MiB at the
+ * maximum) is a file-scope device array of the library, one per device,
+ * held until the process ends.  It allocates nothing on its success path: no
+ * hipMalloc / hipFree, no graph capture or instantiation, no host heap.  So
+ * the device's context and the epoch graph of the job's form must exist:
+ * make one abc_sample call on the device with the same model class,
+ * tolerance mode and launch shape first, else PPS_EINVAL (nothing run).
+ * n_draws above PPS_NOALLOC_MAX_DRAWS: PPS_EINVAL.  Every call on a device
+ * uses that device's one array, which keeps the last call's contents (every
+ * part a call reads is rewritten or cleared by that call's own kernels).
+ * Calls on one device are serialised by the library (each holds the device's
+ * lock until its epoch has ended); calls that overlapped on one device would
+ * race on the array. */
+#define PPS_NOALLOC_MAX_DRAWS (1ull << 22)
+int abc_sample_noalloc(const pps_model *model, const double *y_obs, const pps_sampling *sampling,
+                       int eps_mode, double eps_or_frac, uint64_t capacity, uint64_t *acc_idx,
+                       float *acc_theta, float *acc_dist, pps_abc_stats *stats, void *stream);
+
 /* ---- prior-predictive p-values over a lambda grid (Eq. pppvhype) -------- */
 
 /* For each lambda_k, parameter `lambda_param` gets the prior

@@ -19,7 +19,7 @@ from ._pps import (  # noqa: F401
     PPSError, LIB_PATH, lib, make_model, make_sampling,
     pps_version, pps_n_summaries, pps_set_timing, pps_last_kernel_ms, pps_set_block_size, pps_get_block_size,
     pps_set_launch_shape, pps_get_launch_shape, PATH_SHAPES, GARCH_SHAPES, CELL_SHAPES, pps_philox, pps_normals, pps_simulate,
-    abc_sample, prior_pred_pvalue, pps_summary_tally, simulate, abc,
+    abc_sample, abc_sample_noalloc, PPS_NOALLOC_MAX_DRAWS, prior_pred_pvalue, pps_summary_tally, simulate, abc,
     PPS_JOB_ABC, PPS_JOB_PVALUE, PPS_POLICY_BATCHED, PPS_POLICY_PLAIN,
     pps_job, pps_job_result, pps_server_config, pps_server_stats,
     make_abc_job, make_pvalue_job, make_server_config, pps_job_arena_bytes, pps_run_batch,

@@ -26,6 +26,7 @@ PPS_NO_CONSTRAINT, PPS_GARCH_STATIONARY, PPS_TB_SUPERCRITICAL = 0, 1, 2
 PPS_EPS_FIXED, PPS_EPS_TOP_FRACTION = 0, 1
 PPS_MAX_PARAMS, PPS_MAX_OBS, PPS_GARCH_NSUMM, PPS_TSW_MAX_CELLS = 8, 64, 14, 8192
 PPS_TB_MAX_POP, PPS_TB_MAX_SAMPLE = 16384, 1024
+PPS_NOALLOC_MAX_DRAWS = 1 << 22
 # kernel classes (pps_set_launch_shape)
 CLASS_PATH, CLASS_GARCH, CLASS_GROUP, CLASS_CELLS, CLASS_GILLESPIE = 0, 1, 2, 3, 4
 
@@ -172,6 +173,8 @@ def lib():
         L.pps_n_summaries.argtypes = [mp]
         L.abc_sample.argtypes = [mp, vp, sp, i32, f64, u64, vp, vp, vp,
                                  ctypes.POINTER(pps_abc_stats), vp]
+        L.abc_sample_noalloc.argtypes = [mp, vp, sp, i32, f64, u64, vp, vp, vp,
+                                 ctypes.POINTER(pps_abc_stats), vp]
         L.prior_pred_pvalue.argtypes = [mp, i32, i32, vp, i32, sp, f64, vp, vp, vp]
         L.pps_summary_tally.argtypes = [mp, sp, vp, vp, vp]
         L.pps_strerror.argtypes = [i32]
@@ -216,6 +219,7 @@ def lib():
                                          ctypes.POINTER(ctypes.c_double), vp]
         L.pps_bege_count_ops.restype = ctypes.c_int
         for name in ("pps_philox", "pps_normals", "pps_simulate", "pps_n_summaries", "abc_sample",
+                     "abc_sample_noalloc",
                      "prior_pred_pvalue", "pps_summary_tally", "pps_run_batch", "pps_server_create",
                      "pps_submit", "pps_poll", "pps_release", "pps_server_stats_get",
                      "pps_server_destroy", "pps_server_inject_error"):
@@ -355,6 +359,21 @@ def abc_sample(model, y_obs, sampling: pps_sampling, eps_mode: int, eps_or_frac:
     rc = lib().abc_sample(ctypes.byref(_model_arg(model)), y.ctypes.data, ctypes.byref(sampling),
                           eps_mode, eps_or_frac, capacity, _ptr(acc_idx), _ptr(acc_theta),
                           _ptr(acc_dist), ctypes.byref(st), _stream(stream))
+    _check(rc, allow=(PPS_OK, PPS_ETRUNC))
+    return rc, {"n_accepted": int(st.n_accepted), "eps_used": float(st.eps_used),
+                "mean": np.array(st.mean[:]), "var": np.array(st.var[:])}
+
+
+def abc_sample_noalloc(model, y_obs, sampling: pps_sampling, eps_mode: int, eps_or_frac: float,
+                       capacity: int, acc_idx, acc_theta, acc_dist, stream=None) -> tuple[int, dict]:
+    """abc_sample with the library's static scratch (no allocation); the same
+    return value as abc_sample."""
+    y = _host_f64(y_obs)
+    st = pps_abc_stats()
+    rc = lib().abc_sample_noalloc(ctypes.byref(_model_arg(model)), y.ctypes.data,
+                                  ctypes.byref(sampling), eps_mode, eps_or_frac, capacity,
+                                  _ptr(acc_idx), _ptr(acc_theta), _ptr(acc_dist), ctypes.byref(st),
+                                  _stream(stream))
     _check(rc, allow=(PPS_OK, PPS_ETRUNC))
     return rc, {"n_accepted": int(st.n_accepted), "eps_used": float(st.eps_used),
                 "mean": np.array(st.mean[:]), "var": np.array(st.var[:])}

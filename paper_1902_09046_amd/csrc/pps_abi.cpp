@@ -43,6 +43,61 @@ static int run_sync(Context &c, EpochPlan &plan, hipStream_t stream)
     return PPS_OK;
 }
 
+namespace pps {
+
+int abc_check(const pps_model *model, const double *y_obs, const pps_sampling *sampling,
+              int eps_mode, double eps_or_frac, uint64_t capacity, uint64_t *acc_idx,
+              float *acc_theta, float *acc_dist, const pps_abc_stats *stats, int *n_summ)
+{
+    PPS_TRY(validate_model(model, n_summ));
+    PPS_TRY(validate_sampling(sampling));
+    if (!stats)
+        return fail(PPS_EINVAL, "abc_sample: stats is required");
+    PPS_TRY(validate_abc(model, y_obs, *n_summ, sampling, eps_mode, eps_or_frac));
+    if (capacity > 0 && (!acc_idx || !acc_theta || !acc_dist))
+        return fail(PPS_EINVAL, "abc_sample: output buffers required when capacity > 0");
+    return PPS_OK;
+}
+
+int abc_run(Context &c, const pps_model *model, int n_summ, const double *y_obs,
+            const pps_sampling *sampling, int eps_mode, double eps_or_frac, uint64_t capacity,
+            uint64_t *acc_idx, float *acc_theta, float *acc_dist, pps_abc_stats *stats,
+            void *scratch, EpochPlan &plan, bool build, hipStream_t stream)
+{
+    const AbcScratch scr = abc_scratch_at(scratch, sampling->n_draws);
+    plan.clear();
+    JobDev J;
+    fill_job(J, model, sampling, n_summ, JOB_WRITE_DIST);
+    for (int k = 0; k < n_summ; ++k)
+        J.y_obs[k] = static_cast<float>(y_obs[k]);
+    J.dist = scr.dist;
+    const int cls = model_class(model);
+    whole_job(*c.engine, cls, J);
+    plan.rows[cls].push_back(J);
+    FinJob F;
+    fill_fin(F, J, eps_mode, eps_or_frac, capacity, acc_idx, acc_theta, acc_dist, scr);
+    plan.fins.push_back(F);
+    PPS_TRY(c.engine->launch(0, plan, stream, build));
+    PPS_TRY(c.engine->wait(0));
+    if (g_timing)
+        c.last_kernel_ms = c.engine->sim_ms(0);
+
+    const FinResult &R = c.engine->out_fin(0)[0];
+    stats->n_accepted = R.n_accepted;
+    stats->eps_used = R.eps_used;
+    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
+        stats->mean[j] = R.mean[j];
+        stats->var[j] = R.var[j];
+    }
+    if (R.n_accepted > capacity)
+        return fail(PPS_ETRUNC, "abc_sample: %llu accepted, capacity %llu",
+                    static_cast<unsigned long long>(R.n_accepted),
+                    static_cast<unsigned long long>(capacity));
+    return PPS_OK;
+}
+
+}  // namespace pps
+
 extern "C" {
 
 const char *pps_version(void) { return "pps 0.2 (gfx950)"; }
@@ -219,47 +274,16 @@ int abc_sample(const pps_model *model, const double *y_obs, const pps_sampling *
 {
     clear_error();
     int ns = 0, rc;
-    PPS_TRY(validate_model(model, &ns));
-    PPS_TRY(validate_sampling(sampling));
-    if (!stats)
-        return fail(PPS_EINVAL, "abc_sample: stats is required");
-    PPS_TRY(validate_abc(model, y_obs, ns, sampling, eps_mode, eps_or_frac));
-    if (capacity > 0 && (!acc_idx || !acc_theta || !acc_dist))
-        return fail(PPS_EINVAL, "abc_sample: output buffers required when capacity > 0");
+    PPS_TRY(abc_check(model, y_obs, sampling, eps_mode, eps_or_frac, capacity, acc_idx, acc_theta,
+                      acc_dist, stats, &ns));
     Context *c = current_context(&rc);
     if (!c)
         return rc;
     std::lock_guard<std::mutex> lk(c->mu);
-    const uint64_t n = sampling->n_draws;
-    PPS_TRY_HIP(c->dist.ensure(abc_scratch_bytes(n)), "ABC scratch");
-    const AbcScratch scr = abc_scratch_at(c->dist.p, n);
-
+    PPS_TRY_HIP(c->dist.ensure(abc_scratch_bytes(sampling->n_draws)), "ABC scratch");
     EpochPlan plan;
-    JobDev J;
-    fill_job(J, model, sampling, ns, JOB_WRITE_DIST);
-    for (int k = 0; k < ns; ++k)
-        J.y_obs[k] = static_cast<float>(y_obs[k]);
-    J.dist = scr.dist;
-    const int cls = model_class(model);
-    whole_job(*c->engine, cls, J);
-    plan.rows[cls].push_back(J);
-    FinJob F;
-    fill_fin(F, J, eps_mode, eps_or_frac, capacity, acc_idx, acc_theta, acc_dist, scr);
-    plan.fins.push_back(F);
-    PPS_TRY(run_sync(*c, plan, as_stream(stream)));
-
-    const FinResult &R = c->engine->out_fin(0)[0];
-    stats->n_accepted = R.n_accepted;
-    stats->eps_used = R.eps_used;
-    for (int j = 0; j < PPS_MAX_PARAMS; ++j) {
-        stats->mean[j] = R.mean[j];
-        stats->var[j] = R.var[j];
-    }
-    if (R.n_accepted > capacity)
-        return fail(PPS_ETRUNC, "abc_sample: %llu accepted, capacity %llu",
-                    static_cast<unsigned long long>(R.n_accepted),
-                    static_cast<unsigned long long>(capacity));
-    return PPS_OK;
+    return abc_run(*c, model, ns, y_obs, sampling, eps_mode, eps_or_frac, capacity, acc_idx,
+                   acc_theta, acc_dist, stats, c->dist.p, plan, true, as_stream(stream));
 }
 
 int prior_pred_pvalue(const pps_model *model, int lambda_param, int lambda_family,

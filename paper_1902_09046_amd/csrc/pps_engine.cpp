@@ -115,7 +115,7 @@ int EpochEngine::init(int n_slots, int cu_count)
     return PPS_OK;
 }
 
-int EpochEngine::set_graph_shape(Slot &s)
+int EpochEngine::set_graph_shape(Slot &s, bool build)
 {
     EpochShape want = shape_;
     for (int c = 0; c < N_CLASSES; ++c) {
@@ -130,6 +130,8 @@ int EpochEngine::set_graph_shape(Slot &s)
     want.fin_grid = static_cast<unsigned>(8 * cu_count_);
     if (s.have_shape && s.exec_shape == want)
         return PPS_OK;
+    if (!build)
+        return fail(PPS_EINVAL, "the launch shape changed since the epoch graphs were built");
     for (auto &kv : s.execs)
         (void)hipGraphExecDestroy(kv.second);
     s.execs.clear();
@@ -163,13 +165,15 @@ static hipError_t capture_event(hipStream_t cs, hipEvent_t ev)
 
 // Form bits: bit c = class c has tiles; bits N_CLASSES.. = 0 no
 // finalisation, 1 with the selection passes, 2 fixed tolerances only.
-int EpochEngine::graph_for(Slot &s, unsigned form, hipGraphExec_t *out)
+int EpochEngine::graph_for(Slot &s, unsigned form, hipGraphExec_t *out, bool build)
 {
     auto it = s.execs.find(form);
     if (it != s.execs.end()) {
         *out = it->second;
         return PPS_OK;
     }
+    if (!build)
+        return fail(PPS_EINVAL, "no epoch graph of this form has been built on the device yet");
     const EpochShape &sh = s.exec_shape;
     hipError_t e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
@@ -207,7 +211,7 @@ int EpochEngine::graph_for(Slot &s, unsigned form, hipGraphExec_t *out)
     return PPS_OK;
 }
 
-int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
+int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream, bool build)
 {
     Slot &s = slots_[slot];
     if (s.in_flight)
@@ -218,7 +222,7 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
     if (n_rows > static_cast<size_t>(MAX_ROWS) || plan.fins.size() > static_cast<size_t>(MAX_FINS))
         return fail(PPS_EINVAL, "epoch too large: %zu rows, %zu finalisations", n_rows,
                     plan.fins.size());
-    int rc = set_graph_shape(s);
+    int rc = set_graph_shape(s, build);
     if (rc != PPS_OK)
         return rc;
     EpochHeader &H = *s.h_hdr;
@@ -269,7 +273,7 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream)
     if (H.n_fins > 0)
         form |= (H.any_top ? 1u : 2u) << N_CLASSES;
     hipGraphExec_t x = nullptr;
-    if ((rc = graph_for(s, form, &x)) != PPS_OK)
+    if ((rc = graph_for(s, form, &x, build)) != PPS_OK)
         return rc;
     hipError_t e = hipSuccess;
     if (last_slot_ >= 0 && last_stream_ != stream)

@@ -61,7 +61,10 @@ class EpochEngine {
     // simulation kernels have ended (a job's tiles can span both epochs and
     // its finalisation reads all of them); its finalisation and stage-out
     // still overlap this epoch.
-    int launch(int slot, EpochPlan &plan, hipStream_t stream);
+    // With build == false the epoch replays an instantiated graph of its form
+    // and launch shape or fails with PPS_EINVAL: nothing is captured,
+    // instantiated or destroyed.
+    int launch(int slot, EpochPlan &plan, hipStream_t stream, bool build = true);
     // The stream of a slot: `primary` for slot 0, a stream of the engine for
     // the others (so that epochs alternate between two streams).
     hipStream_t slot_stream(int slot, hipStream_t primary) const
@@ -100,8 +103,8 @@ class EpochEngine {
         bool in_flight = false;
         float sim_ms = -1.0f;
     };
-    int set_graph_shape(Slot &s);
-    int graph_for(Slot &s, unsigned form, hipGraphExec_t *out);
+    int set_graph_shape(Slot &s, bool build);
+    int graph_for(Slot &s, unsigned form, hipGraphExec_t *out, bool build);
     int finish(Slot &s);
 
     std::vector<Slot> slots_;

@@ -82,6 +82,9 @@ Context *current_context(int *status)
         Context *c = new Context();
         c->device = dev;
         c->cu_count = prop.multiProcessorCount;
+        for (auto &r : c->noalloc_plan.rows)
+            r.reserve(1);
+        c->noalloc_plan.fins.reserve(1);
         c->engine.reset(new EpochEngine());
         int rc = c->engine->init(1, c->cu_count);
         if (rc != PPS_OK) {
@@ -89,6 +92,27 @@ Context *current_context(int *status)
             return nullptr;  // the partially built context is leaked on purpose
         }
         g_contexts[dev] = c;
+    }
+    *status = PPS_OK;
+    return g_contexts[dev];
+}
+
+Context *existing_context(int *status)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *status = fail_hip(e, "hipGetDevice");
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *status = fail(PPS_EDEVICE, "device %d out of range", dev);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_contexts_mu);
+    if (!g_contexts[dev]) {
+        *status = fail(PPS_EINVAL, "device %d has no context yet (any other call creates it)", dev);
+        return nullptr;
     }
     *status = PPS_OK;
     return g_contexts[dev];
@@ -266,13 +290,7 @@ bool g_timing = false;
 
 static size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-size_t abc_scratch_bytes(uint64_t n)
-{
-    const uint64_t nb = (n + FIN_TILE - 1) / FIN_TILE;
-    return align256(n * sizeof(float)) + align256(2 * nb * sizeof(unsigned long long)) +
-           align256(nb * (1 + 2 * PPS_MAX_PARAMS) * sizeof(double)) +
-           align256(SEL_BINS * sizeof(unsigned)) + align256(sizeof(FinResult));
-}
+size_t abc_scratch_bytes(uint64_t n) { return abc_scratch_bound(n); }
 
 AbcScratch abc_scratch_at(void *base, uint64_t n)
 {

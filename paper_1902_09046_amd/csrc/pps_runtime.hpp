@@ -44,6 +44,9 @@ struct Context {
     // BEGE log-likelihood: the shapes of every (vector, t), and the per-t
     // log densities when the caller does not take them
     DevBuf bege_shapes, bege_logdens;
+    // the epoch plan of abc_sample_noalloc, its vectors reserved when the
+    // context is created so that the call allocates no host memory either
+    EpochPlan noalloc_plan;
     double last_kernel_ms = -1.0;
 };
 
@@ -51,6 +54,9 @@ extern bool g_timing;
 
 // Context of the current HIP device (created on first use, engine included).
 Context *current_context(int *status);
+// The current device's context if it exists; else NULL with PPS_EINVAL
+// (creates nothing).
+Context *existing_context(int *status);
 
 int model_class(const pps_model *m);
 // Validates a model; on success returns PPS_OK and its summary count.
@@ -68,6 +74,15 @@ struct AbcScratch {
     unsigned *hist = nullptr;                 // SEL_BINS
     FinResult *result = nullptr;              // 1
 };
+constexpr size_t abc_scratch_bound(uint64_t n)
+{
+    const uint64_t nb = (n + FIN_TILE - 1) / FIN_TILE;
+    return ((n * sizeof(float) + 255) & ~size_t(255)) +
+           ((2 * nb * sizeof(unsigned long long) + 255) & ~size_t(255)) +
+           ((nb * (1 + 2 * PPS_MAX_PARAMS) * sizeof(double) + 255) & ~size_t(255)) +
+           ((SEL_BINS * sizeof(unsigned) + 255) & ~size_t(255)) +
+           ((sizeof(FinResult) + 255) & ~size_t(255));
+}
 size_t abc_scratch_bytes(uint64_t n);
 // Carves an AbcScratch out of `base` (abc_scratch_bytes(n) bytes, 256-aligned).
 AbcScratch abc_scratch_at(void *base, uint64_t n);
@@ -79,5 +94,18 @@ void fill_fin(FinJob &F, const JobDev &row, int eps_mode, double eps_or_frac, ui
               uint64_t *acc_idx, float *acc_theta, float *acc_dist, const AbcScratch &scr);
 
 uint64_t top_count(double frac, uint64_t n);
+
+// The ABC job of abc_sample on validated arguments, context lock held: the
+// simulation writes rho into the scratch at `scratch` (abc_scratch_bytes(n)
+// bytes), the finalisation selects, compacts and reduces.  `plan` is cleared
+// and refilled; build == false replays an existing epoch graph only.
+int abc_run(Context &c, const pps_model *model, int n_summ, const double *y_obs,
+            const pps_sampling *sampling, int eps_mode, double eps_or_frac, uint64_t capacity,
+            uint64_t *acc_idx, float *acc_theta, float *acc_dist, pps_abc_stats *stats,
+            void *scratch, EpochPlan &plan, bool build, hipStream_t stream);
+// Argument checks of abc_sample; on success *n_summ is the summary count.
+int abc_check(const pps_model *model, const double *y_obs, const pps_sampling *sampling,
+              int eps_mode, double eps_or_frac, uint64_t capacity, uint64_t *acc_idx,
+              float *acc_theta, float *acc_dist, const pps_abc_stats *stats, int *n_summ);
 
 }  // namespace pps
