@@ -54,17 +54,28 @@ def ops_per_draw(steps: int, n_obs: int) -> float:
     return steps * per_step + n_obs * OPS_OBS + OPS_PRIOR
 
 
-# A lambda group (p-value grids): 8 lambda values of one draw per lane share
-# the normal; each member adds its EM update, its Kahan mean (4 per
-# observation) and its lambda'd prior value (one Philox call + FP64 transform).
-GROUP_LPL = 8
-OPS_PRIOR_MEMBER = 160
+# A lambda group (p-value grids): 32 lambda values of one draw per lane share
+# the normals; each member adds its EM update and its Kahan mean (4 per
+# observation).  The lambda'd parameter's variate is drawn once per draw (one
+# Philox call + the FP64 Box-Muller, 72); each member applies its own prior to
+# it and forms its EM constants (a + b z, exp, two products / quotients, two
+# roundings: 7).
+GROUP_LPL = 32
+OPS_PRIOR_VARIATES = 72
+OPS_PRIOR_MEMBER = 7
 
 
-def ops_per_group_draw(steps: int, n_obs: int) -> float:
-    per_step = (OPS_PHILOX + 2 * OPS_BM_PAIR) / 4.0 + GROUP_LPL * OPS_EM
-    return (steps * per_step + n_obs * GROUP_LPL * 4 + OPS_PRIOR
-            + (GROUP_LPL - 1) * OPS_PRIOR_MEMBER)
+def ops_per_group_draw(steps: int, n_obs: int, lpl: int = GROUP_LPL) -> float:
+    """Executed lane-operations of one draw of one lambda group."""
+    per_step = (OPS_PHILOX + 2 * OPS_BM_PAIR) / 4.0 + lpl * OPS_EM
+    return (steps * per_step + n_obs * lpl * 4 + OPS_PRIOR + OPS_PRIOR_VARIATES
+            + lpl * OPS_PRIOR_MEMBER)
+
+
+def ops_per_grid_draw_one_normal_set(steps: int, n_obs: int, n_lambda: int) -> float:
+    """Lane-operations of one draw under a whole grid with its normals counted
+    once (the work the method needs under common random numbers)."""
+    return ops_per_group_draw(steps, n_obs, n_lambda)
 
 
 # GARCH(1,1) step: the normal (21) + sqrt, 2 multiplies, 2 fma for the
@@ -339,10 +350,12 @@ def main():
         wall, kms = time_calls(P, torch, lambda: P.prior_pred_pvalue(
             pspec, 0, P.PPS_LOGNORMAL, lam, P.make_sampling(pn, 0, W.SAMPLING_SEED), t_obs), 1, 3)
         pops = ops_per_group_draw(steps_em, n_obs) * pn * (64 // GROUP_LPL)
+        pops1 = ops_per_grid_draw_one_normal_set(steps_em, n_obs, 64) * pn
         workloads["pvalue_logistic_64lambda_n1e6"] = {
             "sims_per_s": round(64 * pn / wall, 1), "ms_per_batch": round(wall * 1e3, 3),
             "kernel_ms": round(kms, 3), "valu_frac": round(pops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
-            "kernel": "k_simulate_group<256,8>",
+            "valu_frac_one_normal_set": round(pops1 / (kms * 1e-3) / VALU_PEAK_OPS, 4),
+            "kernel": "k_simulate_group<256,%d>" % GROUP_LPL,
             "traffic": measured_traffic("k_simulate_group_pvalue_64x1e6")}
         if args.cpu_sample > 0:
             # the oracle on the first 1e4 draws of every lambda, timed, and the

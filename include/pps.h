@@ -253,8 +253,9 @@ int abc_sample_noalloc(const pps_model *model, const double *y_obs, const pps_sa
  * numbers (common random numbers).  count_ge[k] = #{i : T_i >= t_obs} with
  * T_i the mean of draw i's observations (compared in FP64) and
  * pvalue[k] = count_ge[k] / N.  All lambda values run in one launch; for the
- * logistic SDE, lambda values are simulated in groups of 8 per lane from one
- * random stream (the common random numbers make their normals identical).
+ * logistic SDE, lambda values are simulated in groups of 32 per lane from one
+ * random stream (the common random numbers make their normals and the
+ * lambda'd parameter's variate identical); the rest one row per lambda.
  * lambda, count_ge, pvalue: host arrays of n_lambda (1..4096).  For the
  * toggle switch T_i is the mean of its quantile summaries.
  * Not for GARCH (use pps_summary_tally). */
@@ -519,7 +520,7 @@ int pps_get_block_size(int model_class);
 /* Full launch shape of a kernel class: workgroup size, draws simulated
  * interleaved per lane (1 or 2) and Philox blocks generated per loop trip
  * (1 or 2; logistic SDE).  Classes: 0 logistic SDE / normal-mean, 1 GARCH,
- * 2 lambda groups of a p-value grid (8 lambda values of one draw per lane,
+ * 2 lambda groups of a p-value grid (32 lambda values of one draw per lane,
  * sharing its random numbers), 3 toggle switch (one draw per workgroup, its
  * cells across the lanes).  Supported shapes: class 0 block {64, 128, 256}
  * x draws_per_lane {1, 2} x unroll {1, 2}; classes 1 and 2 block

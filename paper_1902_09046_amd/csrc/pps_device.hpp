@@ -144,17 +144,38 @@ __device__ __forceinline__ void cell_normals4(StreamKey key, uint64_t draw, uint
 // Kept out of line: the FP64 log / cospi / exp would otherwise set the
 // register budget of the whole simulation loop (117 vs 58 VGPRs).
 // ---------------------------------------------------------------------------
+// The value of a prior from its attempt's variates: u = uniform of word 0,
+// z = the first FP64 Box-Muller normal of words (0, 1).
+__device__ __forceinline__ double prior_transform(const PriorDev &p, double u, double z)
+{
+    if (p.family == PPS_POINT)
+        return p.a;
+    if (p.family == PPS_UNIFORM)
+        return __dadd_rn(p.a, __dmul_rn(__dsub_rn(p.b, p.a), u));
+    const double v = __dadd_rn(p.a, __dmul_rn(p.b, z));
+    return p.family == PPS_LOGNORMAL ? exp(v) : v;
+}
+
 __device__ __attribute__((noinline)) double prior_value(const PriorDev &p, StreamKey key, uint64_t draw,
                                               int j, int attempt)
 {
     if (p.family == PPS_POINT)
         return p.a;
     const Words4 w = stream_block(key, draw, static_cast<uint32_t>(8 * attempt + j), PURPOSE_PRIOR);
+    const double u = uniform_f64(w.x);
     if (p.family == PPS_UNIFORM)
-        return __dadd_rn(p.a, __dmul_rn(__dsub_rn(p.b, p.a), uniform_f64(w.x)));
-    const double z = box_muller_f64_first(w.x, w.y);
-    const double v = __dadd_rn(p.a, __dmul_rn(p.b, z));
-    return p.family == PPS_LOGNORMAL ? exp(v) : v;
+        return prior_transform(p, u, 0.0);
+    return prior_transform(p, u, box_muller_f64_first(w.x, w.y));
+}
+
+// The variates u and z of parameter j, attempt 0 (the lambda-group kernel
+// applies every member's prior to one set).
+__device__ __attribute__((noinline)) void prior_variates(StreamKey key, uint64_t draw, int j,
+                                                         double &u, double &z)
+{
+    const Words4 w = stream_block(key, draw, static_cast<uint32_t>(j), PURPOSE_PRIOR);
+    u = uniform_f64(w.x);
+    z = box_muller_f64_first(w.x, w.y);
 }
 
 constexpr int MAX_PRIOR_ATTEMPTS = 32;

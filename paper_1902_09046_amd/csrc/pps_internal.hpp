@@ -35,7 +35,7 @@ enum : int {
     CLASS_GILLESPIE = 4,
     N_CLASSES = 5
 };
-constexpr int GROUP_LPL = 8;
+constexpr int GROUP_LPL = 32;
 
 // Prior parameters held by the one-lane-per-draw kernels (logistic SDE,
 // normal-mean, GARCH: at most 3 used); the cell kernel holds PPS_MAX_PARAMS.

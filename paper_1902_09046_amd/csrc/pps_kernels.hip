@@ -467,10 +467,73 @@ __global__ __launch_bounds__(BLOCK) void k_simulate(const EpochHeader *__restric
 // Lambda-group kernel (p-value grids, logistic SDE).  One lane simulates draw
 // i under the LPL lambda values of its group: the path normals and every
 // prior parameter except `lambda_param` are shared (common random numbers),
-// each member keeps its own state, EM constants and compensated mean, and
-// tallies its own statistic.  The member arithmetic is the same sequence of
+// and so is the variate of `lambda_param` itself, to which each member
+// applies its own prior; each member keeps its own state, the EM constants
+// that depend on the varied parameter, and its compensated mean, and tallies
+// its own statistic.  The member arithmetic is the same sequence of
 // operations as in k_simulate, so counts equal those of one row per lambda.
 // ===========================================================================
+
+// The members' Euler-Maruyama runs of one draw; VARY is the varied
+// parameter (0: a and b depend on it, 1: b, 2: c), the other constants are
+// held once.
+template <int LPL, int VARY>
+__device__ __forceinline__ void group_members(const JobDev *__restrict__ J, StreamKey key,
+                                              uint64_t draw, const double *theta, double u,
+                                              double zv, Kahan *sum)
+{
+    constexpr int NA = VARY == 0 ? LPL : 1;
+    constexpr int NB = VARY <= 1 ? LPL : 1;
+    constexpr int NC = VARY == 2 ? LPL : 1;
+    const double dt = J->dt;
+    const double sdt = sqrt(dt);
+    float a[NA], b[NB], c[NC], x[LPL];
+#pragma unroll
+    for (int k = 0; k < LPL; ++k) {
+        double th[3] = {theta[0], theta[1], theta[2]};
+        th[VARY] = prior_transform(J[k].prior[VARY], u, zv);
+        if (k < NA)
+            a[k] = static_cast<float>(th[0] * dt);
+        if (k < NB)
+            b[k] = static_cast<float>(th[0] * dt / th[1]);
+        if (k < NC)
+            c[k] = static_cast<float>(th[2] * sdt);
+        x[k] = static_cast<float>(J->x0);
+    }
+    const int steps = J->steps;
+    const int stride = J->obs_stride;
+    const int nblk = (steps + 3) >> 2;
+    int next_obs = stride;
+    // the normals of block blk + 1 are generated while the members advance
+    // through block blk: the two are independent, so the scheduler can fill
+    // the Philox / Box-Muller latencies with member updates
+    float zn[4];
+    path_normals4(key, draw, 0u, zn[0], zn[1], zn[2], zn[3]);
+    for (int blk = 0; blk < nblk; ++blk) {
+        const float z[4] = {zn[0], zn[1], zn[2], zn[3]};
+        if (blk + 1 < nblk)
+            path_normals4(key, draw, static_cast<uint32_t>(blk + 1), zn[0], zn[1], zn[2], zn[3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int step = 4 * blk + j + 1;
+            if (step > steps)
+                break;
+#pragma unroll
+            for (int k = 0; k < LPL; ++k) {
+                float g = __builtin_fmaf(-b[k < NB ? k : 0], x[k], a[k < NA ? k : 0]);
+                g = __builtin_fmaf(c[k < NC ? k : 0], z[j], g);
+                x[k] = __builtin_fmaxf(__builtin_fmaf(x[k], g, x[k]), 0.0f);
+            }
+            if (step == next_obs) {
+#pragma unroll
+                for (int k = 0; k < LPL; ++k)
+                    sum[k].add(x[k]);
+                next_obs += stride;
+            }
+        }
+    }
+}
+
 template <int BLOCK, int LPL>
 __global__ __launch_bounds__(BLOCK) void k_simulate_group(const EpochHeader *__restrict__ hdr,
                                                           const JobDev *__restrict__ rows,
@@ -514,49 +577,14 @@ __global__ __launch_bounds__(BLOCK) void k_simulate_group(const EpochHeader *__r
             double theta[SDE_MAX_PARAMS] = {0.0, 0.0, 0.0, 0.0};
             prior_draw<SDE_MAX_PARAMS>(J->prior, J->n_params, J->constraint, key, draw, theta);
             const int lp = J->lambda_param;
-            const double dt = J->dt;
-            float a[LPL], b[LPL], c[LPL], x[LPL];
-            const double sdt = sqrt(dt);
-#pragma unroll
-            for (int k = 0; k < LPL; ++k) {
-                double th[3] = {theta[0], theta[1], theta[2]};
-                if (k > 0) {
-                    const double v = prior_value(J[k].prior[lp], key, draw, lp, 0);
-                    th[0] = lp == 0 ? v : th[0];
-                    th[1] = lp == 1 ? v : th[1];
-                    th[2] = lp == 2 ? v : th[2];
-                }
-                a[k] = static_cast<float>(th[0] * dt);
-                b[k] = static_cast<float>(th[0] * dt / th[1]);
-                c[k] = static_cast<float>(th[2] * sdt);
-                x[k] = static_cast<float>(J->x0);
-            }
-            const int steps = J->steps;
-            const int stride = J->obs_stride;
-            const int nblk = (steps + 3) >> 2;
-            int next_obs = stride;
-            for (int blk = 0; blk < nblk; ++blk) {
-                float z[4];
-                path_normals4(key, draw, static_cast<uint32_t>(blk), z[0], z[1], z[2], z[3]);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int step = 4 * blk + j + 1;
-                    if (step > steps)
-                        break;
-#pragma unroll
-                    for (int k = 0; k < LPL; ++k) {
-                        float g = __builtin_fmaf(-b[k], x[k], a[k]);
-                        g = __builtin_fmaf(c[k], z[j], g);
-                        x[k] = __builtin_fmaxf(__builtin_fmaf(x[k], g, x[k]), 0.0f);
-                    }
-                    if (step == next_obs) {
-#pragma unroll
-                        for (int k = 0; k < LPL; ++k)
-                            sum[k].add(x[k]);
-                        next_obs += stride;
-                    }
-                }
-            }
+            double u = 0.0, zv = 0.0;
+            prior_variates(key, draw, lp, u, zv);
+            if (lp == 0)
+                group_members<LPL, 0>(J, key, draw, theta, u, zv, sum);
+            else if (lp == 1)
+                group_members<LPL, 1>(J, key, draw, theta, u, zv, sum);
+            else
+                group_members<LPL, 2>(J, key, draw, theta, u, zv, sum);
         }
         const double inv = 1.0 / static_cast<double>(J->n_summ);
 #pragma unroll

@@ -27,9 +27,12 @@ def test_operation_counts_of_the_roofline():
     # per EM step: a quarter Philox call (60), half a Box-Muller pair per
     # normal (2 x 12 per call of four normals), the EM update (4)
     assert bench.ops_per_draw(1000, 20) == 1000 * ((60 + 24) / 4 + 4) + 20 * 9 + 250 == 25430
-    # a draw-group of 8 lambda values: one normal per step, 8 EM updates,
-    # 8 Kahan means per observation, 7 extra lambda'd prior values
-    assert bench.ops_per_group_draw(1000, 20) == 1000 * (21 + 32) + 20 * 32 + 250 + 7 * 160 == 55010
+    # a draw-group of 32 lambda values: one normal per step, 32 EM updates,
+    # 32 Kahan means per observation, the shared theta, the lambda'd
+    # parameter's variate once, 32 member transforms
+    assert bench.ops_per_group_draw(1000, 20) == 1000 * (21 + 128) + 20 * 128 + 250 + 72 + 32 * 7 == 152106
+    # the 64-lambda grid with its normals counted once per draw
+    assert bench.ops_per_grid_draw_one_normal_set(1000, 20, 64) == 1000 * (21 + 256) + 20 * 256 + 250 + 72 + 64 * 7
     # toggle switch: 62 per cell-step, 15 per cell, 600 per draw
     assert bench.toggle_ops_per_draw(8000, 599) == 8000 * (599 * 62 + 15) + 600
     assert bench.VALU_PEAK_OPS == 256 * 128 * 2.4e9

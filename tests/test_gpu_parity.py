@@ -208,12 +208,12 @@ def test_pvalue_lambda_grid_parity(P, torch):
 
 
 @pytest.mark.parametrize("lp,family,lams", [
-    (0, "lognormal", list(W.lambda_grid(13))),
-    (1, "uniform", [60.0 + 7.0 * k for k in range(9)]),        # th2 ~ U(50, lambda)
-    (2, "uniform", [0.05 + 0.03 * k for k in range(16)]),      # th3 ~ U(0, lambda)
+    (0, "lognormal", list(W.lambda_grid(37))),                 # one group + 5 rows
+    (1, "uniform", [60.0 + 1.5 * k for k in range(33)]),       # th2 ~ U(50, lambda)
+    (2, "uniform", [0.05 + 0.006 * k for k in range(70)]),     # th3 ~ U(0, lambda), 2 groups + 6
 ])
 def test_pvalue_lambda_groups_equal_single_rows(P, torch, lp, family, lams):
-    """Grids run in groups of 8 lambda values per lane (shared random numbers);
+    """Grids run in groups of 32 lambda values per lane (shared random numbers);
     every count equals the one-lambda-per-row result, remainder rows included."""
     spec = W.pvalue_spec(steps=400)
     fam = {"lognormal": P.PPS_LOGNORMAL, "uniform": P.PPS_UNIFORM}[family]
