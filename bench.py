@@ -133,11 +133,32 @@ def measured_traffic(key: str):
     return e["bytes_per_launch"]
 
 
-def time_calls(P, torch, fn, warmup: int, reps: int):
-    """Wall time per call (host clock, synchronised) and mean kernel time."""
-    for _ in range(warmup):
+def measured_issue(key: str):
+    """VALU issue fraction of a kernel from the rocprofv3 counter runs under
+    profiles/ (wave64 VALU instructions x 2 SIMD cycles, FP64 arithmetic x 4,
+    over the SIMD cycles of the dispatch), while its sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(key)
+    if not e or "issue" not in e or \
+            e.get("kernel_source_sha256") != kernel_source_digest(e.get("sources", "simulate")):
+        return None
+    return e["issue"]["frac"]
+
+
+def time_calls(P, torch, fn, warmup: int, reps: int, warm_s: float = 0.25):
+    """Wall time per call (host clock, synchronised) and mean kernel time.
+    Warm-up: at least `warmup` calls and at least `warm_s` seconds of them, so
+    that the GPU clock has ramped up after the host-only oracle legs."""
+    t0 = time.perf_counter()
+    k = 0
+    while k < warmup or time.perf_counter() - t0 < warm_s:
         fn()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        k += 1
     t0 = time.perf_counter()
     ks = []
     for _ in range(reps):
@@ -314,13 +335,14 @@ def main():
     print(f"bench: warmup {args.warmup} x abc_sample N={n}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         P.abc_sample(model, y_obs, sampling, P.PPS_EPS_FIXED, eps, capacity, idx, th, dd)
-    kernel_ms = []
+    kernel_ms, fin_ms = [], []
     stats = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         rc, stats = P.abc_sample(model, y_obs, sampling, P.PPS_EPS_FIXED, eps, capacity, idx, th, dd)
         kernel_ms.append(P.pps_last_kernel_ms())
+        fin_ms.append(P.pps_last_finalize_ms())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -335,12 +357,67 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "TOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic("k_simulate_path_abc_n1e7"),
+                "valu_issue_frac_counters": measured_issue("k_simulate_path_abc_n1e7"),
                 "kernel": "k_simulate<block=%d,path,dpl=%d,unroll=%d>" % tuple(tune["best"]),
                 "kernel_ms": round(k_ms, 4),
                 "ops_per_draw": ops_per_draw(steps_em, n_obs)}
 
+    # The accept step of Alg. 1 on the same 1e7 distances: its HBM rate on
+    # algorithmic bytes (rho read once per pass, 4 B per draw; records
+    # written, idx 8 B + theta 4 B per parameter + rho 4 B), timed by HIP
+    # events around the finalisation inside the call's graph.  Fixed eps:
+    # count and write passes.  Closest fraction 0.1 %: three radix-select
+    # histogram passes first.
+    rec_bytes = 8 + 4 * 3 + 4
+    compaction = {}
+    fixed_ms = float(np.mean(fin_ms))
+    fixed_bytes = 2 * 4 * n + stats["n_accepted"] * rec_bytes
+    compaction["fixed_eps"] = {
+        "ms": round(fixed_ms, 4), "records": stats["n_accepted"], "passes_over_rho": 2,
+        "algorithmic_bytes": fixed_bytes,
+        "GB_per_s": round(fixed_bytes / (fixed_ms * 1e-3) / 1e9, 1),
+        "traffic": measured_traffic("abc_finalize_fixed_n1e7"),
+        "kernels": "k_compact_count, k_compact_scan, k_compact_write, k_moments_final"}
+    top_ms = []
+    for _ in range(1 + 3):
+        _, tstats = P.abc_sample(model, y_obs, sampling, P.PPS_EPS_TOP_FRACTION, 0.001, capacity,
+                                 idx, th, dd)
+        top_ms.append(P.pps_last_finalize_ms())
+    tms = float(np.mean(top_ms[1:]))
+    top_bytes = 5 * 4 * n + tstats["n_accepted"] * rec_bytes
+    compaction["top_fraction"] = {
+        "ms": round(tms, 4), "records": tstats["n_accepted"], "passes_over_rho": 5,
+        "algorithmic_bytes": top_bytes,
+        "GB_per_s": round(top_bytes / (tms * 1e-3) / 1e9, 1),
+        "traffic": measured_traffic("abc_finalize_top_n1e7"),
+        "kernels": "k_sel_hist x3, k_sel_pick x3, then the fixed-eps kernels"}
+    compaction["note"] = ("rho (40 MB) was just written by the simulation and is re-read "
+                          "from the last-level cache, so the rate can exceed HBM's 8 TB/s")
+
     workloads = {}
     if not args.only_main:
+        # Plain ABC rejection at the small size (N = 1e4, closest 1 %, k = 100):
+        # the GPU call, and the FP64 oracle on the same draws, timed on the
+        # host cores, with the accept sets compared.
+        n0 = 10_000
+        s0 = P.make_sampling(n0, 0, W.SAMPLING_SEED)
+        wall0, _ = time_calls(P, torch, lambda: P.abc_sample(
+            model, y_obs, s0, P.PPS_EPS_TOP_FRACTION, 0.01, capacity, idx, th, dd), 2, 5)
+        g0 = P.abc(spec, y_obs, W.SAMPLING_SEED, 0, n0, P.PPS_EPS_TOP_FRACTION, 0.01)
+        small = {"ms": round(wall0 * 1e3, 4), "sims_per_s": round(n0 / wall0, 1),
+                 "accepted": g0["n_accepted"]}
+        if args.cpu_sample > 0:
+            import oracle
+            c0 = time.perf_counter()
+            o0 = oracle.abc(spec, y_obs, W.SAMPLING_SEED, 0, n0, oracle.EPS_TOP_FRACTION, 0.01)
+            c1 = time.perf_counter()
+            sym = set(g0["idx"].cpu().numpy().tolist()) ^ set(o0["idx"].tolist())
+            small["oracle"] = {
+                "s": round(c1 - c0, 4), "sims_per_s": round(n0 / (c1 - c0), 1),
+                "cores": oracle.threads(), "sample": "the whole run (FP64)",
+                "accept_set_sym_diff": len(sym),
+                "eps_rel_diff": float(f"{abs(g0['eps_used'] - o0['eps_used']) / o0['eps_used']:.3g}")}
+        workloads["abc_logistic_n1e4_top1pct"] = small
         # 64-lambda p-value batch, 1e6 draws per lambda, one launch.
         t_obs = golden["logistic_S1000"]["t_obs"]
         pspec = W.pvalue_spec(steps=steps_em)
@@ -356,7 +433,8 @@ def main():
             "kernel_ms": round(kms, 3), "valu_frac": round(pops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
             "valu_frac_one_normal_set": round(pops1 / (kms * 1e-3) / VALU_PEAK_OPS, 4),
             "kernel": "k_simulate_group<256,%d>" % GROUP_LPL,
-            "traffic": measured_traffic("k_simulate_group_pvalue_64x1e6")}
+            "traffic": measured_traffic("k_simulate_group_pvalue_64x1e6"),
+            "valu_issue_frac_counters": measured_issue("k_simulate_group_pvalue_64x1e6")}
         if args.cpu_sample > 0:
             # the oracle on the first 1e4 draws of every lambda, timed, and the
             # device's counts on the same draws: equal for lambda <= 1; above,
@@ -389,7 +467,8 @@ def main():
             "sims_per_s": round(gn / wall, 1), "ms": round(wall * 1e3, 3), "kernel_ms": round(kms, 3),
             "valu_frac": round(gops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
             "kernel": "k_simulate<256,garch>",
-            "traffic": measured_traffic("k_simulate_garch_L2000_n1e6")}
+            "traffic": measured_traffic("k_simulate_garch_L2000_n1e6"),
+            "valu_issue_frac_counters": measured_issue("k_simulate_garch_L2000_n1e6")}
         if args.cpu_sample > 0:
             # the device's FP32 streaming summaries of the first 1e4 draws
             # against the oracle's FP64 two-pass ones, each error divided by
@@ -438,6 +517,7 @@ def main():
               "valu_frac": round(tops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
               "kernel": f"k_simulate_cells<{cell_block}>",
               "traffic": measured_traffic("k_simulate_cells_toggle_n8064"),
+              "valu_issue_frac_counters": measured_issue("k_simulate_cells_toggle_n8064"),
               "paper_context": {"table": "A.1", "seconds": 69.0, "cpu": "Xeon Gold 6140",
                                 "threads": 16, "code": "C, AVX512, FP64",
                                 "ratio_to_gpu": round(69.0 / wall, 1)}}
@@ -463,6 +543,7 @@ def main():
         ww = {"smc_runs_per_s": round(runs / wall, 1), "ms": round(wall * 1e3, 3),
               "kernel_ms": round(kms, 3), "smc_runs": runs, "kernel": "k_smc<512> (FP64)",
               "traffic": measured_traffic("k_smc_wip_K400_N400"),
+              "valu_issue_frac_counters": measured_issue("k_smc_wip_K400_N400"),
               "paper_context": {"table": "A.2", "seconds": 90.0, "cpu": "Xeon Gold 6140",
                                 "threads": 16, "code": "C, AVX512, FP64",
                                 "ratio_to_gpu": round(90.0 / wall, 1)}}
@@ -497,6 +578,7 @@ def main():
                            "unit": "TFLOP/s", "frac": round(bach / FP64_PEAK_TFLOPS, 4),
                            "ops_per_launch": bops,
                            "traffic": measured_traffic("k_bege_density_T1099_Np1024")},
+                           "valu_issue_frac_counters": measured_issue("k_bege_density_T1099_Np1024"),
               "paper_context": {"table": "A.3", "what": "whole SMC inference (N_p = 1024), "
                                 "not one likelihood batch", "seconds": 3115.0,
                                 "cpu": "Xeon E5-2680v3", "threads": 16, "code": "C, AVX2, FP64"}}
@@ -534,6 +616,7 @@ def main():
                "ms": round(wall * 1e3, 3), "kernel_ms": round(kms, 3), "events": events_tb,
                "complete_extinct_truncated": status_tb,
                "kernel": "k_simulate_tb<64> (one run per workgroup, counts in LDS)",
+               "valu_issue_frac_counters": measured_issue("k_simulate_tb_N16000_K10000"),
                "cycles_per_event_per_workgroup": round(kms * 1e-3 * CLOCK * 4 * CUS / events_tb, 1),
                # a run is a serial chain: the batch cannot end before its
                # longest run, so the latency view is the kernel time per
@@ -580,6 +663,7 @@ def main():
                    "accepted": stats["n_accepted"], "launch_shape": list(tune["best"])},
         "sde_steps_per_s": round(value * steps_em, 1),
         "roofline": roofline,
+        "compaction": compaction,
         "cpu_baseline": cpu,
         "workloads": workloads,
     }

@@ -505,6 +505,12 @@ int pps_set_timing(int enable);
 int pps_bege_count_ops(const double *theta, int n_theta, const double *r, int T, int n_omega,
                        double *ops, void *stream);
 double pps_last_kernel_ms(void);
+/* While timing is enabled: the duration in milliseconds of the ABC
+ * finalisation (the accept step of Alg. 1: radix selection in closest-fraction
+ * mode, ordered compaction of the accepted draws, FP64 moments) of the most
+ * recent abc_sample / abc_sample_noalloc call on the current device, timed
+ * by HIP events around it in the call's graph; negative if none was timed. */
+double pps_last_finalize_ms(void);
 
 /* ---- launch shape ------------------------------------------------------- */
 

@@ -17,7 +17,7 @@ from ._pps import (  # noqa: F401
     PPS_EPS_FIXED, PPS_EPS_TOP_FRACTION, PPS_GARCH_NSUMM, PPS_MAX_PARAMS, PPS_TSW_MAX_CELLS,
     CLASS_PATH, CLASS_GARCH, CLASS_GROUP, CLASS_CELLS,
     PPSError, LIB_PATH, lib, make_model, make_sampling,
-    pps_version, pps_n_summaries, pps_set_timing, pps_last_kernel_ms, pps_set_block_size, pps_get_block_size,
+    pps_version, pps_n_summaries, pps_set_timing, pps_last_kernel_ms, pps_last_finalize_ms, pps_set_block_size, pps_get_block_size,
     pps_set_launch_shape, pps_get_launch_shape, PATH_SHAPES, GARCH_SHAPES, CELL_SHAPES, pps_philox, pps_normals, pps_simulate,
     abc_sample, abc_sample_noalloc, PPS_NOALLOC_MAX_DRAWS, prior_pred_pvalue, pps_summary_tally, simulate, abc,
     PPS_JOB_ABC, PPS_JOB_PVALUE, PPS_POLICY_BATCHED, PPS_POLICY_PLAIN,

@@ -184,6 +184,7 @@ def lib():
         L.pps_set_timing.argtypes = [ctypes.c_int]
         L.pps_set_timing.restype = ctypes.c_int
         L.pps_last_kernel_ms.restype = ctypes.c_double
+        L.pps_last_finalize_ms.restype = ctypes.c_double
         L.pps_set_block_size.argtypes = [ctypes.c_int, ctypes.c_int]
         L.pps_set_block_size.restype = ctypes.c_int
         L.pps_get_block_size.argtypes = [ctypes.c_int]
@@ -285,6 +286,10 @@ def pps_version() -> str:
 
 def pps_set_timing(enable: bool) -> None:
     _check(lib().pps_set_timing(1 if enable else 0))
+
+
+def pps_last_finalize_ms() -> float:
+    return float(lib().pps_last_finalize_ms())
 
 
 def pps_last_kernel_ms() -> float:

@@ -79,8 +79,10 @@ int abc_run(Context &c, const pps_model *model, int n_summ, const double *y_obs,
     plan.fins.push_back(F);
     PPS_TRY(c.engine->launch(0, plan, stream, build));
     PPS_TRY(c.engine->wait(0));
-    if (g_timing)
+    if (g_timing) {
         c.last_kernel_ms = c.engine->sim_ms(0);
+        c.last_finalize_ms = c.engine->fin_ms(0);
+    }
 
     const FinResult &R = c.engine->out_fin(0)[0];
     stats->n_accepted = R.n_accepted;
@@ -108,6 +110,16 @@ int pps_set_timing(int enable)
 {
     g_timing = enable != 0;
     return PPS_OK;
+}
+
+double pps_last_finalize_ms(void)
+{
+    int rc;
+    Context *c = current_context(&rc);
+    if (!c)
+        return -1.0;
+    std::lock_guard<std::mutex> lk(c->mu);
+    return c->last_finalize_ms;
 }
 
 double pps_last_kernel_ms(void)

@@ -46,7 +46,7 @@ EpochEngine::~EpochEngine()
                         static_cast<void *>(s.dev.d_fins), static_cast<void *>(s.dev.states)})
             if (d)
                 (void)hipFree(d);
-        for (hipEvent_t ev : {s.sim_start, s.sim_stop, s.done})
+        for (hipEvent_t ev : {s.sim_start, s.sim_stop, s.fin_stop, s.done})
             if (ev)
                 (void)hipEventDestroy(ev);
         if (s.own_stream)
@@ -106,7 +106,8 @@ int EpochEngine::init(int n_slots, int cu_count)
         s.dev.states = static_cast<LaunchState *>(p);
         if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess ||
             (e = hipEventCreate(&s.sim_start)) != hipSuccess ||
-            (e = hipEventCreate(&s.sim_stop)) != hipSuccess)
+            (e = hipEventCreate(&s.sim_stop)) != hipSuccess ||
+            (e = hipEventCreate(&s.fin_stop)) != hipSuccess)
             return fail_hip(e, "epoch events");
         if (&s != &slots_[0] &&
             (e = hipStreamCreateWithFlags(&s.own_stream, hipStreamNonBlocking)) != hipSuccess)
@@ -192,6 +193,8 @@ int EpochEngine::graph_for(Slot &s, unsigned form, hipGraphExec_t *out, bool bui
     if (ei == hipSuccess && fin != 0)
         ei = issue_epoch_part(fin == 1 ? EPOCH_FINALIZE : EPOCH_FINALIZE_FIXED, s.dev, sh,
                               capture_stream_);
+    if (ei == hipSuccess && fin != 0)
+        ei = capture_event(capture_stream_, s.fin_stop);
     if (ei == hipSuccess)
         ei = issue_epoch_part(EPOCH_STAGE_OUT, s.dev, sh, capture_stream_);
     hipGraph_t graph = nullptr;
@@ -286,6 +289,7 @@ int EpochEngine::launch(int slot, EpochPlan &plan, hipStream_t stream, bool buil
     if (e != hipSuccess)
         return fail_hip(e, "epoch event");
     s.in_flight = true;
+    s.has_fin = H.n_fins > 0;
     last_slot_ = slot;
     last_stream_ = stream;
     return PPS_OK;
@@ -300,6 +304,12 @@ int EpochEngine::finish(Slot &s)
         ms = -1.0f;
     }
     s.sim_ms = ms;
+    float fms = -1.0f;
+    if (s.has_fin && hipEventElapsedTime(&fms, s.sim_stop, s.fin_stop) != hipSuccess) {
+        (void)hipGetLastError();
+        fms = -1.0f;
+    }
+    s.fin_ms = s.has_fin ? fms : -1.0f;
     return PPS_OK;
 }
 

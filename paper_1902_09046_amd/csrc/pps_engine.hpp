@@ -82,6 +82,9 @@ class EpochEngine {
     const unsigned long long *out_counts(int slot) const { return slots_[slot].h_out_counts; }
     // Duration of the simulation kernels of the slot's last finished epoch.
     float sim_ms(int slot) const { return slots_[slot].sim_ms; }
+    // Duration of that epoch's ABC finalisation (selection, compaction,
+    // moments), or a negative value if it had none.
+    float fin_ms(int slot) const { return slots_[slot].fin_ms; }
     int n_slots() const { return static_cast<int>(slots_.size()); }
 
   private:
@@ -98,10 +101,11 @@ class EpochEngine {
         std::map<unsigned, hipGraphExec_t> execs;
         bool have_shape = false;
         EpochShape exec_shape;
-        hipEvent_t sim_start = nullptr, sim_stop = nullptr, done = nullptr;
+        hipEvent_t sim_start = nullptr, sim_stop = nullptr, fin_stop = nullptr, done = nullptr;
         hipStream_t own_stream = nullptr;  // slots after the first
         bool in_flight = false;
-        float sim_ms = -1.0f;
+        bool has_fin = false;  // the epoch in flight has a finalisation
+        float sim_ms = -1.0f, fin_ms = -1.0f;
     };
     int set_graph_shape(Slot &s, bool build);
     int graph_for(Slot &s, unsigned form, hipGraphExec_t *out, bool build);

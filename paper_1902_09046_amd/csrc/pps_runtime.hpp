@@ -48,6 +48,7 @@ struct Context {
     // context is created so that the call allocates no host memory either
     EpochPlan noalloc_plan;
     double last_kernel_ms = -1.0;
+    double last_finalize_ms = -1.0;
 };
 
 extern bool g_timing;

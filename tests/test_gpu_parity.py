@@ -389,7 +389,10 @@ def test_kernel_timing_events(P, torch):
             torch.cuda.synchronize()
             wall_ms = (time.perf_counter() - t0) * 1e3
             k = P.pps_last_kernel_ms()
+            f = P.pps_last_finalize_ms()
             assert 0.0 < k <= wall_ms, (n, k, wall_ms)
+            # the finalisation follows the simulation inside the same call
+            assert 0.0 < f and k + f <= wall_ms, (n, k, f, wall_ms)
             kms.append(k)
         assert 2.5 * kms[0] < kms[1] < 6.0 * kms[0]
     finally:
