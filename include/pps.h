@@ -499,8 +499,7 @@ int pps_set_timing(int enable);
  * density kernel and stores in *ops (host) the FP64 operations that the
  * lanes executed as the algorithm states them: an FMA counts 2, a division
  * 1, a series term of P(a, x) 5 (plus 1 per block of 8), a continued-fraction
- * step 10 (plus 4 per block of 4), exp 32, log 90 and lgamma 200 (the FP64
- * operations of their gfx950 code).
+ * step 10 (plus 4 per block of 4), and exp, log, lgamma and sqrt 1 each.
  * Arguments and errors as pps_bege_loglik (ops must not be NULL). */
 int pps_bege_count_ops(const double *theta, int n_theta, const double *r, int T, int n_omega,
                        double *ops, void *stream);

@@ -65,7 +65,7 @@ def build(force: bool = True) -> str:
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp"
     subprocess.run(
-        ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-Wall", *_SRCS, "-o", tmp, "-lm"],
+        ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-Wall", *_SRCS, "-o", tmp, "-lquadmath", "-lm"],
         check=True,
     )
     os.replace(tmp, _LIB_PATH)
@@ -205,14 +205,19 @@ def _load():
         lib.or_gamma_p.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.or_gamma_p.restype = ctypes.c_double
         d5 = [ctypes.c_double] * 5
+        lib.or_gamma_q.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.or_gamma_q.restype = ctypes.c_double
         lib.or_bege_cdf.argtypes = d5 + [ctypes.c_int]
         lib.or_bege_cdf.restype = ctypes.c_double
         lib.or_bege_density.argtypes = d5 + [ctypes.c_int]
         lib.or_bege_density.restype = ctypes.c_double
+        lib.or_bege_density_q.argtypes = d5 + [ctypes.c_int]
+        lib.or_bege_density_q.restype = ctypes.c_double
         lib.or_bege_loglik.argtypes = [f64p, f64p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_double)]
         lib.or_bege_loglik.restype = ctypes.c_int
-        lib.or_bege_loglik_batch.argtypes = [f64p, ctypes.c_int, f64p, ctypes.c_int, ctypes.c_int, f64p]
+        lib.or_bege_loglik_batch.argtypes = [f64p, ctypes.c_int, f64p, ctypes.c_int, ctypes.c_int, f64p,
+                                             ctypes.c_void_p]
         lib.or_bege_loglik_batch.restype = ctypes.c_int
         lib.or_bege_simulate.argtypes = [f64p, ctypes.c_int, ctypes.c_uint64, f64p]
         lib.or_bege_simulate.restype = ctypes.c_int
@@ -521,12 +526,23 @@ def gamma_p(a: float, x: float) -> float:
     return float(_load().or_gamma_p(a, x))
 
 
+def gamma_q(a: float, x: float) -> float:
+    """Q(a, x) = 1 - P(a, x), the upper regularised incomplete gamma function."""
+    return float(_load().or_gamma_q(a, x))
+
+
 def bege_cdf(u: float, p: float, n: float, sp: float, sn: float, n_omega: int = 100) -> float:
     return float(_load().or_bege_cdf(u, p, n, sp, sn, n_omega))
 
 
 def bege_density(u: float, p: float, n: float, sp: float, sn: float, n_omega: int = 100) -> float:
     return float(_load().or_bege_density(u, p, n, sp, sn, n_omega))
+
+
+def bege_density_q(u: float, p: float, n: float, sp: float, sn: float, n_omega: int = 100) -> float:
+    """The central difference of bege_density with every operation in quad
+    precision (the FP64 density uses it where its two sums cancel)."""
+    return float(_load().or_bege_density_q(u, p, n, sp, sn, n_omega))
 
 
 def bege_loglik(theta, r, n_omega: int = 100) -> dict:
@@ -540,12 +556,16 @@ def bege_loglik(theta, r, n_omega: int = 100) -> dict:
     return {"loglik": float(out.value), "logdens": ld}
 
 
-def bege_loglik_batch(thetas, r, n_omega: int = 100) -> np.ndarray:
+def bege_loglik_batch(thetas, r, n_omega: int = 100, with_logdens: bool = False):
+    """log L of every row (OpenMP over rows); with_logdens: (log L, log f
+    of every (row, step)) instead."""
     th = np.ascontiguousarray(thetas, np.float64).reshape(-1, 11)
     rr = np.ascontiguousarray(r, np.float64)
     out = np.zeros(th.shape[0], np.float64)
-    _load().or_bege_loglik_batch(th, th.shape[0], rr, len(rr) - 1, n_omega, out)
-    return out
+    ld = np.zeros((th.shape[0], len(rr) - 1), np.float64) if with_logdens else None
+    _load().or_bege_loglik_batch(th, th.shape[0], rr, len(rr) - 1, n_omega, out,
+                                 None if ld is None else ld.ctypes.data)
+    return (out, ld) if with_logdens else out
 
 
 def bege_simulate(theta, T: int, seed: int) -> np.ndarray:

@@ -12,6 +12,7 @@
  * or call it, and it shares no code with the HIP library.
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 
@@ -35,10 +36,15 @@ void or_box_muller(uint32_t w0, uint32_t w1, double *z0, double *z1);
  *     factor is within 2^-53 of 1 (the series alone would overflow for large
  *     x: its terms grow like e^x before they fall).
  * x <= 0 gives 0.                                                           */
-double or_gamma_p(double a, double x)
+/* P(a, x) and its complement Q(a, x) = 1 - P(a, x) (*q): the series gives P
+ * and Q = 1 - P; the continued fraction gives Q = lead * fraction directly
+ * and P = 1 - Q, so a Q of e^-x size keeps its relative accuracy.          */
+static double gamma_pq(double a, double x, double *q)
 {
-    if (!(x > 0.0))
+    if (!(x > 0.0)) {
+        *q = 1.0;
         return 0.0;
+    }
     const double lead = exp(-x + a * log(x) - lgamma(a));
     if (x < a + 1.0) {
         double term = 1.0 / a, sum = term, den = a;
@@ -49,7 +55,9 @@ double or_gamma_p(double a, double x)
             if (fabs(term) < fabs(sum) * OR_IGAM_EPS)
                 break;
         }
-        return sum * lead;
+        const double pv = sum * lead;
+        *q = 1.0 - pv;
+        return pv;
     }
     const double tiny = 1e-300;
     double b = x + 1.0 - a;
@@ -71,7 +79,22 @@ double or_gamma_p(double a, double x)
         if (fabs(del - 1.0) < OR_IGAM_EPS)
             break;
     }
-    return 1.0 - lead * f;
+    *q = lead * f;
+    return 1.0 - *q;
+}
+
+double or_gamma_p(double a, double x)
+{
+    double q;
+    return gamma_pq(a, x, &q);
+}
+
+/* Q(a, x) = 1 - P(a, x), the upper regularised incomplete gamma function. */
+double or_gamma_q(double a, double x)
+{
+    double q;
+    gamma_pq(a, x, &q);
+    return q;
 }
 
 /* Distribution function of u = s_p w_p - s_n w_n, w ~ centred gamma (shapes p,
@@ -79,7 +102,9 @@ double or_gamma_p(double a, double x)
  * paper: w^j = w^0 + j dw, j = 0..N, w^0 = 1e-4 - p s_p, dw = (10 s_p sqrt(p)
  * - w^0) / (N - 1):
  *   F(u) = sum_{j=1..N} [1 - P(n, (w^{j-1} - u + n s_n)/s_n)]
- *                       [P(p, (w^j + p s_p)/s_p) - P(p, (w^{j-1} + p s_p)/s_p)]. */
+ *                       [P(p, (w^j + p s_p)/s_p) - P(p, (w^{j-1} + p s_p)/s_p)].
+ * The first factor is the upper function Q(n, .), taken as computed (not as
+ * 1 minus a P that is within rounding of 1).                                */
 double or_bege_cdf(double u, double p, double n, double sp, double sn, int n_omega)
 {
     const double w0 = 1e-4 - p * sp;
@@ -89,20 +114,117 @@ double or_bege_cdf(double u, double p, double n, double sp, double sn, int n_ome
     for (int j = 1; j <= n_omega; ++j) {
         const double wj = w0 + j * dw, wjm = w0 + (j - 1) * dw;
         const double cur = or_gamma_p(p, (wj + p * sp) / sp);
-        const double tail = 1.0 - or_gamma_p(n, (wjm - u + n * sn) / sn);
+        const double tail = or_gamma_q(n, (wjm - u + n * sn) / sn);
         f += tail * (cur - prev);
         prev = cur;
     }
     return f;
 }
 
+/* ---- the same difference in quad precision (__float128: 113-bit
+ * significand), for the steps where the two FP64 sums of the central
+ * difference cancel.                                                        */
+typedef __float128 quad;
+#define OR_IGAM_EPS_Q 1.925929944387235853055977942584927319e-34Q /* 2^-112 */
+
+/* P and Q as gamma_pq, in quad precision. */
+static quad gamma_pq_q(quad a, quad x, quad *q)
+{
+    if (!(x > 0)) {
+        *q = 1;
+        return 0;
+    }
+    const quad lead = expq(-x + a * logq(x) - lgammaq(a));
+    if (x < a + 1) {
+        quad term = 1 / a, sum = term, den = a;
+        for (int k = 1; k < OR_IGAM_MAXIT; ++k) {
+            den += 1;
+            term *= x / den;
+            sum += term;
+            if (fabsq(term) < fabsq(sum) * OR_IGAM_EPS_Q)
+                break;
+        }
+        *q = 1 - sum * lead;
+        return sum * lead;
+    }
+    const quad tiny = 1e-4000Q;
+    quad b = x + 1 - a;
+    quad c = 1 / tiny;
+    quad d = 1 / b;
+    quad f = d;
+    for (int i = 1; i < OR_IGAM_MAXIT; ++i) {
+        const quad an = -i * (i - a);
+        b += 2;
+        d = an * d + b;
+        if (fabsq(d) < tiny)
+            d = tiny;
+        c = b + an / c;
+        if (fabsq(c) < tiny)
+            c = tiny;
+        d = 1 / d;
+        const quad del = d * c;
+        f *= del;
+        if (fabsq(del - 1) < OR_IGAM_EPS_Q)
+            break;
+    }
+    *q = lead * f;
+    return 1 - *q;
+}
+
+/* F(u + h) - F(u - h) in quad precision, summed node by node:
+ *   sum_j [P(p, x_j) - P(p, x_{j-1})] [Q(n, y_j(u + h)) - Q(n, y_j(u - h))],
+ * the difference of the two sums of Eq. BEGE_LL_approx regrouped by node
+ * (the increments of P(p, .) are common to both).  Each difference of two
+ * values of the complementary pair (P, Q) is taken on the side where the two
+ * values are small: of P below the argument a + 1, of Q above it, so terms
+ * whose two values agree to more than quad precision (F(u + h) and F(u - h)
+ * near 1/2 with a difference of e^-100) keep their significant digits.     */
+static quad pair_diff_q(quad a, quad xlo, quad xhi)
+{
+    /* P(a, xhi) - P(a, xlo) = Q(a, xlo) - Q(a, xhi), xlo <= xhi, P = 0 below 0 */
+    quad qlo, qhi;
+    const quad plo = gamma_pq_q(a, xlo, &qlo);
+    const quad phi = gamma_pq_q(a, xhi, &qhi);
+    return xlo >= a + 1 ? qlo - qhi : phi - plo;
+}
+
+static quad bege_cdf_diff_q(quad u, quad h, quad p, quad n, quad sp, quad sn, int n_omega)
+{
+    const quad w0 = 1e-4Q - p * sp;
+    const quad dw = (10 * sp * sqrtq(p) - w0) / (n_omega - 1);
+    quad d = 0;
+    for (int j = 1; j <= n_omega; ++j) {
+        const quad wj = w0 + j * dw, wjm = w0 + (j - 1) * dw;
+        const quad dF = pair_diff_q(p, (wjm + p * sp) / sp, (wj + p * sp) / sp);
+        /* y_j(u + h) <= y_j(u - h): the tails differ by the Gamma(n) mass between */
+        const quad m = pair_diff_q(n, (wjm - (u + h) + n * sn) / sn, (wjm - (u - h) + n * sn) / sn);
+        d += dF * m;
+    }
+    return d;
+}
+
+/* The central difference below in quad precision (regrouped by node). */
+double or_bege_density_q(double u, double p, double n, double sp, double sn, int n_omega)
+{
+    const quad h = 1e-3Q * sqrtq((quad)sp * sp * p + (quad)sn * sn * n);
+    return (double)(bege_cdf_diff_q(u, h, p, n, sp, sn, n_omega) / (2 * h));
+}
+
 /* Transition density by the central difference (F(u + h) - F(u - h)) / (2 h),
- * h = 1e-3 times the standard deviation sqrt(s_p^2 p + s_n^2 n) of u.        */
+ * h = 1e-3 times the standard deviation sqrt(s_p^2 p + s_n^2 n) of u.  Each
+ * distribution function is a sum of N_omega products of factors in [0, 1]
+ * (a tail 1 - P and an increment of P), so in FP64 it carries an absolute
+ * rounding error of about N_omega ulps of 1 whatever its own size.  Where the
+ * difference is below 2^-26 that error would leave it fewer than ~20 correct
+ * bits, so it is evaluated again in quad precision, regrouped by node.      */
 double or_bege_density(double u, double p, double n, double sp, double sn, int n_omega)
 {
     const double h = 1e-3 * sqrt(sp * sp * p + sn * sn * n);
-    return (or_bege_cdf(u + h, p, n, sp, sn, n_omega) - or_bege_cdf(u - h, p, n, sp, sn, n_omega)) /
-           (2.0 * h);
+    const double fp = or_bege_cdf(u + h, p, n, sp, sn, n_omega);
+    const double fm = or_bege_cdf(u - h, p, n, sp, sn, n_omega);
+    if (fabs(fp - fm) <= 0x1p-26)
+        return or_bege_density_q(u, p, n, sp, sn, n_omega);
+    return (fp - fm) / (2.0 * h);
 }
 
 /* log L(theta; r_0..r_T) of Eq. BEGE_LL, theta = (p0, s_p, rho_p, phi_p+,
@@ -141,13 +263,15 @@ int or_bege_loglik(const double *th, const double *r, int T, int n_omega, double
     return 0;
 }
 
-/* Batched: log L of n_theta parameter vectors (rows of 11), OpenMP over rows. */
+/* Batched: log L of n_theta parameter vectors (rows of 11), OpenMP over rows;
+ * ld (optional, n_theta x T, row k at k T) receives every step's log f.      */
 int or_bege_loglik_batch(const double *theta, int n_theta, const double *r, int T, int n_omega,
-                         double *ll)
+                         double *ll, double *ld)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(dynamic, 1)
     for (int k = 0; k < n_theta; ++k)
-        or_bege_loglik(&theta[(size_t)k * OR_BEGE_NPAR], r, T, n_omega, NULL, &ll[k]);
+        or_bege_loglik(&theta[(size_t)k * OR_BEGE_NPAR], r, T, n_omega,
+                       ld ? &ld[(size_t)k * T] : NULL, &ll[k]);
     return 0;
 }
 

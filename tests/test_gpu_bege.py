@@ -5,21 +5,39 @@ Bar.  Both sides compute the same discretised distribution functions in FP64
 but not in the same way: the oracle sums F(u + h) and F(u - h) separately and
 subtracts; the device accumulates the differences of the tails directly, each
 one the Gamma(n, 1) mass of a short interval (a Taylor series about its
-midpoint, exact to rounding, where the oracle's two incomplete gamma values
-cancel), evaluates P(a, x) by division-free recurrences, and uses different
+midpoint, or the difference of two upper functions Q in the upper tail),
+evaluates P(a, x) by division-free recurrences, and uses different
 log/exp/lgamma implementations.
-The leading factor exp(a ln x - x - ln Gamma(a)) of P carries an absolute
-error of a few ulps of its largest term, and the oracle's two sums carry up
-to N_omega ulps each, so the numerator F(u + h) - F(u - h) = 2h f may differ
-by
 
-    tol_F = 2^-45 (1 + a (1 + |ln a|)),   a = max(p_{t-1}, n_{t-1}) + N_omega / 100,
+* Where the oracle's FP64 difference exceeds 2^-26 it is its result.  The
+  leading factor exp(a ln x - x - ln Gamma(a)) of P carries an absolute
+  error of a few ulps of its largest term, and the oracle's two sums up to
+  N_omega ulps each, so the numerators F(u + h) - F(u - h) = 2h f may differ
+  by
 
-and the log density by tol_F / (2h f).  A step whose oracle numerator is
-itself below tol_F is not resolved by either side: there only "both are
-small or -inf" is checked, and the log-likelihood of its vector is compared
-only in that weak sense.  Steps with non-positive shapes are -inf on both
-sides exactly.
+      tol_F = 2^-45 (1 + a (1 + |ln a|)),   a = max(p_{t-1}, n_{t-1}) + N_omega / 100,
+
+  and the log density by tol_F / (2h f) (at most ~1e-6 above 2^-26).
+* Below 2^-26 the oracle evaluates the same difference in quad precision,
+  exact to far beyond FP64, so the bar is the device's own error, relative:
+  its interval masses are formed without cancellation (Taylor terms of one
+  sign, or Q values of e^-y size each with its relative accuracy, differing
+  by at least d |L_1| ~ 1e-4 of themselves), 1e-10, plus the rounding of
+  their leading factor's exponent, which reaches a (1 + |ln a|) in size:
+  tol_F read as a relative bound (1e-7 at the largest shapes of the tests);
+  plus the FP64 rounding of the node positions, which the quad oracle does
+  not have: w^0 + j dw cancels terms of size p s_p, so a node is up to
+  8 ulp(2 p s_p + |u| + n s_n) off, which acts on the density as a shift of
+  u by as much, |d ln f / du| times that (|d ln f / du| from the quad oracle
+  by a central difference; it is large where a node's interval of the
+  negative shock's law ends just above 0).
+* Steps with non-positive shapes or scales are -inf on both sides exactly.
+  A density below the smallest normal FP64 number (log f < -708.4) is
+  outside what an FP64 evaluation resolves (the device's products underflow
+  to denormals or 0, the oracle's quad value rounds to a denormal or 0):
+  there both sides must lie below that level, and the vector's log L is not
+  compared.  Every other step is finite on both sides, and log L is compared
+  on every other vector within the sum of its steps' bars.
 """
 import json
 import math
@@ -68,40 +86,78 @@ def shapes(th, r):
     return P_, N_
 
 
+QUAD_BELOW = 2.0 ** -26   # the oracle's switch to its quad-precision difference
+DEVICE_REL = 1e-10        # the device's relative bar where the oracle is exact
+LOG_DBL_MIN = math.log(np.finfo(np.float64).tiny)  # -708.40: below, FP64 loses the density
+
+
 def compare(P, thetas, r, n_omega=100, label=""):
     g = P.pps_bege_loglik(thetas, r, n_omega=n_omega, with_logdens=True)
     gll, gld = g["loglik"].cpu().numpy(), g["logdens"].cpu().numpy()
-    worst, unresolved, checked = 0.0, 0, 0
+    worst_f, worst_q, n_quad, checked, n_low = 0.0, 0.0, 0, 0, 0
+    oll, old_ = oracle.bege_loglik_batch(thetas, r, n_omega, with_logdens=True)
     for k, th in enumerate(thetas):
-        o = oracle.bege_loglik(th, r, n_omega)
+        o = {"loglik": oll[k], "logdens": old_[k]}
         ps, ns = shapes(th, r)
         valid = (ps > 0) & (ns > 0) & (th[1] > 0) & (th[6] > 0)
         # structurally -inf steps agree exactly
         assert np.all(gld[k][~valid] == -np.inf) and np.all(o["logdens"][~valid] == -np.inf)
+        # densities below the smallest normal FP64 number: the device's
+        # products underflow to denormals or 0 there, the oracle's quad value
+        # rounds to a denormal or 0; both must lie below it (with a margin
+        # of e^2 for a step that sits at the edge on one side only)
+        low = valid & ((o["logdens"] < LOG_DBL_MIN) | (gld[k] < LOG_DBL_MIN))
+        assert np.all(np.maximum(o["logdens"][low], gld[k][low]) < LOG_DBL_MIN + 2.0), (label, k)
+        n_low += int(low.sum())
+        valid = valid & ~low
+        assert np.all(np.isfinite(gld[k][valid]) & np.isfinite(o["logdens"][valid])), (label, k)
         with np.errstate(invalid="ignore"):
             h2 = 2e-3 * np.sqrt(th[1] ** 2 * np.where(valid, ps, 0) + th[6] ** 2 * np.where(valid, ns, 0))
         a = np.maximum(ps, ns) + n_omega / 100.0
         tol_f = 2.0 ** -45 * (1.0 + a * (1.0 + np.abs(np.log(np.maximum(a, 1e-300)))))
         num_o = h2 * np.exp(o["logdens"])          # 2h f of the oracle (0 where -inf)
         num_g = h2 * np.exp(gld[k])
-        res = valid & (num_o > tol_f)
-        bad = np.abs(num_g[res] - num_o[res]) > tol_f[res]
-        assert not bad.any(), (label, k, np.nonzero(res)[0][bad][:5])
-        if res.any():
-            worst = max(worst, float((np.abs(num_g[res] - num_o[res]) / tol_f[res]).max()))
-        # unresolved steps: both numerators below 2 tol_F (or -inf)
-        un = valid & ~res
-        unresolved += int(un.sum())
-        assert np.all(num_g[un] <= 2.0 * tol_f[un])
-        if not un.any() and valid.all():
-            tol_ll = float(np.sum(tol_f / num_o)) + 1e-12 * abs(o["loglik"])
+        fin = valid & np.isfinite(o["logdens"])
+        quad = fin & (num_o <= QUAD_BELOW)
+        fp = fin & ~quad
+        n_quad += int(quad.sum())
+        dif = np.abs(num_g - num_o)
+        assert not (dif[fp] > tol_f[fp]).any(), (label, k, np.nonzero(fp)[0][dif[fp] > tol_f[fp]][:5])
+        # where the oracle is exact: the device's relative error, its masses'
+        # own (DEVICE_REL) plus their leading factor's exponent of size up to
+        # a (1 + |ln a|), rounded to a few ulps (tol_F's factor, relative)
+        # plus the FP64 rounding of the node positions: w^0 + j dw cancels
+        # terms of size p s_p, so a node sits up to dw_err = 8 ulp(2 p s_p +
+        # |u| + n s_n) off, which moves the density like a shift of u by as
+        # much (large where a node's interval of the negative shock's law ends
+        # just above 0): |d ln f / du| from the quad oracle, times dw_err
+        rel_q = DEVICE_REL + tol_f
+        u_all = r[1:] - th[10]
+        for t in np.nonzero(quad)[0]:
+            args = (ps[t], ns[t], th[1], th[6], n_omega)
+            eta = 1e-7 * h2[t]
+            fp_, fm_ = (oracle.bege_density_q(u_all[t] + sgn * eta, *args) for sgn in (1.0, -1.0))
+            if fp_ > 0.0 and fm_ > 0.0:
+                kappa = abs(math.log(fp_) - math.log(fm_)) / (2.0 * eta)
+                dw_err = 8.0 * 2.0 ** -52 * (2.0 * ps[t] * th[1] + abs(u_all[t]) + ns[t] * th[6])
+                rel_q[t] += kappa * dw_err
+        assert not (dif[quad] > rel_q[quad] * num_o[quad]).any(), \
+            (label, k, np.nonzero(quad)[0][dif[quad] > rel_q[quad] * num_o[quad]][:5])
+        if fp.any():
+            worst_f = max(worst_f, float((dif[fp] / tol_f[fp]).max()))
+        if quad.any():
+            worst_q = max(worst_q, float((dif[quad] / (rel_q[quad] * num_o[quad])).max()))
+        if low.any():
+            pass  # log L holds a density below the FP64 range: not compared
+        elif np.isfinite(o["loglik"]):
+            tol_ll = float(np.sum(tol_f[fp] / num_o[fp]) + np.sum(rel_q[quad])) + 1e-12 * abs(o["loglik"])
             assert abs(gll[k] - o["loglik"]) <= tol_ll, (label, k, gll[k], o["loglik"], tol_ll)
             checked += 1
-        elif not valid.all():
-            assert gll[k] == -np.inf and o["loglik"] == -np.inf
-        # (a vector with an unresolved step is compared step by step only)
-    print(f"{label}: {len(thetas)} vectors, {checked} log L compared, worst |dF|/tol {worst:.3g}, "
-          f"{unresolved} unresolved steps")
+        else:
+            assert gll[k] == -np.inf
+    print(f"{label}: {len(thetas)} vectors, {checked} finite log L compared, worst |dF|/tol_F "
+          f"{worst_f:.3g}, {n_quad} steps against the quad difference (worst relative / bar {worst_q:.3g}), "
+          f"{n_low} steps below the FP64 range")
     return gll, gld
 
 
@@ -151,7 +207,7 @@ def test_bege_domain_edges(P, torch, series):
 
 def test_bege_full_batch_sampled(P, torch, series):
     """The benchmark batch: N_p = 1024 prior draws, T = 1099, N_omega = 100.
-    16 sampled vectors against the oracle (every step), and the device's own
+    Every vector against the oracle (every step), and the device's own
     repeatability (bit-identical results on a second call, with and without
     the per-step output)."""
     cfg = W.BEGE_BATCH
@@ -165,10 +221,10 @@ def test_bege_full_batch_sampled(P, torch, series):
     fin = np.isfinite(la)
     np.testing.assert_allclose(la[fin], ld[fin].sum(axis=1), rtol=1e-12)
     assert np.all(np.isneginf(ld[~fin]).any(axis=1))
-    rng = np.random.default_rng(0)
-    pick = rng.choice(cfg["n_theta"], size=16, replace=False)
-    gll, _ = compare(P, th[pick], series, label="full batch, sampled")
-    np.testing.assert_array_equal(gll, la[pick])
+    # every vector, every step (the oracle resolves the deep tails by its
+    # quad-precision difference)
+    gll, _ = compare(P, th, series, label="full batch")
+    np.testing.assert_array_equal(gll, la)
 
 
 def test_bege_invalid(P, torch, series):

@@ -215,3 +215,95 @@ def test_observed_series_is_the_golden_one():
     r = oracle.bege_simulate(g["theta"], g["T"], g["seed"])
     np.testing.assert_array_equal(r, np.array(g["r"]))
     assert abs(r.std() - 0.057) < 0.01
+
+
+# ---- the upper tail and the quad-precision difference ----------------------
+
+def _mp_gamma(a, x, upper):
+    import mpmath as mp
+    return mp.gammainc(mp.mpf(a), mp.mpf(x), mp.inf, regularized=True) if upper else \
+        mp.gammainc(mp.mpf(a), 0, mp.mpf(x), regularized=True)
+
+
+@pytest.mark.parametrize("a,x", [(0.008, 64.0), (0.83, 676.0), (49.7, 135.0), (0.3, 2.0),
+                                 (5.0, 6.0), (2.0, 700.0), (1e3, 1.3e3)])
+def test_gamma_q_upper_tail_relative(a, x):
+    """Q(a, x) = 1 - P(a, x) keeps its relative accuracy down to e^-700
+    (50-digit mpmath); P = 1 - Q stays consistent."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    ref = float(_mp_gamma(a, x, True))
+    got = oracle.gamma_q(a, x)
+    assert abs(got / ref - 1.0) < 1e-12 + gamma_tol(a, x) * 10, (a, x, got, ref)
+    assert oracle.gamma_p(a, x) == 1.0 - got
+
+
+def _mp_density(u, p, n, sp, sn, n_omega, dps=50):
+    """The central difference of the discretised distribution function of
+    Eq. BEGE_LL_approx (as the oracle reads it: nodes w^j, h = 1e-3 sd), the
+    two sums formed as written and subtracted, at `dps` digits."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    p, n, sp, sn, u = (mp.mpf(v) for v in (p, n, sp, sn, u))
+    w0 = mp.mpf('1e-4') - p * sp
+    dw = (10 * sp * mp.sqrt(p) - w0) / (n_omega - 1)
+
+    def cdf(uu):
+        prev = _mp_gamma(p, (w0 + p * sp) / sp, False)
+        f = mp.mpf(0)
+        for j in range(1, n_omega + 1):
+            cur = _mp_gamma(p, (w0 + j * dw + p * sp) / sp, False)
+            x = (w0 + (j - 1) * dw - uu + n * sn) / sn
+            tail = _mp_gamma(n, x, True) if x > 0 else mp.mpf(1)
+            f += tail * (cur - prev)
+            prev = cur
+        return f
+    h = mp.mpf('1e-3') * mp.sqrt(sp * sp * p + sn * sn * n)
+    return (cdf(u + h) - cdf(u - h)) / (2 * h)
+
+
+# far left tails of u (the negative shock's upper tail): densities e^-27 .. e^-624,
+# where the two FP64 sums agree to every bit; and an ordinary point
+TAIL_CASES = [(-0.766984, 0.281325, 0.862055, 0.1061, 0.02371),
+              (-0.715164, 0.490402, 0.00800925, 0.00508, 0.01121),
+              (-0.486412, 0.243791, 49.7437, 0.2939, 0.005708),
+              (0.01, 2.0, 3.0, 0.02, 0.03)]
+
+
+@pytest.mark.parametrize("u,p,n,sp,sn", TAIL_CASES)
+def test_density_in_the_tails_matches_50_digits(u, p, n, sp, sn):
+    """The oracle's density (FP64, with the quad-precision difference where
+    the FP64 one would keep fewer than ~20 bits) and the quad evaluation
+    itself against the same formula at 50 digits (N_omega = 12)."""
+    ref = float(_mp_density(u, p, n, sp, sn, 12))
+    assert ref > 0.0
+    q = oracle.bege_density_q(u, p, n, sp, sn, 12)
+    f = oracle.bege_density(u, p, n, sp, sn, 12)
+    assert abs(q / ref - 1.0) < 1e-14, (q, ref)
+    assert abs(f / ref - 1.0) < 1e-6, (f, ref)
+
+
+def test_density_n_omega_100_deep_tail():
+    """One deep-tail point at the benchmark's N_omega = 100: log f = -68.41
+    (the literal FP64 difference is exactly 0 there)."""
+    u, p, n, sp, sn = TAIL_CASES[1]
+    ref = float(_mp_density(u, p, n, sp, sn, 100))
+    f = oracle.bege_density(u, p, n, sp, sn, 100)
+    assert abs(math.log(f) - math.log(ref)) < 1e-10, (math.log(f), math.log(ref))
+
+
+def test_density_where_the_two_sums_agree_beyond_quad_precision():
+    """A huge positive-shock shape (grid spacing ~1 sd of its law): F(u + h)
+    and F(u - h) are ~0.9 and differ by ~1e-39 (log f = -83.65), beyond the
+    113 bits of a quad difference of the two sums; the oracle's quad tier
+    regroups the difference by node.  Against the literal formula at 90
+    digits, N_omega = 100."""
+    u, p, n, sp, sn = 0.0151, 8376.36, 0.426262, 0.0226767, 0.0192717
+    ref = _mp_density(u, p, n, sp, sn, 100, dps=90)
+    f = oracle.bege_density(u, p, n, sp, sn, 100)
+    assert abs(math.log(f) - float(mp_log(ref))) < 1e-10, (math.log(f), float(mp_log(ref)))
+
+
+def mp_log(v):
+    import mpmath as mp
+    return mp.log(v)
