@@ -866,28 +866,36 @@ struct TbHit {
     int pre;   // this lane's prefix in the row
 };
 
-// The slot holding case m (0 <= m < number of cases) in slot order.
+// The slot holding case m (0 <= m < number of cases) in slot order.  Every
+// lane works out, from its own four row totals, which of its rows would hold
+// case m and its rank there (VALU work beside the ballot that picks the
+// lane); one lane read then takes the picked lane's (row, rank).
 __device__ __forceinline__ TbHit tb_find(const uint16_t *pre, const TbRegs &c, uint32_t m)
 {
     const int lane = threadIdx.x;
     TbHit h;
-    // the last lane whose lower lanes hold at most m cases (lane 0 always)
-    h.grp = 63 - __builtin_clzll(__ballot(c.excl <= static_cast<int>(m)) | 1ull);
-    const int r = static_cast<int>(m) - __builtin_amdgcn_readlane(c.excl, h.grp);
-    const uint64_t f = tb_readlane64(c.tot4, h.grp);
-    const int f0 = static_cast<int>(f & 0xffffu);
-    const int f1 = static_cast<int>((f >> 16) & 0xffffu);
-    const int f2 = static_cast<int>((f >> 32) & 0xffffu);
+    const int r = static_cast<int>(m) - c.excl;
+    const int f0 = static_cast<int>(c.tot4 & 0xffffu);
+    const int f1 = static_cast<int>((c.tot4 >> 16) & 0xffffu);
+    const int f2 = static_cast<int>((c.tot4 >> 32) & 0xffffu);
     // all ones when r >= the cases of the lane's first 1, 2, 3 rows (the
     // sign of a difference of values below 2^15; no branches)
     const int m0 = (f0 - 1 - r) >> 31;
     const int m1 = (f0 + f1 - 1 - r) >> 31;
     const int m2 = (f0 + f1 + f2 - 1 - r) >> 31;
-    h.fld = -(m0 + m1 + m2);
+    const int fld = -(m0 + m1 + m2);
     const int before = (f0 & m0) + (f1 & m1) + (f2 & m2);
-    h.row = 4 * h.grp + h.fld;
+    // (row << 16) | rank in the row: the rank is below 2^15 in the lane
+    // that holds case m (other lanes' keys are never read)
+    const int key = ((4 * lane + fld) << 16) | ((r - before) & 0xffff);
+    // the last lane whose lower lanes hold at most m cases (lane 0 always)
+    h.grp = 63 - __builtin_clzll(__ballot(c.excl <= static_cast<int>(m)) | 1ull);
+    const int k = __builtin_amdgcn_readlane(key, h.grp);
+    h.row = k >> 16;
+    h.fld = h.row & 3;
+    const int rank = k & 0xffff;
     h.pre = pre[64 * h.row + lane];
-    h.col = tb_first(__ballot(h.pre > r - before));
+    h.col = tb_first(__ballot(h.pre > rank));
     // whether the slot held one case: its prefix minus the one before it, two
     // lane reads of the row itself (the difference formed by a DPP subtract
     // that shifts the row by one lane, wave_shr:1, into its own register gave
@@ -918,11 +926,11 @@ __device__ __forceinline__ void tb_add(uint16_t *pre, TbRegs &c, int grp, int fl
 __device__ __forceinline__ void tb_new_genotype(uint16_t *pre, TbRegs &c)
 {
     const int lane = threadIdx.x;
+    // every lane: its first row that is not full (bit 6 + 16 j of ~occ4)
+    const int fld_l = __builtin_ctzll((~c.occ4 & TB_FULL_BITS) | (1ull << 63)) >> 4;
     const int grp = tb_first(__ballot((c.occ4 & TB_FULL_BITS) != TB_FULL_BITS));
-    const uint64_t f = tb_readlane64(c.occ4, grp);
-    // bit 6 + 16 j of ~f: row j of the lane is not full
-    const int fld = __builtin_ctzll((~f & TB_FULL_BITS) | (1ull << 63)) >> 4;
-    const int row = 4 * grp + fld;
+    const int row = __builtin_amdgcn_readlane(4 * lane + fld_l, grp);
+    const int fld = row & 3;
     const int p = pre[64 * row + lane];
     const int cnt = p - __builtin_amdgcn_update_dpp(0, p, 0x138, 0xF, 0xF, false);
     const int col = tb_first(__ballot(cnt == 0));
