@@ -10,6 +10,8 @@ against facts fixed outside its code:
   the evidence computed by 2-D quadrature (the estimator is unbiased for Z),
   within its Monte Carlo error; the tempering schedule ends at 1 and the move
   counts follow ceil(ln c / ln(1 - p_acc));
+* multinomial resampling: every ancestor is the categorical inverse
+  distribution function of the float weights, in rational arithmetic;
 * Alg. 2's p-values and alpha cut-offs equal numpy's counts and inverse-CDF
   quantiles of the returned evidences.
 """
@@ -147,6 +149,52 @@ def test_smc_resampling_is_inversion_of_the_weights():
     nz = expected > 0
     chi2 = ((counts[nz] - expected[nz]) ** 2 / expected[nz]).sum()
     assert chi2 < stats.chi2.ppf(0.999, nz.sum() - 1)
+
+
+@pytest.mark.parametrize("case", ["uniform", "dyadic", "one_nonzero", "tiny_and_large"])
+def test_smc_resampling_is_categorical_inversion(case):
+    """Multinomial resampling is the inverse distribution function of the
+    categorical law with probabilities w_i / sum w (Alg. 3, resampling step):
+    with the uniform U = r / 2^64 of each particle's 64-bit random integer r,
+    the ancestor is the first i whose exact cumulative share C_i = (w_1 + ...
+    + w_i) / sum w exceeds U.  Checked in rational arithmetic on the float
+    weights themselves, not on their fixed-point images, so the fixed-point
+    reading is held to the textbook law: it may move an ancestor only for a
+    uniform within (n + 2) 2^-52 / sum w of a boundary C_i (the truncation of
+    each weight and the flooring of U), and none of these draws lands there."""
+    from fractions import Fraction
+    rng = np.random.default_rng({"uniform": 15, "dyadic": 16, "one_nonzero": 17, "tiny_and_large": 18}[case])
+    n = 257
+    if case == "uniform":
+        w = rng.uniform(0.0, 1.0, size=n)
+        w[rng.integers(0, n, size=40)] = 0.0
+    elif case == "dyadic":
+        w = rng.integers(0, 9, size=n) / 8.0
+    elif case == "one_nonzero":
+        w = np.zeros(n)
+        w[123] = 0.3
+    else:
+        w = np.where(rng.uniform(size=n) < 0.5, 1e-300, 1.0) * rng.uniform(0.5, 1.0, size=n)
+    step = 9
+    anc = oracle.smc_resample(w, 5, 71, step)
+    words = np.array([oracle.stream_block(5, 71, step, 0x60000000 + i) for i in range(n)], np.uint64)
+    r64 = [(int(a) << 32) | int(b) for a, b in zip(words[:, 1], words[:, 0])]
+    wq = [Fraction(float(x)) for x in w]
+    tot = sum(wq)
+    cum, acc = [], Fraction(0)
+    for x in wq:
+        acc += x
+        cum.append(acc / tot)
+    band = Fraction(n + 2, 2 ** 52) / tot
+    for i, r in enumerate(r64):
+        U = Fraction(r, 2 ** 64)
+        exact = next(k for k, c in enumerate(cum) if c > U)
+        near = min(abs(U - c) for c in cum)
+        assert near > band, (case, i)
+        assert anc[i] == exact, (case, i, anc[i], exact)
+        assert w[anc[i]] > 0.0
+    if case == "one_nonzero":
+        assert np.all(anc == 123)
 
 
 def test_smc_proposal_factor():
