@@ -1019,46 +1019,57 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
             if (4 * lane + k >= nr_used)
                 c.occ4 |= 64ull << (16 * k);
         __syncthreads();
-        // one event with words (wc, wt); false once the run has ended
         uint32_t e = 0;
-        // one event: case word wc; birth, and type word below the death
-        // threshold (birth implies it; neither is a mutation)
-        auto event = [&](uint32_t wc, bool birth, bool below_td) {
+        // one event: case word wc and the population step dn (+1 birth,
+        // -1 death, 0 mutation); dn is wave-uniform, so N stays scalar
+        auto event = [&](uint32_t wc, int dn) {
             const uint32_t m = __umulhi(wc, N);
             const TbHit h = tb_find(s_pre, c, m);
-            const bool death = !birth && below_td;
-            const int d = birth ? 1 : -1;
-            const int o = (!birth && h.one) ? -1 : 0;
+            const int d = dn > 0 ? 1 : -1;
+            const int o = (dn <= 0 && h.one) ? -1 : 0;
             tb_add(s_pre, c, h.grp, h.fld, h.row, h.col, h.pre, d, o);
-            N = birth ? N + 1 : (death ? N - 1 : N);
-            if (!birth && !death) {
+            N += static_cast<uint32_t>(dn);
+            if (dn == 0) {
                 // mutation: the case leaves its genotype for a new one in
                 // the lowest empty slot (after the parent's count dropped)
                 __builtin_amdgcn_wave_barrier();
                 tb_new_genotype(s_pre, c);
             }
             __builtin_amdgcn_wave_barrier();
-            ++e;
         };
         // running: 0 < N < n_stop and e < max_events
         auto running = [&]() { return N - 1 < n_stop - 1 && e < max_events; };
         while (running()) {
-            // events e .. e + 127: block e/2 + j in lane j (e is even here)
+            // events e .. e + 127: block e/2 + j in lane j (e is a multiple
+            // of 128 here); lane j's type words are those of events e + 2j
+            // (word y) and e + 2j + 1 (word w)
             const Words4 wv = stream_block(key, draw, (e >> 1) + static_cast<uint32_t>(lane),
                                            PURPOSE_TB_EVENT);
-            // the types of all 128 events at once: lane j's type words are
-            // those of events e + 2j (word y) and e + 2j + 1 (word w)
-            const unsigned long long birth_y = __ballot(b_all || wv.y < tb32);
-            const unsigned long long below_y = __ballot(d_all || wv.y < td32);
-            const unsigned long long birth_w = __ballot(b_all || wv.w < tb32);
-            const unsigned long long below_w = __ballot(d_all || wv.w < td32);
-            for (int j = 0; j < 64; ++j) {
-                event(__builtin_amdgcn_readlane(wv.x, j), (birth_y >> j) & 1ull, (below_y >> j) & 1ull);
-                if (!running())
-                    break;
-                event(__builtin_amdgcn_readlane(wv.z, j), (birth_w >> j) & 1ull, (below_w >> j) & 1ull);
-                if (!running())
-                    break;
+            const int dn_y = (b_all || wv.y < tb32) ? 1 : ((d_all || wv.y < td32) ? -1 : 0);
+            const int dn_w = (b_all || wv.w < tb32) ? 1 : ((d_all || wv.w < td32) ? -1 : 0);
+            int j = 0;
+            while (j < 64 && running()) {
+                // N moves by at most one per event, so with s = min(N - 1,
+                // n_stop - 1 - N) the next s events cannot end the run: they
+                // go in pairs without the stop test
+                const uint32_t s = min(N - 1, n_stop - 1 - N);
+                const int pairs = static_cast<int>(
+                    min(min(s >> 1, static_cast<uint32_t>(64 - j)), (max_events - e) >> 1));
+                for (int i = 0; i < pairs; ++i, ++j) {
+                    event(__builtin_amdgcn_readlane(wv.x, j), __builtin_amdgcn_readlane(dn_y, j));
+                    event(__builtin_amdgcn_readlane(wv.z, j), __builtin_amdgcn_readlane(dn_w, j));
+                }
+                e += 2u * static_cast<uint32_t>(pairs);
+                if (pairs == 0) {
+                    // near a bound: one pair with the test after each event
+                    event(__builtin_amdgcn_readlane(wv.x, j), __builtin_amdgcn_readlane(dn_y, j));
+                    ++e;
+                    if (!running())
+                        break;
+                    event(__builtin_amdgcn_readlane(wv.z, j), __builtin_amdgcn_readlane(dn_w, j));
+                    ++e;
+                    ++j;
+                }
             }
         }
         __syncthreads();
