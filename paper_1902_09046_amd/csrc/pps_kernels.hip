@@ -858,12 +858,13 @@ struct TbRegs {
 };
 
 struct TbHit {
-    int grp;   // lane holding the row's totals
-    int fld;   // the row's field in that lane
-    int row;   // 4 grp + fld
-    int col;   // slot within the row
-    bool one;  // the slot held exactly one case before the event
-    int pre;   // this lane's prefix in the row
+    int grp;         // lane holding the row's totals
+    int fld;         // the row's field in that lane
+    int row;         // 4 grp + fld
+    int col;         // slot within the row
+    int pre;         // this lane's prefix in the row
+    bool from_col;   // this lane's slot is col or after it
+    bool after_grp;  // this lane is after grp
 };
 
 // The slot holding case m (0 <= m < number of cases) in slot order.  Every
@@ -888,38 +889,54 @@ __device__ __forceinline__ TbHit tb_find(const uint16_t *pre, const TbRegs &c, u
     // (row << 16) | rank in the row: the rank is below 2^15 in the lane
     // that holds case m (other lanes' keys are never read)
     const int key = ((4 * lane + fld) << 16) | ((r - before) & 0xffff);
-    // the last lane whose lower lanes hold at most m cases (lane 0 always)
-    h.grp = 63 - __builtin_clzll(__ballot(c.excl <= static_cast<int>(m)) | 1ull);
+    // the last lane whose lower lanes hold at most m cases (lane 0 always);
+    // the lane prefixes never decrease, so the lanes after it are those
+    // whose lower lanes hold more
+    h.after_grp = c.excl > static_cast<int>(m);
+    h.grp = 63 - __builtin_clzll(__ballot(!h.after_grp) | 1ull);
     const int k = __builtin_amdgcn_readlane(key, h.grp);
     h.row = k >> 16;
     h.fld = h.row & 3;
     const int rank = k & 0xffff;
     h.pre = pre[64 * h.row + lane];
-    h.col = tb_first(__ballot(h.pre > rank));
-    // whether the slot held one case: its prefix minus the one before it, two
-    // lane reads of the row itself (the difference formed by a DPP subtract
-    // that shifts the row by one lane, wave_shr:1, into its own register gave
-    // wrong counts on gfx950, read either by v_readlane or by a compare)
-    const int below = __builtin_amdgcn_readlane(h.pre, (h.col + 63) & 63);
-    h.one = __builtin_amdgcn_readlane(h.pre, h.col) - (h.col > 0 ? below : 0) == 1;
+    // the row's prefixes never decrease either: the slots from col on are
+    // those whose prefix exceeds the rank
+    h.from_col = h.pre > rank;
+    h.col = tb_first(__ballot(h.from_col));
     return h;
 }
 
-// Adds d to slot (row, col) whose prefix row this lane holds as p, and d
-// cases / o occupied slots to the row's register totals.
-__device__ __forceinline__ void tb_add(uint16_t *pre, TbRegs &c, int grp, int fld, int row, int col,
-                                       int p, int d, int o)
+// Whether slot col of the row held one case before the event: its prefix
+// minus the one before it, two lane reads of the row itself (p, this lane's
+// prefix before the event).  (The difference formed by a DPP subtract that
+// shifts the row by one lane, wave_shr:1, into its own register gave wrong
+// counts on gfx950, read either by v_readlane or by a compare.)
+__device__ __forceinline__ bool tb_held_one(int p, int col)
+{
+    const int below = __builtin_amdgcn_readlane(p, (col + 63) & 63);
+    return __builtin_amdgcn_readlane(p, col) - (col > 0 ? below : 0) == 1;
+}
+
+// Adds d to slot (row, col) whose prefix row this lane holds as p (from_col:
+// this lane's slot is col or after it), and d cases to the row's register
+// total in lane grp (after_grp: this lane is after grp).
+__device__ __forceinline__ void tb_add(uint16_t *pre, TbRegs &c, int grp, int fld, int row, bool from_col,
+                                       bool after_grp, int p, int d)
 {
     const int lane = threadIdx.x;
-    pre[64 * row + lane] = static_cast<uint16_t>(p + (lane >= col ? d : 0));
-    const int sh = 16 * fld;
-    const uint64_t dd = static_cast<uint64_t>(static_cast<int64_t>(d)) << sh;
-    const uint64_t od = static_cast<uint64_t>(static_cast<int64_t>(o)) << sh;
-    if (lane == grp) {
+    pre[64 * row + lane] = static_cast<uint16_t>(p + (from_col ? d : 0));
+    const uint64_t dd = static_cast<uint64_t>(static_cast<int64_t>(d)) << (16 * fld);
+    if (lane == grp)
         c.tot4 += dd;
+    c.excl += after_grp ? d : 0;
+}
+
+// Adds o occupied slots to the row's register count in lane grp.
+__device__ __forceinline__ void tb_occupy(TbRegs &c, int grp, int fld, int o)
+{
+    const uint64_t od = static_cast<uint64_t>(static_cast<int64_t>(o)) << (16 * fld);
+    if (static_cast<int>(threadIdx.x) == grp)
         c.occ4 += od;
-    }
-    c.excl += lane > grp ? d : 0;
 }
 
 // A new genotype: one case in the lowest empty slot.
@@ -934,7 +951,8 @@ __device__ __forceinline__ void tb_new_genotype(uint16_t *pre, TbRegs &c)
     const int p = pre[64 * row + lane];
     const int cnt = p - __builtin_amdgcn_update_dpp(0, p, 0x138, 0xF, 0xF, false);
     const int col = tb_first(__ballot(cnt == 0));
-    tb_add(pre, c, grp, fld, row, col, p, 1, 1);
+    tb_add(pre, c, grp, fld, row, lane >= col, lane > grp, p, 1);
+    tb_occupy(c, grp, fld, 1);
 }
 
 __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__restrict__ hdr,
@@ -1025,15 +1043,19 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         auto event = [&](uint32_t wc, int dn) {
             const uint32_t m = __umulhi(wc, N);
             const TbHit h = tb_find(s_pre, c, m);
-            const int d = dn > 0 ? 1 : -1;
-            const int o = (dn <= 0 && h.one) ? -1 : 0;
-            tb_add(s_pre, c, h.grp, h.fld, h.row, h.col, h.pre, d, o);
+            tb_add(s_pre, c, h.grp, h.fld, h.row, h.from_col, h.after_grp, h.pre, dn > 0 ? 1 : -1);
             N += static_cast<uint32_t>(dn);
-            if (dn == 0) {
-                // mutation: the case leaves its genotype for a new one in
-                // the lowest empty slot (after the parent's count dropped)
-                __builtin_amdgcn_wave_barrier();
-                tb_new_genotype(s_pre, c);
+            if (dn <= 0) {
+                // a case left the slot: it is empty now if it held one
+                if (tb_held_one(h.pre, h.col))
+                    tb_occupy(c, h.grp, h.fld, -1);
+                if (dn == 0) {
+                    // mutation: the case leaves its genotype for a new one
+                    // in the lowest empty slot (after the parent's count
+                    // dropped)
+                    __builtin_amdgcn_wave_barrier();
+                    tb_new_genotype(s_pre, c);
+                }
             }
             __builtin_amdgcn_wave_barrier();
         };
@@ -1090,7 +1112,7 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
                     const uint32_t wv = __builtin_amdgcn_readlane(
                         wsel == 0 ? ws.x : (wsel == 1 ? ws.y : (wsel == 2 ? ws.z : ws.w)), j);
                     const TbHit h = tb_find(s_pre, c, __umulhi(wv, N - si));
-                    tb_add(s_pre, c, h.grp, h.fld, h.row, h.col, h.pre, -1, 0);
+                    tb_add(s_pre, c, h.grp, h.fld, h.row, h.from_col, h.after_grp, h.pre, -1);
                     if (lane == 0)
                         s_samp[si] = static_cast<float>(64 * h.row + h.col);
                     __builtin_amdgcn_wave_barrier();
