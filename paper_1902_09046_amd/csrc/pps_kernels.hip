@@ -811,22 +811,23 @@ __global__ __launch_bounds__(BLOCK) void k_simulate_cells(const EpochHeader *__r
 // A Gillespie run is a sequential Markov chain, so the lanes of a wave share
 // one run.  The genotype slots (PPS_TB_MAX_POP of them) are cut into rows of
 // 64; LDS holds each row as the inclusive prefix sums of its slots' counts
-// (uint16), and registers hold, four rows per lane, the rows' case totals and
-// occupied-slot counts, plus each lane's exclusive prefix of the totals over
-// the lanes before it.  The case chosen by an event is found by a 64-way
-// descent: a ballot over the lane prefixes picks the lane, a scalar compare
-// over its four totals the row, and a ballot over the row's prefixes the slot
-// -- the same slot as the paper's linear scan over the genotype weights.  An
-// update adds +-1 to the row's prefixes from the slot on (one LDS row
-// read-modify-write) and to the register totals.  The lowest empty slot for
-// a new genotype is found the same way from the occupied counts.  The event
-// words of 64 Philox blocks (128 events) are drawn at once, one block per
-// lane, and read out by lane index.  Runs end when the population reaches the
-// stop size, dies out or hits the event cap, and the workgroup takes the next
-// draw from the tile queue at once, so runs of very different lengths balance
-// across the machine; the queue is walked twice, the runs predicted from theta
-// to be long first.  The workgroup is one wave: its LDS operations complete
-// in order, and wave barriers keep the compiler from reordering them.
+// (uint16), and registers hold, four rows per lane, the lane's cumulative
+// case counts through each row and the rows' occupied-slot counts, plus each
+// lane's exclusive prefix of the case counts over the lanes before it.  The
+// case chosen by an event is found by a 64-way descent: a ballot over the
+// lane prefixes picks the lane, the lane's compares of its cumulative counts
+// the row, and a ballot over the row's prefixes the slot -- the same slot as
+// the paper's linear scan over the genotype weights.  An update adds +-1 to
+// the row's prefixes from the slot on (one LDS row read-modify-write) and to
+// the register counts.  The lowest empty slot for a new genotype is found the
+// same way from the occupied counts.  The event words of 64 Philox blocks
+// (128 events) are drawn at once, one block per lane, and read out by lane
+// index.  Runs end when the population reaches the stop size, dies out or
+// hits the event cap, and the workgroup takes the next draw from the tile
+// queue at once, so runs of very different lengths balance across the
+// machine; the queue is walked twice, the runs predicted from theta to be
+// long first.  The workgroup is one wave: its LDS operations complete in
+// order, and wave barriers keep the compiler from reordering them.
 // ===========================================================================
 constexpr int TB_BLOCK = 64;
 constexpr int TB_SLOTS = PPS_TB_MAX_POP;
@@ -852,10 +853,17 @@ __device__ __forceinline__ int tb_first(unsigned long long mask)
 
 // Register half of the counts: rows 4 lane + j, j = 0..3, in 16-bit fields.
 struct TbRegs {
-    uint64_t tot4;  // cases per row
+    uint64_t cum4;  // cases in the lane's rows up to and including row j
     uint64_t occ4;  // occupied slots per row (rows past the population: 64)
     int excl;       // cases in the rows of lower lanes
 };
+
+// Two 16-bit lanes of a 32-bit register: a - b in each (v_pk_sub_u16).
+typedef unsigned short tb_u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t tb_sub16x2(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(tb_u16x2, a) - __builtin_bit_cast(tb_u16x2, b));
+}
 
 struct TbHit {
     int grp;         // lane holding the row's totals
@@ -868,26 +876,26 @@ struct TbHit {
 };
 
 // The slot holding case m (0 <= m < number of cases) in slot order.  Every
-// lane works out, from its own four row totals, which of its rows would hold
-// case m and its rank there (VALU work beside the ballot that picks the
+// lane works out, from its own cumulative row counts, which of its rows would
+// hold case m and its rank there (VALU work beside the ballot that picks the
 // lane); one lane read then takes the picked lane's (row, rank).
 __device__ __forceinline__ TbHit tb_find(const uint16_t *pre, const TbRegs &c, uint32_t m)
 {
     const int lane = threadIdx.x;
     TbHit h;
     const int r = static_cast<int>(m) - c.excl;
-    const int f0 = static_cast<int>(c.tot4 & 0xffffu);
-    const int f1 = static_cast<int>((c.tot4 >> 16) & 0xffffu);
-    const int f2 = static_cast<int>((c.tot4 >> 32) & 0xffffu);
-    // all ones when r >= the cases of the lane's first 1, 2, 3 rows (the
-    // sign of a difference of values below 2^15; no branches)
-    const int m0 = (f0 - 1 - r) >> 31;
-    const int m1 = (f0 + f1 - 1 - r) >> 31;
-    const int m2 = (f0 + f1 + f2 - 1 - r) >> 31;
-    const int fld = -(m0 + m1 + m2);
-    const int before = (f0 & m0) + (f1 & m1) + (f2 & m2);
-    // (row << 16) | rank in the row: the rank is below 2^15 in the lane
-    // that holds case m (other lanes' keys are never read)
+    // C_j - r - 1 in each 16-bit field: negative (bit 15 of the field set)
+    // exactly when the lane's first j + 1 rows hold at most r cases.  In the
+    // lane that holds case m, 0 <= r < C_3 <= 2^14, so every difference
+    // fits in 16 signed bits (other lanes' keys are never read).
+    const uint32_t r1 = static_cast<uint32_t>(r + 1) & 0xffffu;
+    const uint32_t rr = r1 | (r1 << 16);
+    const uint32_t dlo = tb_sub16x2(static_cast<uint32_t>(c.cum4), rr);
+    const uint32_t dhi = tb_sub16x2(static_cast<uint32_t>(c.cum4 >> 32), rr);
+    const int fld = static_cast<int>(((dlo >> 15) & 1u) + (dlo >> 31) + ((dhi >> 15) & 1u));
+    // cases in the rows before row fld of the lane: C_{fld-1}, 0 for fld 0
+    const int before = static_cast<int>(((c.cum4 << 16) >> (16 * fld)) & 0xffffu);
+    // (row << 16) | rank in the row
     const int key = ((4 * lane + fld) << 16) | ((r - before) & 0xffff);
     // the last lane whose lower lanes hold at most m cases (lane 0 always);
     // the lane prefixes never decrease, so the lanes after it are those
@@ -918,16 +926,20 @@ __device__ __forceinline__ bool tb_held_one(int p, int col)
 }
 
 // Adds d to slot (row, col) whose prefix row this lane holds as p (from_col:
-// this lane's slot is col or after it), and d cases to the row's register
-// total in lane grp (after_grp: this lane is after grp).
+// this lane's slot is col or after it), d cases to the register counts of
+// the row in lane grp, and d to the lower-lane counts of the lanes after grp
+// (after_grp).
 __device__ __forceinline__ void tb_add(uint16_t *pre, TbRegs &c, int grp, int fld, int row, bool from_col,
                                        bool after_grp, int p, int d)
 {
     const int lane = threadIdx.x;
     pre[64 * row + lane] = static_cast<uint16_t>(p + (from_col ? d : 0));
-    const uint64_t dd = static_cast<uint64_t>(static_cast<int64_t>(d)) << (16 * fld);
+    // d to the cumulative counts of rows fld..3 (never below zero: a case
+    // leaves only a row that holds it)
+    const uint64_t ones = 0x0001000100010001ull;
+    const uint64_t dd = (d > 0 ? ones : 0ull - ones) << (16 * fld);
     if (lane == grp)
-        c.tot4 += dd;
+        c.cum4 += dd;
     c.excl += after_grp ? d : 0;
 }
 
@@ -1029,7 +1041,7 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
         for (int i = lane; i < nr_used * 64; i += TB_BLOCK)
             s_pre[i] = i < 64 ? static_cast<uint16_t>(N) : 0;
         TbRegs c;
-        c.tot4 = lane == 0 ? N : 0;
+        c.cum4 = lane == 0 ? 0x0001000100010001ull * N : 0;
         c.occ4 = lane == 0 ? 1 : 0;
         c.excl = lane == 0 ? 0 : static_cast<int>(N);
 #pragma unroll
@@ -1038,12 +1050,13 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
                 c.occ4 |= 64ull << (16 * k);
         __syncthreads();
         uint32_t e = 0;
-        // one event: case word wc and the population step dn (+1 birth,
-        // -1 death, 0 mutation); dn is wave-uniform, so N stays scalar
-        auto event = [&](uint32_t wc, int dn) {
+        // one event: case word wc, the population step dn (+1 birth, -1
+        // death, 0 mutation) and the chosen slot's step d (+1 birth, -1
+        // otherwise); both are wave-uniform, so N stays scalar
+        auto event = [&](uint32_t wc, int dn, int d) {
             const uint32_t m = __umulhi(wc, N);
             const TbHit h = tb_find(s_pre, c, m);
-            tb_add(s_pre, c, h.grp, h.fld, h.row, h.from_col, h.after_grp, h.pre, dn > 0 ? 1 : -1);
+            tb_add(s_pre, c, h.grp, h.fld, h.row, h.from_col, h.after_grp, h.pre, d);
             N += static_cast<uint32_t>(dn);
             if (dn <= 0) {
                 // a case left the slot: it is empty now if it held one
@@ -1069,6 +1082,7 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
                                            PURPOSE_TB_EVENT);
             const int dn_y = (b_all || wv.y < tb32) ? 1 : ((d_all || wv.y < td32) ? -1 : 0);
             const int dn_w = (b_all || wv.w < tb32) ? 1 : ((d_all || wv.w < td32) ? -1 : 0);
+            const int d_y = dn_y > 0 ? 1 : -1, d_w = dn_w > 0 ? 1 : -1;
             int j = 0;
             while (j < 64 && running()) {
                 // N moves by at most one per event, so with s = min(N - 1,
@@ -1078,17 +1092,21 @@ __global__ __launch_bounds__(TB_BLOCK) void k_simulate_tb(const EpochHeader *__r
                 const int pairs = static_cast<int>(
                     min(min(s >> 1, static_cast<uint32_t>(64 - j)), (max_events - e) >> 1));
                 for (int i = 0; i < pairs; ++i, ++j) {
-                    event(__builtin_amdgcn_readlane(wv.x, j), __builtin_amdgcn_readlane(dn_y, j));
-                    event(__builtin_amdgcn_readlane(wv.z, j), __builtin_amdgcn_readlane(dn_w, j));
+                    event(__builtin_amdgcn_readlane(wv.x, j), __builtin_amdgcn_readlane(dn_y, j),
+                          __builtin_amdgcn_readlane(d_y, j));
+                    event(__builtin_amdgcn_readlane(wv.z, j), __builtin_amdgcn_readlane(dn_w, j),
+                          __builtin_amdgcn_readlane(d_w, j));
                 }
                 e += 2u * static_cast<uint32_t>(pairs);
                 if (pairs == 0) {
                     // near a bound: one pair with the test after each event
-                    event(__builtin_amdgcn_readlane(wv.x, j), __builtin_amdgcn_readlane(dn_y, j));
+                    event(__builtin_amdgcn_readlane(wv.x, j), __builtin_amdgcn_readlane(dn_y, j),
+                          __builtin_amdgcn_readlane(d_y, j));
                     ++e;
                     if (!running())
                         break;
-                    event(__builtin_amdgcn_readlane(wv.z, j), __builtin_amdgcn_readlane(dn_w, j));
+                    event(__builtin_amdgcn_readlane(wv.z, j), __builtin_amdgcn_readlane(dn_w, j),
+                          __builtin_amdgcn_readlane(d_w, j));
                     ++e;
                     ++j;
                 }
