@@ -467,8 +467,11 @@ int pps_wip_test(const pps_bioassay *model, const double *lambda, int n_lambda, 
  * u = s_p w_p - s_n w_n (centred gamma shocks) discretised as in
  * Eq. BEGE_LL_approx on the n_omega + 1 nodes w^j = w^0 + j dw,
  * w^0 = 1e-4 - p s_p, dw = (10 s_p sqrt(p) - w^0) / (n_omega - 1) (the paper
- * uses n_omega = 100), with P(a, x) evaluated to full FP64 accuracy (power
- * series for x < a + 1, continued fraction otherwise).  A step whose shapes
+ * uses n_omega = 100), with the increments of P(a, x) between nodes
+ * evaluated to full FP64 accuracy (the density's Taylor series integrated
+ * over the interval where it converges fast, else the difference of two
+ * values of P from its power series for x < a + 1 or of Q = 1 - P from its
+ * continued fraction otherwise).  A step whose shapes
  * are not positive, or whose density estimate is not positive, has
  * log f = -inf, and so has every step when s_p or s_n is not positive; the
  * sum is then -inf.
@@ -499,7 +502,8 @@ int pps_set_timing(int enable);
  * density kernel and stores in *ops (host) the FP64 operations that the
  * lanes executed as the algorithm states them: an FMA counts 2, a division
  * 1, a series term of P(a, x) 5 (plus 1 per block of 8), a continued-fraction
- * step 10 (plus 4 per block of 4), and exp, log, lgamma and sqrt 1 each.
+ * step 10 (plus 4 per block of 4), a term of the density's Taylor series 8
+ * (plus 3 per block of 4), and exp, log, lgamma and sqrt 1 each.
  * Arguments and errors as pps_bege_loglik (ops must not be NULL). */
 int pps_bege_count_ops(const double *theta, int n_theta, const double *r, int T, int n_omega,
                        double *ops, void *stream);

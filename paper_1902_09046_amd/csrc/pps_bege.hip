@@ -185,6 +185,71 @@ __device__ __attribute__((noinline)) double igam_q_upper(double a, double x, dou
     return exp(e) * f;
 }
 
+// The Gamma(a, 1) density integrated over one node interval, relative to its
+// value at one end, by the Taylor series of the density about that end (the
+// distribution function of Eq. BEGE_LL_approx needs only the increments of
+// P(a, .) between consecutive nodes, and the integral of its density over the
+// interval is such an increment).  About the end X where the density is the
+// smaller one (the left end x if x < a - 1, where the density rises, else the
+// right end x + dx), the density at distance t into the interval is its value
+// at X times
+//   k(t) = (1 - s t / X)^(a - 1) e^(s t),   s = -1 about the left end, +1 about the right,
+// a function that grows into the interval, so the series' terms keep one sign
+// up to the small curvature term.  From (X - s t) k' = s (X - a + 1 - s t) k,
+// the coefficients scaled by dx^m, e_m = k_m dx^m, follow
+//   e_0 = 1,  e_{m+1} = ((B + s m) beta e_m - beta dx e_{m-1}) / (m + 1),
+//   B = s (X - a + 1),  beta = dx / X,
+// and the interval's integral is dx sum_m e_m / (m + 1), the density at the
+// other end the value at X times sum_m e_m.  The series converges for beta < 1
+// (the singularity of k at t = s X); the caller takes it where beta <= 1/2 and
+// the log-density changes by little over the interval, and it stops once two
+// consecutive terms are below 2^-54 of the integral, or gives up (ok = false)
+// after TAYLOR_BLOCKS blocks of four terms.
+constexpr int TAYLOR_BLOCKS = 12;
+constexpr double TAYLOR_L1 = 8.0;    // bound on |d ln g / dx| dx over the interval
+constexpr double TAYLOR_CURV = 4.0;  // bound on |a - 1| beta^2 (the curvature term)
+constexpr double OPS_TAYLOR_TERM = 8.0, OPS_TAYLOR_CHECK = 3.0;
+
+struct TaylorSum {
+    double I;  // sum_m e_m / (m + 1)
+    double H;  // sum_m e_m
+    bool ok;
+};
+
+template <bool COUNT>
+__device__ __attribute__((noinline)) TaylorSum gamma_taylor(double B, double beta, double dx, double s,
+                                                            OpCount<COUNT> &ops)
+{
+    const double gam = beta * dx;
+    const double step = s * beta;
+    double em1 = 0.0, e = 1.0, t = B * beta;
+    TaylorSum r;
+    r.I = 1.0;
+    r.H = 1.0;
+    r.ok = false;
+    int blocks = 0;
+#pragma unroll
+    for (int blk = 0; blk < TAYLOR_BLOCKS; ++blk) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int m = 4 * blk + u;  // e_{m+1} from e_m and e_{m-1}
+            const double en = fma(t, e, -gam * em1) * (1.0 / (m + 1));
+            t += step;
+            em1 = e;
+            e = en;
+            r.I = fma(e, 1.0 / (m + 2), r.I);
+            r.H += e;
+        }
+        blocks = blk + 1;
+        if (fabs(e) + fabs(em1) <= 0x1p-54 * r.I) {
+            r.ok = true;
+            break;
+        }
+    }
+    ops.add(4.0 + blocks * (4.0 * OPS_TAYLOR_TERM + OPS_TAYLOR_CHECK));
+    return r;
+}
+
 // Cost class of a chunk from the largest shape p among its valid steps: the
 // series of P(p, x) near x = p need about sqrt(p) terms, so the class is
 // 2 log2(max p) + 16 clamped to [1, 63] (quarter octaves of sqrt p); a chunk
@@ -398,29 +463,77 @@ __device__ double bege_density(double u, double p, double n, double sp, double s
     const double zc = 1.0 + sqrt(fabs(c));
     const double d = 2.0 * h / sn;
     ops.add(2.0 * OPS_LGAMMA + 30.0);
-    // The increments of P(p, .) over the nodes: below x = p + 1 as the
-    // difference of two P (series), above it as the difference of two Q
-    // (continued fraction), where the two P would be within rounding of 1;
-    // the one increment that crosses p + 1 as (1 - Q) - P.
+    // The increments of P(p, .) over the nodes.  Where the Taylor series of
+    // the density converges fast (gamma_taylor), the increment is the
+    // density's integral over the interval, the density being carried from
+    // node to node by the same series (evaluated directly where a run of such
+    // intervals starts, and again before it would reach the denormals).
+    // Elsewhere (the first nodes, whose intervals reach too close to 0, and
+    // where the log-density changes fast): below x = p + 1 as the difference
+    // of two P (series), above it as the difference of two Q (continued
+    // fraction), where the two P would be within rounding of 1; the one
+    // increment that crosses p + 1 as (1 - Q) - P.
+    const double am1 = p - 1.0;
     const double xsplit = p + 1.0;
     double x = (w0 + psp) / sp;
-    bool upper = x >= xsplit;
-    double prev = upper ? igam_q_upper(p, x, lgp, ops) : igam_p(p, x, lgp, ops);
+    bool have_prev = false, upper = false, have_g = false;
+    double prev = 0.0, g = 0.0;
     double acc = 0.0;
     for (int j = 1; j <= n_omega; ++j) {
-        x = (w0 + j * dw + psp) / sp;
-        ops.add(5.0);
-        double dF;
-        if (x >= xsplit) {
-            const double q = igam_q_upper(p, x, lgp, ops);
-            dF = upper ? prev - q : (1.0 - q) - prev;
-            prev = q;
-            upper = true;
-        } else {
-            const double pv = igam_p(p, x, lgp, ops);
-            dF = pv - prev;
-            prev = pv;
+        const double xn = (w0 + j * dw + psp) / sp;
+        const double dx = xn - x;
+        ops.add(6.0);
+        double dF = 0.0;
+        bool done = false;
+        const bool left = x < am1;
+        const double X = left ? x : xn;
+        if (X > 0.0 && dx > 0.0) {
+            const double rX = 1.0 / X;
+            const double beta = dx * rX;
+            const double l1 = fabs(fma(am1, rX, -1.0)) * dx;
+            ops.add(8.0);
+            if (beta <= 0.5 && l1 <= TAYLOR_L1 && fabs(am1) * beta * beta <= TAYLOR_CURV) {
+                if (!have_g) {
+                    g = exp(am1 * log(x) - x - lgp);  // the density at x
+                    have_g = true;
+                    ops.add(OPS_LOG + OPS_EXP + 3.0);
+                }
+                const double sg = left ? -1.0 : 1.0;
+                const TaylorSum ts = gamma_taylor(sg * (X - am1), beta, dx, sg, ops);
+                if (ts.ok) {
+                    if (left) {
+                        dF = g * dx * ts.I;
+                        g *= ts.H;
+                    } else {
+                        g /= ts.H;
+                        dF = g * dx * ts.I;
+                    }
+                    ops.add(3.0);
+                    have_g = g > 0x1p-1000;
+                    have_prev = false;
+                    done = true;
+                }
+            }
         }
+        if (!done) {
+            have_g = false;
+            if (!have_prev) {
+                upper = x >= xsplit;
+                prev = upper ? igam_q_upper(p, x, lgp, ops) : igam_p(p, x, lgp, ops);
+                have_prev = true;
+            }
+            if (xn >= xsplit) {
+                const double q = igam_q_upper(p, xn, lgp, ops);
+                dF = upper ? prev - q : (1.0 - q) - prev;
+                prev = q;
+                upper = true;
+            } else {
+                const double pv = igam_p(p, xn, lgp, ops);
+                dF = pv - prev;
+                prev = pv;
+            }
+        }
+        x = xn;
         if (dF == 0.0)
             continue;
         const double base = w0 + (j - 1) * dw - u + nsn;

@@ -6,8 +6,10 @@ but not in the same way: the oracle sums F(u + h) and F(u - h) separately and
 subtracts; the device accumulates the differences of the tails directly, each
 one the Gamma(n, 1) mass of a short interval (a Taylor series about its
 midpoint, or the difference of two upper functions Q in the upper tail),
-evaluates P(a, x) by division-free recurrences, and uses different
-log/exp/lgamma implementations.
+forms most increments of P(p, .) between nodes as the integral of the
+density's Taylor series over the interval (the rest by division-free
+recurrences for P and Q), and uses different log/exp/lgamma
+implementations.
 
 * Where the oracle's FP64 difference exceeds 2^-26 it is its result.  The
   leading factor exp(a ln x - x - ln Gamma(a)) of P carries an absolute
