@@ -77,6 +77,22 @@ def test_tb_edges(P, torch):
     assert (o["status"] == oracle.TB_EXTINCT).sum() > 16
 
 
+@pytest.mark.parametrize("n_stop,max_events,x0", [(2, 1 << 20, 1.0), (3, 1 << 20, 1.0), (200, 1, 1.0),
+                                                  (200, 127, 1.0), (200, 129, 5.0), (400, 255, 1.0),
+                                                  (500, 4001, 1.0), (300, 1 << 20, 299.0)])
+def test_tb_stop_test_edges(P, torch, n_stop, max_events, x0):
+    # the kernel tests the stop rule once per stretch of events that cannot
+    # end the run (the count moves by one per event): stop sizes of 2 and 3
+    # and a start one case below the stop size make every stretch one event
+    # long; odd caps and caps inside a 64-event half end a run mid-stretch
+    spec = W.tb_spec(n_stop=n_stop, n_sample=min(40, n_stop), max_events=max_events, x0=x0)
+    o = check(P, spec, W.SAMPLING_SEED, 11, 48, y_obs=[0.5, 0.9],
+              label=f"K={n_stop} cap={max_events} x0={x0:g}")
+    assert np.all(o["events"] <= max_events)
+    if max_events < 1 << 20:
+        assert np.any(o["status"] == oracle.TB_TRUNCATED)
+
+
 def test_tb_point_prior_reproduces_the_observed_summaries(P, torch):
     g = observed()["tb_K10000_n473"]
     spec = W.tb_point_spec(tuple(g["theta"]), n_stop=g["n_stop"], n_sample=g["n_sample"])
