@@ -87,7 +87,11 @@ __device__ __forceinline__ Words4 stream_block(StreamKey key, uint64_t draw, uin
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float uniform_f32(uint32_t w)
 {
-    return __builtin_fmaf(static_cast<float>(w >> 9), 0x1p-23f, 0x1p-24f);
+    // 0x3F800000 | (w >> 9) is 1 + k 2^-23, k = w >> 9 (one funnel shift of
+    // the pair 0x7F:w by 9 bits); subtracting 1 - 2^-24 leaves (2k+1) 2^-24
+    // exactly (the operands lie within a factor 2 of each other)
+    const uint32_t one_k = __builtin_amdgcn_alignbit(0x7Fu, w, 9u);
+    return __builtin_bit_cast(float, one_k) - 0x1.fffffep-1f;
 }
 
 __device__ __forceinline__ double uniform_f64(uint32_t w)
