@@ -85,13 +85,20 @@ __device__ __forceinline__ Words4 stream_block(StreamKey key, uint64_t draw, uin
 // Uniforms on the open unit interval: the top 23 bits pick the cell midpoint
 // (2k+1) 2^-24; exact in FP32 and FP64.
 // ---------------------------------------------------------------------------
+// Two instruction sequences give the same value.  FUNNEL: 0x3F800000 | (w >>
+// 9) is 1 + k 2^-23, k = w >> 9 (one funnel shift of the pair 0x7F:w by 9
+// bits), and subtracting 1 - 2^-24 leaves (2k+1) 2^-24 exactly (the operands
+// lie within a factor 2 of each other): two instructions.  Otherwise shift,
+// convert and FMA: three, which the GARCH kernel's schedule runs faster.
+template <bool FUNNEL = true>
 __device__ __forceinline__ float uniform_f32(uint32_t w)
 {
-    // 0x3F800000 | (w >> 9) is 1 + k 2^-23, k = w >> 9 (one funnel shift of
-    // the pair 0x7F:w by 9 bits); subtracting 1 - 2^-24 leaves (2k+1) 2^-24
-    // exactly (the operands lie within a factor 2 of each other)
-    const uint32_t one_k = __builtin_amdgcn_alignbit(0x7Fu, w, 9u);
-    return __builtin_bit_cast(float, one_k) - 0x1.fffffep-1f;
+    if constexpr (FUNNEL) {
+        const uint32_t one_k = __builtin_amdgcn_alignbit(0x7Fu, w, 9u);
+        return __builtin_bit_cast(float, one_k) - 0x1.fffffep-1f;
+    } else {
+        return __builtin_fmaf(static_cast<float>(w >> 9), 0x1p-23f, 0x1p-24f);
+    }
 }
 
 __device__ __forceinline__ double uniform_f64(uint32_t w)
@@ -102,10 +109,11 @@ __device__ __forceinline__ double uniform_f64(uint32_t w)
 // Box-Muller in FP32 with the hardware transcendentals: v_log_f32 is log2,
 // v_sin_f32 / v_cos_f32 take their argument in revolutions (x -> sin(2 pi x)),
 // so the angle 2 pi u1 needs no range reduction.
+template <bool FUNNEL = true>
 __device__ __forceinline__ void box_muller_f32(uint32_t w0, uint32_t w1, float &z0, float &z1)
 {
-    const float u0 = uniform_f32(w0);
-    const float u1 = uniform_f32(w1);
+    const float u0 = uniform_f32<FUNNEL>(w0);
+    const float u1 = uniform_f32<FUNNEL>(w1);
     // -2 ln u0 = log2(u0) * (-2 ln 2)
     const float r = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(u0) * -1.38629436111989061883f);
     z0 = r * __builtin_amdgcn_cosf(u1);
@@ -122,12 +130,13 @@ __device__ __forceinline__ double box_muller_f64_first(uint32_t w0, uint32_t w1)
 }
 
 // Four path normals z_{4b..4b+3} of one draw.
+template <bool FUNNEL = true>
 __device__ __forceinline__ void path_normals4(StreamKey key, uint64_t draw, uint32_t block,
                                               float &z0, float &z1, float &z2, float &z3)
 {
     const Words4 w = stream_block(key, draw, block, PURPOSE_PATH);
-    box_muller_f32(w.x, w.y, z0, z1);
-    box_muller_f32(w.z, w.w, z2, z3);
+    box_muller_f32<FUNNEL>(w.x, w.y, z0, z1);
+    box_muller_f32<FUNNEL>(w.z, w.w, z2, z3);
 }
 
 // Four normals z_{4b..4b+3} of cell `cell` of one draw.

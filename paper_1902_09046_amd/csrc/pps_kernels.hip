@@ -164,7 +164,8 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
             float z[4];
-            path_normals4(key, draw, static_cast<uint32_t>(blk * 5 + p), z[0], z[1], z[2], z[3]);
+            path_normals4<false>(key, draw, static_cast<uint32_t>(blk * 5 + p), z[0], z[1], z[2],
+                                 z[3]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int jj = 4 * p + j;  // position in the 20-step block
@@ -196,7 +197,7 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             float z[4];
-            path_normals4(key, draw, static_cast<uint32_t>(p), z[0], z[1], z[2], z[3]);
+            path_normals4<false>(key, draw, static_cast<uint32_t>(p), z[0], z[1], z[2], z[3]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (4 * p + j < PPS_GARCH_LAGS) {
