@@ -133,6 +133,32 @@ def measured_traffic(key: str):
     return e["bytes_per_launch"]
 
 
+# Published FP32 vector peak (an FMA counted as two flops).
+FP32_PEAK_TFLOPS = 157.3
+
+
+def measured_fp32(key: str, kernel_ms: float):
+    """The FP32 FLOP view of a kernel's VALU work from the rocprofv3 counter
+    run under profiles/ (64 x (ADD_F32 + MUL_F32 + TRANS_F32 + 2 FMA_F32) per
+    dispatch), rated against this run's kernel time, with the instruction
+    classes the FLOP counters do not see; null once the sources changed."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path) or not kernel_ms or kernel_ms <= 0:
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(key)
+    if not e or "fp32" not in e or \
+            e.get("kernel_source_sha256") != kernel_source_digest(e.get("sources", "simulate")):
+        return None
+    x = e["fp32"]
+    tflops = x["flops_per_launch"] / (kernel_ms * 1e-3) / 1e12
+    return {"tflops": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
+            "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+            "weighted_issue_frac": x.get("weighted_issue_frac"),
+            "insts_per_launch": x.get("insts")}
+
+
 def measured_issue(key: str):
     """VALU issue fraction of a kernel from the rocprofv3 counter runs under
     profiles/ (wave64 VALU instructions x 2 SIMD cycles, FP64 arithmetic x 4,
@@ -358,6 +384,7 @@ def main():
                 "unit": "TOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic("k_simulate_path_abc_n1e7"),
                 "valu_issue_frac_counters": measured_issue("k_simulate_path_abc_n1e7"),
+                "fp32_flops_counters": measured_fp32("k_simulate_path_abc_n1e7", k_ms),
                 "kernel": "k_simulate<block=%d,path,dpl=%d,unroll=%d>" % tuple(tune["best"]),
                 "kernel_ms": round(k_ms, 4),
                 "ops_per_draw": ops_per_draw(steps_em, n_obs)}
@@ -434,7 +461,8 @@ def main():
             "valu_frac_one_normal_set": round(pops1 / (kms * 1e-3) / VALU_PEAK_OPS, 4),
             "kernel": "k_simulate_group<256,%d>" % GROUP_LPL,
             "traffic": measured_traffic("k_simulate_group_pvalue_64x1e6"),
-            "valu_issue_frac_counters": measured_issue("k_simulate_group_pvalue_64x1e6")}
+            "valu_issue_frac_counters": measured_issue("k_simulate_group_pvalue_64x1e6"),
+            "fp32_flops_counters": measured_fp32("k_simulate_group_pvalue_64x1e6", kms)}
         if args.cpu_sample > 0:
             # the oracle on the first 1e4 draws of every lambda, timed, and the
             # device's counts on the same draws: equal for lambda <= 1; above,
@@ -468,7 +496,8 @@ def main():
             "valu_frac": round(gops / (kms * 1e-3) / VALU_PEAK_OPS, 4),
             "kernel": "k_simulate<256,garch>",
             "traffic": measured_traffic("k_simulate_garch_L2000_n1e6"),
-            "valu_issue_frac_counters": measured_issue("k_simulate_garch_L2000_n1e6")}
+            "valu_issue_frac_counters": measured_issue("k_simulate_garch_L2000_n1e6"),
+            "fp32_flops_counters": measured_fp32("k_simulate_garch_L2000_n1e6", kms)}
         if args.cpu_sample > 0:
             # the device's FP32 streaming summaries of the first 1e4 draws
             # against the oracle's FP64 two-pass ones, each error divided by
@@ -518,6 +547,7 @@ def main():
               "kernel": f"k_simulate_cells<{cell_block}>",
               "traffic": measured_traffic("k_simulate_cells_toggle_n8064"),
               "valu_issue_frac_counters": measured_issue("k_simulate_cells_toggle_n8064"),
+              "fp32_flops_counters": measured_fp32("k_simulate_cells_toggle_n8064", kms),
               "paper_context": {"table": "A.1", "seconds": 69.0, "cpu": "Xeon Gold 6140",
                                 "threads": 16, "code": "C, AVX512, FP64",
                                 "ratio_to_gpu": round(69.0 / wall, 1)}}
