@@ -62,3 +62,26 @@ def test_traffic_is_reported_only_for_the_measured_sources(monkeypatch):
         assert e["bytes_per_launch"] == round((e["fetch_kib"] * e["fetch_scale"] +
                                                e["write_kib"] * e["write_scale"]) * 1024)
     assert bench.measured_traffic("no such kernel") is None
+
+
+def test_fp32_counter_view_follows_the_measured_sources(monkeypatch):
+    """The FP32 FLOP view (64 x (ADD + MUL + TRANS + 2 FMA) wave instructions
+    per dispatch) is rated against the run's own kernel time and reported
+    only for the sources it was measured on."""
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+        table = json.load(f)
+    entries = {k: e for k, e in table.items() if isinstance(e, dict) and "fp32" in e}
+    assert "k_simulate_path_abc_n1e7" in entries
+    for key, e in entries.items():
+        x = e["fp32"]
+        # the flops are the counters' FP32 arithmetic classes, FMA twice
+        assert x["flops_per_launch"] >= 64 * x["insts"]["f32_add_mul_fma"]
+        assert x["insts"]["valu"] >= x["insts"]["f32_add_mul_fma"] + x["insts"]["trans_f32"]
+        monkeypatch.setattr(bench, "kernel_source_digest", lambda fam, d=e["kernel_source_sha256"]: d)
+        v = bench.measured_fp32(key, 2.0)
+        assert v["tflops"] == pytest.approx(x["flops_per_launch"] / 2e-3 / 1e12, rel=1e-3)
+        assert v["frac"] == pytest.approx(v["tflops"] / 157.3, abs=1e-4)
+        assert bench.measured_fp32(key, 4.0)["tflops"] == pytest.approx(v["tflops"] / 2, rel=1e-3)
+        monkeypatch.setattr(bench, "kernel_source_digest", lambda fam: "0" * 64)
+        assert bench.measured_fp32(key, 2.0) is None
+    assert bench.measured_fp32("no such kernel", 1.0) is None
