@@ -79,9 +79,9 @@ def test_fp32_counter_view_follows_the_measured_sources(monkeypatch):
         assert x["insts"]["valu"] >= x["insts"]["f32_add_mul_fma"] + x["insts"]["trans_f32"]
         monkeypatch.setattr(bench, "kernel_source_digest", lambda fam, d=e["kernel_source_sha256"]: d)
         v = bench.measured_fp32(key, 2.0)
-        assert v["tflops"] == pytest.approx(x["flops_per_launch"] / 2e-3 / 1e12, rel=1e-3)
+        assert v["tflops"] == pytest.approx(x["flops_per_launch"] / 2e-3 / 1e12, rel=1e-3, abs=1e-3)
         assert v["frac"] == pytest.approx(v["tflops"] / 157.3, abs=1e-4)
-        assert bench.measured_fp32(key, 4.0)["tflops"] == pytest.approx(v["tflops"] / 2, rel=1e-3)
+        assert bench.measured_fp32(key, 4.0)["tflops"] == pytest.approx(v["tflops"] / 2, rel=1e-3, abs=1e-3)
         monkeypatch.setattr(bench, "kernel_source_digest", lambda fam: "0" * 64)
         assert bench.measured_fp32(key, 2.0) is None
     assert bench.measured_fp32("no such kernel", 1.0) is None
