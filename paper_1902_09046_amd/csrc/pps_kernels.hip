@@ -127,8 +127,8 @@ __device__ __forceinline__ void sim_normal_mean(const JobDev *__restrict__ J, St
 // unrounded: with persistence alpha+beta near 1 the recursion keeps an error
 // in its state for ~1/(1-alpha-beta) steps, so an FP32 state (or FP32
 // alpha, beta) moves the variance and kurtosis of near-integrated draws by
-// up to ~1e-4.  Normals, returns s_t and every summary stay FP32; the two
-// FP64 FMAs issue at the rate of non-packed FP32 ones on this chip.
+// up to ~1e-4.  Normals, returns s_t and every summary stay FP32; the state
+// costs two FP64 FMAs and two conversions per step.
 // Streaming summaries: plain FP32 sums over 20-step blocks folded into Kahan
 // totals; b_t = s_t^2 - 1 kept in a 10-deep register ring for the lag
 // products; the first 10 b_t are recomputed from the stream at the end for
