@@ -37,20 +37,23 @@ FP64_PEAK_TFLOPS = 78.6
 
 # Algorithmic VALU lane-operations of the logistic path (see the design notes):
 #   Philox4x32-10 call: 10 rounds x (2 widening 32x32->64 multiplies + 4 xor) = 60
-#   Box-Muller pair: 2 x (shift, convert, fma) + log2, scale, sqrt, cos, sin,
-#                    2 multiplies = 12   -> 24 per call (4 normals)
+#   Box-Muller pair: radius uniform (funnel shift, subtract), log2, scale,
+#                    sqrt, angle (funnel shift, and-or, and for two of the
+#                    three pairs a shift of word 3), cos, sin, 2 multiplies
+#                    = 12   -> 36 per call (6 normals)
 #   Euler-Maruyama step: 3 fma + max = 4
 #   observation: difference, Kahan (4) for rho^2, Kahan (4) for the sum = 9
 #   prior draw: 3 Philox calls + 3 uniform transforms ~ 250 per draw
 OPS_PHILOX = 60
 OPS_BM_PAIR = 12
+NORMALS_PER_CALL = 6
 OPS_EM = 4
 OPS_OBS = 9
 OPS_PRIOR = 250
 
 
 def ops_per_draw(steps: int, n_obs: int) -> float:
-    per_step = (OPS_PHILOX + 2 * OPS_BM_PAIR) / 4.0 + OPS_EM
+    per_step = (OPS_PHILOX + NORMALS_PER_CALL // 2 * OPS_BM_PAIR) / NORMALS_PER_CALL + OPS_EM
     return steps * per_step + n_obs * OPS_OBS + OPS_PRIOR
 
 
@@ -67,7 +70,7 @@ OPS_PRIOR_MEMBER = 7
 
 def ops_per_group_draw(steps: int, n_obs: int, lpl: int = GROUP_LPL) -> float:
     """Executed lane-operations of one draw of one lambda group."""
-    per_step = (OPS_PHILOX + 2 * OPS_BM_PAIR) / 4.0 + lpl * OPS_EM
+    per_step = (OPS_PHILOX + NORMALS_PER_CALL // 2 * OPS_BM_PAIR) / NORMALS_PER_CALL + lpl * OPS_EM
     return (steps * per_step + n_obs * lpl * 4 + OPS_PRIOR + OPS_PRIOR_VARIATES
             + lpl * OPS_PRIOR_MEMBER)
 
@@ -78,22 +81,22 @@ def ops_per_grid_draw_one_normal_set(steps: int, n_obs: int, n_lambda: int) -> f
     return ops_per_group_draw(steps, n_obs, n_lambda)
 
 
-# GARCH(1,1) step: the normal (21) + sqrt, 2 multiplies, 2 fma for the
-# variance, 4 moment sums, b_t, 10 lag products = 41, plus 14 Kahan folds
+# GARCH(1,1) step: the normal (16) + sqrt, 2 multiplies, 2 fma for the
+# variance, 4 moment sums, b_t, 10 lag products = 36, plus 14 Kahan folds
 # (4 ops) every 20 steps = 2.8; closing algebra and prior ~ 600 per draw.
-GARCH_OPS_PER_STEP = 43.8
+GARCH_OPS_PER_STEP = 38.8
 GARCH_OPS_PER_DRAW_FIXED = 600
 
 
-# Toggle switch (Sec. 3.2), per cell-step: half a Philox call (30), one
-# Box-Muller pair for (xi_u, xi_v) (12), and per gene the power
+# Toggle switch (Sec. 3.2), per cell-step: a third of a Philox call (20),
+# one Box-Muller pair for (xi_u, xi_v) (12), and per gene the power
 # exp2(beta log2 level) (3), the Hill factor 1 / (1 + p) (2), the drift
-# and noise updates and the boundary (5) = 62; per cell the measurement
+# and noise updates and the boundary (5) = 52; per cell the measurement
 # (power, scale, two adds, boundary: 7), half a pair for eta (6) and a
 # linear-time share of the quantile selection (2); per draw the 7 prior
 # values (~600).  The LDS bitonic sort that does the selection is not
 # counted beyond that linear share.
-TSW_OPS_PER_CELL_STEP = 62
+TSW_OPS_PER_CELL_STEP = 52
 TSW_OPS_PER_CELL = 15
 TSW_OPS_PER_DRAW = 600
 

@@ -131,6 +131,8 @@ def _load():
         lib.or_stream_block.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, u32p]
         lib.or_uniform.argtypes = [ctypes.c_uint32]
         lib.or_uniform.restype = ctypes.c_double
+        lib.or_angle_uniform.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
+        lib.or_angle_uniform.restype = ctypes.c_double
         lib.or_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         lib.or_path_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
@@ -265,6 +267,11 @@ def uniform(word: int) -> float:
     return float(_load().or_uniform(word))
 
 
+def angle_uniform(word_i: int, word3: int, i: int) -> float:
+    """Angle uniform of Box-Muller pair i of a path or cell block (words i and 3)."""
+    return float(_load().or_angle_uniform(word_i, word3, i))
+
+
 def box_muller(w0: int, w1: int) -> tuple[float, float]:
     z0, z1 = ctypes.c_double(), ctypes.c_double()
     _load().or_box_muller(w0, w1, ctypes.byref(z0), ctypes.byref(z1))
@@ -272,6 +279,7 @@ def box_muller(w0: int, w1: int) -> tuple[float, float]:
 
 
 def path_normal(seed: int, draw: int, n: int) -> float:
+    """Normal n of a draw's path stream: block n // 6, pair (n % 6) // 2."""
     return float(_load().or_path_normal(seed, draw, n))
 
 

@@ -109,35 +109,59 @@ void or_box_muller(uint32_t w0, uint32_t w1, double *z0, double *z1)
     *z1 = radius * sin(two_pi * u1);
 }
 
-/* Path normals of one draw: normal n comes from block n/4 of the PATH stream;
- * words (0,1) give normals 4b, 4b+1 and words (2,3) give 4b+2, 4b+3.        */
+/* Path normals of one draw: block b of the stream holds normals 6b .. 6b+5
+ * as three Box-Muller pairs (reading of Sec. 3.4: the generator's 128 bits
+ * serve three pairs, 42 bits each).  Pair i (i = 0, 1, 2) gives normals
+ * 6b + 2i (cosine) and 6b + 2i + 1 (sine):
+ *   radius uniform u0 from word i: its top 23 bits k, u0 = (2k+1)/2^24;
+ *   angle uniform u1 from 19 further bits: the low 9 bits of word i followed
+ *   by bits 22 - 10i .. 31 - 10i of word 3 form m, u1 = m/2^19 (2^19 equally
+ *   spaced angles from 0; unlike u0, the angle may be 0).
+ * The 126 bits used are disjoint.                                           */
+#define OR_NORMALS_PER_BLOCK 6
+
+double or_angle_uniform(uint32_t word_i, uint32_t word3, int i)
+{
+    const uint32_t m = ((word_i & 0x1FFu) << 10) | ((word3 >> (22 - 10 * i)) & 0x3FFu);
+    return (double)m / 524288.0;
+}
+
+/* One Box-Muller pair from its two uniforms.                                */
+static void box_muller_u(double u0, double u1, double *z0, double *z1)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double radius = sqrt(-2.0 * log(u0));
+    *z0 = radius * cos(two_pi * u1);
+    *z1 = radius * sin(two_pi * u1);
+}
+
 static void normals_block(uint64_t seed, uint64_t draw, uint32_t block, uint32_t purpose,
-                          double z[4])
+                          double z[OR_NORMALS_PER_BLOCK])
 {
     uint32_t w[4];
     or_stream_block(seed, draw, block, purpose, w);
-    or_box_muller(w[0], w[1], &z[0], &z[1]);
-    or_box_muller(w[2], w[3], &z[2], &z[3]);
+    for (int i = 0; i < 3; ++i)
+        box_muller_u(or_uniform(w[i]), or_angle_uniform(w[i], w[3], i), &z[2 * i], &z[2 * i + 1]);
 }
 
-void or_path_block(uint64_t seed, uint64_t draw, uint32_t block, double z[4])
+void or_path_block(uint64_t seed, uint64_t draw, uint32_t block, double z[OR_NORMALS_PER_BLOCK])
 {
     normals_block(seed, draw, block, OR_PURPOSE_PATH, z);
 }
 
 double or_path_normal(uint64_t seed, uint64_t draw, uint64_t n)
 {
-    double z[4];
-    or_path_block(seed, draw, (uint32_t)(n / 4), z);
-    return z[n % 4];
+    double z[OR_NORMALS_PER_BLOCK];
+    or_path_block(seed, draw, (uint32_t)(n / OR_NORMALS_PER_BLOCK), z);
+    return z[n % OR_NORMALS_PER_BLOCK];
 }
 
 /* Normal n of cell `cell` of a draw (same block layout, purpose 2 + cell).  */
 double or_cell_normal(uint64_t seed, uint64_t draw, uint32_t cell, uint64_t n)
 {
-    double z[4];
-    normals_block(seed, draw, (uint32_t)(n / 4), OR_PURPOSE_CELL0 + cell, z);
-    return z[n % 4];
+    double z[OR_NORMALS_PER_BLOCK];
+    normals_block(seed, draw, (uint32_t)(n / OR_NORMALS_PER_BLOCK), OR_PURPOSE_CELL0 + cell, z);
+    return z[n % OR_NORMALS_PER_BLOCK];
 }
 
 /* Sequential reader of the normals z_0, z_1, ... of one stream of a draw.  */
@@ -145,7 +169,7 @@ typedef struct {
     uint64_t seed, draw;
     uint32_t purpose;
     uint64_t next;
-    double buf[4];
+    double buf[OR_NORMALS_PER_BLOCK];
 } normal_reader;
 
 static void reader_init_purpose(normal_reader *r, uint64_t seed, uint64_t draw, uint32_t purpose)
@@ -163,9 +187,10 @@ static void reader_init(normal_reader *r, uint64_t seed, uint64_t draw)
 
 static double reader_next(normal_reader *r)
 {
-    if (r->next % 4 == 0)
-        normals_block(r->seed, r->draw, (uint32_t)(r->next / 4), r->purpose, r->buf);
-    return r->buf[r->next++ % 4];
+    if (r->next % OR_NORMALS_PER_BLOCK == 0)
+        normals_block(r->seed, r->draw, (uint32_t)(r->next / OR_NORMALS_PER_BLOCK), r->purpose,
+                      r->buf);
+    return r->buf[r->next++ % OR_NORMALS_PER_BLOCK];
 }
 
 /* ------------------------------------------------------------------------ */

@@ -89,7 +89,7 @@ __device__ __forceinline__ Words4 stream_block(StreamKey key, uint64_t draw, uin
 // 9) is 1 + k 2^-23, k = w >> 9 (one funnel shift of the pair 0x7F:w by 9
 // bits), and subtracting 1 - 2^-24 leaves (2k+1) 2^-24 exactly (the operands
 // lie within a factor 2 of each other): two instructions.  Otherwise shift,
-// convert and FMA: three, which the GARCH kernel's schedule runs faster.
+// convert and FMA: three, which the GARCH kernel's schedule has run faster.
 template <bool FUNNEL = true>
 __device__ __forceinline__ float uniform_f32(uint32_t w)
 {
@@ -106,20 +106,6 @@ __device__ __forceinline__ double uniform_f64(uint32_t w)
     return static_cast<double>(w >> 9) * 0x1p-23 + 0x1p-24;
 }
 
-// Box-Muller in FP32 with the hardware transcendentals: v_log_f32 is log2,
-// v_sin_f32 / v_cos_f32 take their argument in revolutions (x -> sin(2 pi x)),
-// so the angle 2 pi u1 needs no range reduction.
-template <bool FUNNEL = true>
-__device__ __forceinline__ void box_muller_f32(uint32_t w0, uint32_t w1, float &z0, float &z1)
-{
-    const float u0 = uniform_f32<FUNNEL>(w0);
-    const float u1 = uniform_f32<FUNNEL>(w1);
-    // -2 ln u0 = log2(u0) * (-2 ln 2)
-    const float r = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(u0) * -1.38629436111989061883f);
-    z0 = r * __builtin_amdgcn_cosf(u1);
-    z1 = r * __builtin_amdgcn_sinf(u1);
-}
-
 // FP64 Box-Muller (prior draws only: once per parameter per draw);
 // cos(2 pi u1) is evaluated as cospi(2 u1), which needs no range reduction.
 __device__ __forceinline__ double box_muller_f64_first(uint32_t w0, uint32_t w1)
@@ -129,24 +115,51 @@ __device__ __forceinline__ double box_muller_f64_first(uint32_t w0, uint32_t w1)
     return sqrt(-2.0 * log(u0)) * cospi(2.0 * u1);
 }
 
-// Four path normals z_{4b..4b+3} of one draw.
+// Box-Muller in FP32 with the hardware transcendentals: v_log_f32 is log2,
+// v_sin_f32 / v_cos_f32 take their argument in revolutions (x -> sin(2 pi x)),
+// so the angle 2 pi u1 needs no range reduction.
+// The six normals z_{6b..6b+5} of stream block b = (x, y, z, w): three
+// Box-Muller pairs.  Pair i takes its radius uniform from word i (x, y, z)
+// as uniform_f32 does (top 23 bits) and its angle from 19 more bits, the low
+// 9 bits of word i followed by bits [22 - 10i, 32 - 10i) of w, as u1 = m
+// 2^-19 (2^19 equally spaced angles from 0); the 126 bits used are disjoint,
+// so one Philox call serves six normals.  The angle is built in place: a
+// funnel shift of (word i : w << 10i) by 18 bits puts the 9 bits at [14, 23)
+// and the 10 bits of w at [4, 14), and one and-or with the bits of 1.0 (an
+// inline constant) gives 1 + u1 exactly; v_sin / v_cos are periodic in
+// revolutions, so 1 + u1 is used as it is.
+constexpr int NORMALS_PER_BLOCK = 6;
+
 template <bool FUNNEL = true>
-__device__ __forceinline__ void path_normals4(StreamKey key, uint64_t draw, uint32_t block,
-                                              float &z0, float &z1, float &z2, float &z3)
+__device__ __forceinline__ void normals6(const Words4 &w, float (&z)[NORMALS_PER_BLOCK])
 {
-    const Words4 w = stream_block(key, draw, block, PURPOSE_PATH);
-    box_muller_f32<FUNNEL>(w.x, w.y, z0, z1);
-    box_muller_f32<FUNNEL>(w.z, w.w, z2, z3);
+    const uint32_t rw[3] = {w.x, w.y, w.z};
+    const uint32_t sw[3] = {w.w, w.w << 10, w.w << 20};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float u0 = uniform_f32<FUNNEL>(rw[i]);
+        const uint32_t t = __builtin_amdgcn_alignbit(rw[i], sw[i], 18u);
+        const float a1 = __builtin_bit_cast(float, (t & 0x007FFFF0u) | 0x3F800000u);  // 1 + u1
+        // -2 ln u0 = log2(u0) * (-2 ln 2)
+        const float r = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(u0) * -1.38629436111989061883f);
+        z[2 * i] = r * __builtin_amdgcn_cosf(a1);
+        z[2 * i + 1] = r * __builtin_amdgcn_sinf(a1);
+    }
 }
 
-// Four normals z_{4b..4b+3} of cell `cell` of one draw.
-__device__ __forceinline__ void cell_normals4(StreamKey key, uint64_t draw, uint32_t cell,
-                                              uint32_t block, float &z0, float &z1, float &z2,
-                                              float &z3)
+// Normals z_{6b..6b+5} of a draw's path.
+template <bool FUNNEL = true>
+__device__ __forceinline__ void path_normals6(StreamKey key, uint64_t draw, uint32_t block,
+                                              float (&z)[NORMALS_PER_BLOCK])
 {
-    const Words4 w = stream_block(key, draw, block, PURPOSE_CELL0 + cell);
-    box_muller_f32(w.x, w.y, z0, z1);
-    box_muller_f32(w.z, w.w, z2, z3);
+    normals6<FUNNEL>(stream_block(key, draw, block, PURPOSE_PATH), z);
+}
+
+// Normals z_{6b..6b+5} of cell `cell` of a draw.
+__device__ __forceinline__ void cell_normals6(StreamKey key, uint64_t draw, uint32_t cell,
+                                              uint32_t block, float (&z)[NORMALS_PER_BLOCK])
+{
+    normals6(stream_block(key, draw, block, PURPOSE_CELL0 + cell), z);
 }
 
 // ---------------------------------------------------------------------------

@@ -65,13 +65,13 @@ __device__ __forceinline__ void sim_logistic(const JobDev *__restrict__ J, Strea
     float x = static_cast<float>(J->x0);
     int next_obs = stride;
     int k = 0;
-    const int nblk = (steps + 3) >> 2;
+    const int nblk = (steps + NORMALS_PER_BLOCK - 1) / NORMALS_PER_BLOCK;
     for (int blk = 0; blk < nblk; ++blk) {
-        float z[4];
-        path_normals4(key, draw, static_cast<uint32_t>(blk), z[0], z[1], z[2], z[3]);
+        float z[NORMALS_PER_BLOCK];
+        path_normals6(key, draw, static_cast<uint32_t>(blk), z);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int step = 4 * blk + j + 1;  // steps done after this update
+        for (int j = 0; j < NORMALS_PER_BLOCK; ++j) {
+            const int step = NORMALS_PER_BLOCK * blk + j + 1;  // steps done after this update
             if (step > steps)
                 break;
             float g = __builtin_fmaf(-b, x, a);
@@ -100,13 +100,13 @@ __device__ __forceinline__ void sim_normal_mean(const JobDev *__restrict__ J, St
     const float sd = static_cast<float>(J->noise_sd);
     const int m = J->n_summ;
     const uint64_t n = J->n_draws;
-    const int nblk = (m + 3) >> 2;
+    const int nblk = (m + NORMALS_PER_BLOCK - 1) / NORMALS_PER_BLOCK;
     for (int blk = 0; blk < nblk; ++blk) {
-        float z[4];
-        path_normals4(key, draw, static_cast<uint32_t>(blk), z[0], z[1], z[2], z[3]);
+        float z[NORMALS_PER_BLOCK];
+        path_normals6(key, draw, static_cast<uint32_t>(blk), z);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = 4 * blk + j;
+        for (int j = 0; j < NORMALS_PER_BLOCK; ++j) {
+            const int k = NORMALS_PER_BLOCK * blk + j;
             if (k >= m)
                 break;
             const float y = __builtin_fmaf(sd, z[j], mu);
@@ -133,7 +133,8 @@ __device__ __forceinline__ void sim_normal_mean(const JobDev *__restrict__ J, St
 // totals; b_t = s_t^2 - 1 kept in a 10-deep register ring for the lag
 // products; the first 10 b_t are recomputed from the stream at the end for
 // the ACF centring terms.  The closing algebra is FP64.  Requires the length
-// to be a multiple of 20.
+// to be a multiple of 20; the steps run in spans of 60 (ten blocks of six
+// normals, three folds), the last span possibly cut to 20 or 40.
 __device__ __forceinline__ float garch_step(double &h, float z, double al, double be, double c)
 {
     const float s = __builtin_amdgcn_sqrtf(static_cast<float>(h)) * z;
@@ -154,55 +155,71 @@ __device__ __forceinline__ void sim_garch(const JobDev *__restrict__ J, StreamKe
 #pragma unroll
     for (int k = 0; k < PPS_GARCH_LAGS; ++k)
         ring[k] = 0.0f;
-    const int nblk20 = len / 20;
-    for (int blk = 0; blk < nblk20; ++blk) {
-        float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, s4 = 0.0f;
-        float lag[PPS_GARCH_LAGS];
+    float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, s4 = 0.0f;
+    float lag[PPS_GARCH_LAGS];
 #pragma unroll
-        for (int k = 0; k < PPS_GARCH_LAGS; ++k)
-            lag[k] = 0.0f;
+    for (int k = 0; k < PPS_GARCH_LAGS; ++k)
+        lag[k] = 0.0f;
+    // The step at position jj of its 60-step span (10 Philox blocks; spans
+    // start at multiples of 60, so jj % 10 is the step's ring slot); every
+    // 20th step folds the block sums into the Kahan totals.
+    auto step = [&](int jj, float zj) {
+        const float s = garch_step(h, zj, alpha_d, beta_d, oab);
+        const float sq = s * s;
+        s1 += s;
+        s2 += sq;
+        s3 = __builtin_fmaf(sq, s, s3);
+        s4 = __builtin_fmaf(sq, sq, s4);
+        const float bt = sq - 1.0f;
 #pragma unroll
-        for (int p = 0; p < 5; ++p) {
-            float z[4];
-            path_normals4<false>(key, draw, static_cast<uint32_t>(blk * 5 + p), z[0], z[1], z[2],
-                                 z[3]);
+        for (int k = 1; k <= PPS_GARCH_LAGS; ++k)
+            lag[k - 1] = __builtin_fmaf(bt, ring[(jj - k + 60) % 10], lag[k - 1]);
+        ring[jj % 10] = bt;
+        if (jj % 20 == 19) {
+            K1.add(s1);
+            K2.add(s2);
+            K3.add(s3);
+            K4.add(s4);
+            s1 = s2 = s3 = s4 = 0.0f;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int jj = 4 * p + j;  // position in the 20-step block
-                const float s = garch_step(h, z[j], alpha_d, beta_d, oab);
-                const float sq = s * s;
-                s1 += s;
-                s2 += sq;
-                s3 = __builtin_fmaf(sq, s, s3);
-                s4 = __builtin_fmaf(sq, sq, s4);
-                const float bt = sq - 1.0f;
-#pragma unroll
-                for (int k = 1; k <= PPS_GARCH_LAGS; ++k)
-                    lag[k - 1] = __builtin_fmaf(bt, ring[(jj - k + 20) % 10], lag[k - 1]);
-                ring[jj % 10] = bt;
+            for (int k = 0; k < PPS_GARCH_LAGS; ++k) {
+                KL[k].add(lag[k]);
+                lag[k] = 0.0f;
             }
         }
-        K1.add(s1);
-        K2.add(s2);
-        K3.add(s3);
-        K4.add(s4);
+    };
+    // The first `lim` steps of span sp (lim = 60 but in the last span).
+    auto span = [&](int sp, int lim) {
 #pragma unroll
-        for (int k = 0; k < PPS_GARCH_LAGS; ++k)
-            KL[k].add(lag[k]);
-    }
+        for (int p = 0; p < 10; ++p) {
+            if (NORMALS_PER_BLOCK * p >= lim)
+                break;
+            float z[NORMALS_PER_BLOCK];
+            path_normals6<false>(key, draw, static_cast<uint32_t>(10 * sp + p), z);
+#pragma unroll
+            for (int j = 0; j < NORMALS_PER_BLOCK; ++j)
+                if (NORMALS_PER_BLOCK * p + j < lim)
+                    step(NORMALS_PER_BLOCK * p + j, z[j]);
+        }
+    };
+    const int nspan = len / 60;
+    for (int sp = 0; sp < nspan; ++sp)
+        span(sp, 60);
+    if (len > 60 * nspan)
+        span(nspan, len - 60 * nspan);  // 20 or 40 steps
     // The first 10 b_t again (same operations, so the same values).
     float head[PPS_GARCH_LAGS];
     {
         double h0 = 1.0;
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            float z[4];
-            path_normals4<false>(key, draw, static_cast<uint32_t>(p), z[0], z[1], z[2], z[3]);
+        for (int p = 0; p < 2; ++p) {
+            float z[NORMALS_PER_BLOCK];
+            path_normals6<false>(key, draw, static_cast<uint32_t>(p), z);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (4 * p + j < PPS_GARCH_LAGS) {
+            for (int j = 0; j < NORMALS_PER_BLOCK; ++j) {
+                if (NORMALS_PER_BLOCK * p + j < PPS_GARCH_LAGS) {
                     const float s = garch_step(h0, z[j], alpha_d, beta_d, oab);
-                    head[4 * p + j] = s * s - 1.0f;
+                    head[NORMALS_PER_BLOCK * p + j] = s * s - 1.0f;
                 }
             }
         }
@@ -258,23 +275,22 @@ __device__ __forceinline__ void sim_logistic_ilp(const JobDev *__restrict__ J, S
     }
     const int steps = J->steps;
     const int stride = J->obs_stride;
-    const int nblk = (steps + 3) >> 2;
+    const int nblk = (steps + NORMALS_PER_BLOCK - 1) / NORMALS_PER_BLOCK;
     int next_obs = stride;
     int k = 0;
     int blk = 0;
     for (; blk + UNROLL <= nblk; blk += UNROLL) {
-        float z[UNROLL][DPL][4];
+        float z[UNROLL][DPL][NORMALS_PER_BLOCK];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
             for (int d = 0; d < DPL; ++d)
-                path_normals4(key, draw[d], static_cast<uint32_t>(blk + u), z[u][d][0], z[u][d][1],
-                              z[u][d][2], z[u][d][3]);
+                path_normals6(key, draw[d], static_cast<uint32_t>(blk + u), z[u][d]);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int step = 4 * (blk + u) + j + 1;
+            for (int j = 0; j < NORMALS_PER_BLOCK; ++j) {
+                const int step = NORMALS_PER_BLOCK * (blk + u) + j + 1;
                 if (step > steps)
                     break;
 #pragma unroll
@@ -298,13 +314,13 @@ __device__ __forceinline__ void sim_logistic_ilp(const JobDev *__restrict__ J, S
         }
     }
     for (; blk < nblk; ++blk) {
-        float z[DPL][4];
+        float z[DPL][NORMALS_PER_BLOCK];
 #pragma unroll
         for (int d = 0; d < DPL; ++d)
-            path_normals4(key, draw[d], static_cast<uint32_t>(blk), z[d][0], z[d][1], z[d][2], z[d][3]);
+            path_normals6(key, draw[d], static_cast<uint32_t>(blk), z[d]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int step = 4 * blk + j + 1;
+        for (int j = 0; j < NORMALS_PER_BLOCK; ++j) {
+            const int step = NORMALS_PER_BLOCK * blk + j + 1;
             if (step > steps)
                 break;
 #pragma unroll
@@ -503,20 +519,23 @@ __device__ __forceinline__ void group_members(const JobDev *__restrict__ J, Stre
     }
     const int steps = J->steps;
     const int stride = J->obs_stride;
-    const int nblk = (steps + 3) >> 2;
+    const int nblk = (steps + NORMALS_PER_BLOCK - 1) / NORMALS_PER_BLOCK;
     int next_obs = stride;
     // the normals of block blk + 1 are generated while the members advance
     // through block blk: the two are independent, so the scheduler can fill
     // the Philox / Box-Muller latencies with member updates
-    float zn[4];
-    path_normals4(key, draw, 0u, zn[0], zn[1], zn[2], zn[3]);
+    float zn[NORMALS_PER_BLOCK];
+    path_normals6(key, draw, 0u, zn);
     for (int blk = 0; blk < nblk; ++blk) {
-        const float z[4] = {zn[0], zn[1], zn[2], zn[3]};
-        if (blk + 1 < nblk)
-            path_normals4(key, draw, static_cast<uint32_t>(blk + 1), zn[0], zn[1], zn[2], zn[3]);
+        float z[NORMALS_PER_BLOCK];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int step = 4 * blk + j + 1;
+        for (int j = 0; j < NORMALS_PER_BLOCK; ++j)
+            z[j] = zn[j];
+        if (blk + 1 < nblk)
+            path_normals6(key, draw, static_cast<uint32_t>(blk + 1), zn);
+#pragma unroll
+        for (int j = 0; j < NORMALS_PER_BLOCK; ++j) {
+            const int step = NORMALS_PER_BLOCK * blk + j + 1;
             if (step > steps)
                 break;
 #pragma unroll
@@ -646,29 +665,30 @@ __device__ __forceinline__ void toggle_step(const ToggleConsts &P, float &u, flo
 }
 
 // Measurement of one cell after `steps` steps (Eq. gene_u_obs), held at >= 1.
-// Step j uses normals 2j, 2j+1 of the cell's stream (Philox block j/2 holds
-// steps 2b and 2b+1); the measurement noise is normal 2 steps.
+// Step j uses normals 2j, 2j+1 of the cell's stream (Philox block b holds
+// steps 3b, 3b+1 and 3b+2); the measurement noise is normal 2 steps.
 __device__ __forceinline__ float toggle_cell(const ToggleConsts &P, StreamKey key, uint64_t draw,
                                              uint32_t cell, int steps, float x0)
 {
+    constexpr int SPB = NORMALS_PER_BLOCK / 2;  // steps per block
     float u = x0, v = x0;
-    const int pairs = steps >> 1;
-    for (int b = 0; b < pairs; ++b) {
-        float z0, z1, z2, z3;
-        cell_normals4(key, draw, cell, static_cast<uint32_t>(b), z0, z1, z2, z3);
-        toggle_step(P, u, v, z0, z1);
-        toggle_step(P, u, v, z2, z3);
+    const int full = steps / SPB;
+    for (int b = 0; b < full; ++b) {
+        float z[NORMALS_PER_BLOCK];
+        cell_normals6(key, draw, cell, static_cast<uint32_t>(b), z);
+#pragma unroll
+        for (int j = 0; j < SPB; ++j)
+            toggle_step(P, u, v, z[2 * j], z[2 * j + 1]);
     }
-    const Words4 w = stream_block(key, draw, static_cast<uint32_t>(pairs), PURPOSE_CELL0 + cell);
-    float z0, z1, eta;
-    box_muller_f32(w.x, w.y, z0, z1);
-    if (steps & 1) {
-        toggle_step(P, u, v, z0, z1);
-        float z3;
-        box_muller_f32(w.z, w.w, eta, z3);
-    } else {
-        eta = z0;
-    }
+    // the last block: the remaining steps (fewer than three), then eta
+    const int rest = steps - SPB * full;
+    float z[NORMALS_PER_BLOCK];
+    cell_normals6(key, draw, cell, static_cast<uint32_t>(full), z);
+    if (rest > 0)
+        toggle_step(P, u, v, z[0], z[1]);
+    if (rest > 1)
+        toggle_step(P, u, v, z[2], z[3]);
+    const float eta = rest == 0 ? z[0] : (rest == 1 ? z[2] : z[4]);
     // u^-gamma = exp2(-gamma log2 u)
     const float scale = __builtin_amdgcn_exp2f(-P.gamma * __builtin_amdgcn_logf(u));
     const float y = __builtin_fmaf(P.mu_sigma * eta, scale, u + P.mu);
@@ -1301,11 +1321,11 @@ __global__ void k_normals(uint64_t seed, uint64_t first, uint64_t n, uint32_t m,
     const StreamKey key = make_key(seed);
     for (uint64_t q = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; q < n;
          q += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        for (uint32_t b = 0; 4 * b < m; ++b) {
-            float z[4];
-            path_normals4(key, first + q, b, z[0], z[1], z[2], z[3]);
-            for (uint32_t j = 0; j < 4 && 4 * b + j < m; ++j)
-                out[static_cast<uint64_t>(4 * b + j) * n + q] = z[j];
+        for (uint32_t b = 0; NORMALS_PER_BLOCK * b < m; ++b) {
+            float z[NORMALS_PER_BLOCK];
+            path_normals6(key, first + q, b, z);
+            for (uint32_t j = 0; j < NORMALS_PER_BLOCK && NORMALS_PER_BLOCK * b + j < m; ++j)
+                out[static_cast<uint64_t>(NORMALS_PER_BLOCK * b + j) * n + q] = z[j];
         }
     }
 }

@@ -24,17 +24,17 @@ def test_more_than_one_gpu_is_refused_with_a_message(argv, env):
 
 
 def test_operation_counts_of_the_roofline():
-    # per EM step: a quarter Philox call (60), half a Box-Muller pair per
-    # normal (2 x 12 per call of four normals), the EM update (4)
-    assert bench.ops_per_draw(1000, 20) == 1000 * ((60 + 24) / 4 + 4) + 20 * 9 + 250 == 25430
+    # per EM step: a sixth of a Philox call (60), a Box-Muller pair per two
+    # normals (3 x 12 per call of six normals), the EM update (4)
+    assert bench.ops_per_draw(1000, 20) == 1000 * ((60 + 36) / 6 + 4) + 20 * 9 + 250 == 20430
     # a draw-group of 32 lambda values: one normal per step, 32 EM updates,
     # 32 Kahan means per observation, the shared theta, the lambda'd
     # parameter's variate once, 32 member transforms
-    assert bench.ops_per_group_draw(1000, 20) == 1000 * (21 + 128) + 20 * 128 + 250 + 72 + 32 * 7 == 152106
+    assert bench.ops_per_group_draw(1000, 20) == 1000 * (16 + 128) + 20 * 128 + 250 + 72 + 32 * 7 == 147106
     # the 64-lambda grid with its normals counted once per draw
-    assert bench.ops_per_grid_draw_one_normal_set(1000, 20, 64) == 1000 * (21 + 256) + 20 * 256 + 250 + 72 + 64 * 7
-    # toggle switch: 62 per cell-step, 15 per cell, 600 per draw
-    assert bench.toggle_ops_per_draw(8000, 599) == 8000 * (599 * 62 + 15) + 600
+    assert bench.ops_per_grid_draw_one_normal_set(1000, 20, 64) == 1000 * (16 + 256) + 20 * 256 + 250 + 72 + 64 * 7
+    # toggle switch: 52 per cell-step, 15 per cell, 600 per draw
+    assert bench.toggle_ops_per_draw(8000, 599) == 8000 * (599 * 52 + 15) + 600
     assert bench.VALU_PEAK_OPS == 256 * 128 * 2.4e9
 
 

@@ -237,12 +237,15 @@ def _np_philox(ctr, key):
 
 
 def _np_normals(seed, draw, count):
+    # block b: three pairs; pair i has its radius from word i's top 23 bits
+    # and its angle from word i's low 9 bits and 10 bits of word 3
     out = []
-    for b in range((count + 3) // 4):
+    for b in range((count + 5) // 6):
         w = _np_philox([b, 1, draw & 0xFFFFFFFF, draw >> 32], [seed & 0xFFFFFFFF, seed >> 32])
-        for i in (0, 2):
+        for i in range(3):
             u0 = (2 * (w[i] >> 9) + 1) / 2**24
-            u1 = (2 * (w[i + 1] >> 9) + 1) / 2**24
+            m = ((w[i] % 512) * 1024) + (w[3] // 2 ** (22 - 10 * i)) % 1024
+            u1 = m / 2**19
             rad = math.sqrt(-2 * math.log(u0))
             out += [rad * math.cos(2 * math.pi * u1), rad * math.sin(2 * math.pi * u1)]
     return out[:count]

@@ -6,7 +6,8 @@
   implementation (Random123) for 10 rounds;
 * the uniform lattice (exact values);
 * Box-Muller: the polar identities fix which word is the radius and which the
-  angle; the normals are N(0,1) by a KS test.
+  angle; a path block's six normals read disjoint bits; the normals are
+  N(0,1) by a KS test and uncorrelated across their positions in a block.
 """
 import math
 import os
@@ -117,20 +118,57 @@ def test_path_normals_are_standard_normal():
     assert abs(z.mean()) < 4 / math.sqrt(len(z))
     assert abs(z.var() - 1) < 4 * math.sqrt(2 / len(z))
     assert stats.kstest(z, "norm").pvalue > 1e-4
-    # |z| is bounded by the lattice: sqrt(-2 ln 2^-24) = 5.77
+    # |z| is bounded by the radius lattice: sqrt(-2 ln 2^-24) = 5.77
     assert np.abs(z).max() <= math.sqrt(-2 * math.log(2.0**-24)) + 1e-12
+    # the six positions of a block (200 normals per draw = 33 whole blocks)
+    blocks = z.reshape(500, 200)[:, :198].reshape(-1, 6)
+    c = np.corrcoef(blocks.T)
+    assert np.abs(c - np.eye(6)).max() < 5 / math.sqrt(len(blocks))
 
 
 def test_path_normal_block_layout():
-    """Normals 4b..4b+3 come from PATH block b: words (0,1) -> 4b, 4b+1 and
-    words (2,3) -> 4b+2, 4b+3."""
+    """Normals 6b..6b+5 come from PATH block b: pair i takes its radius
+    uniform from word i (top 23 bits) and its angle uniform from the low 9
+    bits of word i followed by bits 22-10i..31-10i of word 3."""
     seed, draw = 5, 77
-    for b in (0, 1, 249):
-        w = oracle.stream_block(seed, draw, b, 1)
-        z = [oracle.path_normal(seed, draw, 4 * b + j) for j in range(4)]
-        a0, a1 = oracle.box_muller(int(w[0]), int(w[1]))
-        a2, a3 = oracle.box_muller(int(w[2]), int(w[3]))
-        assert z == [a0, a1, a2, a3]
+    for b in (0, 1, 166, 333):
+        w = [int(v) for v in oracle.stream_block(seed, draw, b, 1)]
+        z = [oracle.path_normal(seed, draw, 6 * b + j) for j in range(6)]
+        for i in range(3):
+            u0 = oracle.uniform(w[i])
+            m = ((w[i] & 0x1FF) << 10) | ((w[3] >> (22 - 10 * i)) & 0x3FF)
+            u1 = m / 2.0**19
+            assert oracle.angle_uniform(w[i], w[3], i) == u1
+            r = math.sqrt(-2.0 * math.log(u0))
+            assert math.isclose(z[2 * i], r * math.cos(2 * math.pi * u1), rel_tol=1e-15, abs_tol=1e-15)
+            assert math.isclose(z[2 * i + 1], r * math.sin(2 * math.pi * u1), rel_tol=1e-15, abs_tol=1e-15)
+
+
+def test_path_normal_bits_are_disjoint():
+    """The 19-bit angle indices of the three pairs and the three radius
+    indices read disjoint bits of the block: flipping any one of the 126
+    used bits changes exactly one of the six uniforms, and flipping one of
+    the two unused bits (word 3, bits 0 and 1) changes none."""
+    rng = np.random.default_rng(4)
+    w = [int(v) for v in rng.integers(0, 2**32, size=4, dtype=np.uint64)]
+
+    def uniforms(ws):
+        return [oracle.uniform(ws[i]) for i in range(3)] + \
+               [oracle.angle_uniform(ws[i], ws[3], i) for i in range(3)]
+
+    base = uniforms(w)
+    used = 0
+    for word in range(4):
+        for bit in range(32):
+            ws = list(w)
+            ws[word] ^= 1 << bit
+            changed = sum(a != b for a, b in zip(base, uniforms(ws)))
+            if word == 3 and bit < 2:
+                assert changed == 0
+            else:
+                assert changed == 1, (word, bit)
+                used += 1
+    assert used == 126
 
 
 # Known-answer vectors of Philox4x32 with 10 rounds (counter, key, output),
