@@ -227,7 +227,7 @@ int abc_sample(const pps_model *model, const double *y_obs, const pps_sampling *
  * as tight serving loops or harnesses that forbid it): abc_sample with the
  * same arguments, kernels, results and error codes, whose device scratch
  * (the n rho values and the finalisation's block counts, moment partials,
- * selection histogram and result: abc_scratch_bytes(n), 16.2 MiB at the
+ * selection histogram and result: abc_scratch_bytes(n), 16.1 MiB at the
  * maximum) is a file-scope device array of the library, one per device,
  * held until the process ends.  It allocates nothing on its success path: no
  * hipMalloc / hipFree, no graph capture or instantiation, no host heap.  So

@@ -124,9 +124,11 @@ struct alignas(64) EpochHeader {
 
 // ---- ABC finalisation (select / compaction / moments) -------------------
 
-// Elements per compaction / histogram workgroup: 4 waves x 16 rows x 64.
+// Elements per compaction / histogram workgroup: 4 waves x 32 rows x 64
+// (1221 blocks at 1e7 draws: about one round of the compaction kernel's
+// resident workgroups, where 16 rows took three).
 constexpr int FIN_BLOCK = 256;
-constexpr int FIN_ROWS = 16;
+constexpr int FIN_ROWS = 32;
 constexpr int FIN_TILE = FIN_BLOCK * FIN_ROWS;
 constexpr int SEL_BITS0 = 11, SEL_BITS1 = 11, SEL_BITS2 = 10;
 constexpr int SEL_BINS = 1 << 11;
