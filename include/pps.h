@@ -173,9 +173,12 @@ typedef struct {
 int pps_philox(uint64_t seed, uint64_t first_draw, uint64_t n, uint32_t block,
                uint32_t purpose, uint32_t *out, void *stream);
 
-/* FP32 path normals z_0 .. z_{m-1} of each draw (normal k from path block
- * k/4 by Box-Muller: words (0,1) -> z_{4b}, z_{4b+1}; (2,3) -> z_{4b+2},
- * z_{4b+3}; uniforms u = (2 (w >> 9) + 1) 2^-24).  out: device, m*n floats,
+/* FP32 path normals z_0 .. z_{m-1} of each draw (Box-Muller, Sec. 3.4):
+ * normal k comes from path block b = k/6, which holds three pairs; pair i
+ * (z_{6b+2i} = r cos(2 pi u1), z_{6b+2i+1} = r sin(2 pi u1), r = sqrt(-2 ln
+ * u0)) takes u0 = (2 (w_i >> 9) + 1) 2^-24 from word i and u1 = m 2^-19 from
+ * m = (w_i & 0x1FF) << 10 | (w_3 >> (22 - 10 i)) & 0x3FF.  Every model's
+ * path and cell streams use this layout.  out: device, m*n floats,
  * out[k*n + q] (SoA).  Errors: PPS_EINVAL for n == 0, m == 0, out == NULL. */
 int pps_normals(uint64_t seed, uint64_t first_draw, uint64_t n, uint32_t m, float *out,
                 void *stream);
