@@ -561,7 +561,7 @@ typedef struct {
  * shape), keeps the fastest for all later calls, batches and servers created
  * afterwards, and appends it to the cache file named by the environment
  * variable PPS_TUNE_CACHE, if set, keyed by (GPU architecture, class, steps
- * rounded up to a power of two).  With use_cache != 0 and a matching cache
+ * and n_draws, each rounded up to a power of two).  With use_cache != 0 and a matching cache
  * line, the cached shape is applied without timing.  report may be NULL. */
 int pps_autotune(const pps_model *model, uint64_t n_draws, int use_cache, pps_tune_report *report,
                  void *stream);

@@ -39,6 +39,16 @@ int steps_bucket(int steps)
     return b;
 }
 
+// Draw counts rounded up to a power of two: the best shape of a class moves
+// with the job size (tile counts per workgroup and the grid's last round).
+uint64_t draws_bucket(uint64_t n)
+{
+    uint64_t b = 1;
+    while (b < n && b < (uint64_t(1) << 62))
+        b <<= 1;
+    return b;
+}
+
 std::string arch_name(int device)
 {
     hipDeviceProp_t prop;
@@ -49,18 +59,24 @@ std::string arch_name(int device)
     return colon == std::string::npos ? a : a.substr(0, colon);
 }
 
-// Cache file lines: "<arch> <class> <steps bucket> <block> <dpl> <unroll> <ms>".
-bool cache_lookup(const char *path, const std::string &arch, int cls, int bucket, SimShape *sh)
+// Cache file lines: "<arch> <class> <steps bucket> <draws bucket> <block>
+// <dpl> <unroll> <ms>"; lines of any other form are skipped.
+bool cache_lookup(const char *path, const std::string &arch, int cls, int bucket,
+                  unsigned long long dbucket, SimShape *sh)
 {
     FILE *f = std::fopen(path, "r");
     if (!f)
         return false;
-    char a[64];
+    char line[256], a[64];
     int c, b, block, dpl, unroll;
+    unsigned long long db;
     double ms;
     bool found = false;
-    while (std::fscanf(f, "%63s %d %d %d %d %d %lf", a, &c, &b, &block, &dpl, &unroll, &ms) == 7) {
-        if (arch == a && c == cls && b == bucket) {
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "%63s %d %d %llu %d %d %d %lf", a, &c, &b, &db, &block, &dpl, &unroll,
+                        &ms) != 8)
+            continue;
+        if (arch == a && c == cls && b == bucket && db == dbucket) {
             sh->block = block;
             sh->dpl = dpl;
             sh->unroll = unroll;
@@ -72,13 +88,13 @@ bool cache_lookup(const char *path, const std::string &arch, int cls, int bucket
 }
 
 void cache_append(const char *path, const std::string &arch, int cls, int bucket,
-                  const SimShape &sh, double ms)
+                  unsigned long long dbucket, const SimShape &sh, double ms)
 {
     FILE *f = std::fopen(path, "a");
     if (!f)
         return;
-    std::fprintf(f, "%s %d %d %d %d %d %.6f\n", arch.c_str(), cls, bucket, sh.block, sh.dpl,
-                 sh.unroll, ms);
+    std::fprintf(f, "%s %d %d %llu %d %d %d %.6f\n", arch.c_str(), cls, bucket, dbucket, sh.block,
+                 sh.dpl, sh.unroll, ms);
     std::fclose(f);
 }
 
@@ -100,6 +116,7 @@ extern "C" int pps_autotune(const pps_model *model, uint64_t n_draws, int use_ca
     const int cls = model_class(model);
     const int steps = model->model == PPS_NORMAL_MEAN ? model->n_obs : model->steps;
     const int bucket = steps_bucket(steps);
+    const unsigned long long dbucket = draws_bucket(n_draws);
     const std::string arch = arch_name(c->device);
     const char *cache = std::getenv("PPS_TUNE_CACHE");
     if (report) {
@@ -108,7 +125,7 @@ extern "C" int pps_autotune(const pps_model *model, uint64_t n_draws, int use_ca
         report->best = -1;
     }
     SimShape cached;
-    if (use_cache && cache && cache_lookup(cache, arch, cls, bucket, &cached)) {
+    if (use_cache && cache && cache_lookup(cache, arch, cls, bucket, dbucket, &cached)) {
         c->engine->set_shape(cls, cached);
         if (report) {
             report->n_entries = 1;
@@ -167,6 +184,6 @@ extern "C" int pps_autotune(const pps_model *model, uint64_t n_draws, int use_ca
     if (report)
         report->best = best;
     if (cache)
-        cache_append(cache, arch, cls, bucket, shapes[best], best_ms);
+        cache_append(cache, arch, cls, bucket, dbucket, shapes[best], best_ms);
     return PPS_OK;
 }

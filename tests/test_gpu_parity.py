@@ -361,11 +361,18 @@ def test_autotune_and_cache(P, torch, tmp_path, monkeypatch):
         assert rep["best"] in [tuple(s) for s in P.PATH_SHAPES]
         assert P.pps_get_launch_shape(0) == rep["best"]
         line = cache.read_text().split()
-        assert line[1] == "0" and line[2] == "256"  # class 0, steps bucket 256
+        # class 0, steps bucket 256, draws bucket 2^18
+        assert line[1] == "0" and line[2] == "256" and line[3] == str(1 << 18)
         P.pps_set_launch_shape(0, 64, 2, 2)
-        rep2 = P.pps_autotune(spec, 1 << 18, use_cache=True)
+        rep2 = P.pps_autotune(spec, (1 << 17) + 1, use_cache=True)  # same buckets
         assert rep2["from_cache"] and rep2["best"] == rep["best"]
         assert P.pps_get_launch_shape(0) == rep["best"]
+        # another draw count is another entry; lines of another form are skipped
+        assert not P.pps_autotune(spec, 1 << 16, use_cache=True)["from_cache"]
+        old = tmp_path / "old.txt"
+        old.write_text(" ".join(line[:3] + line[4:]) + "\n")
+        monkeypatch.setenv("PPS_TUNE_CACHE", str(old))
+        assert not P.pps_autotune(spec, 1 << 18, use_cache=True)["from_cache"]
         g = P.pps_autotune(W.garch_spec(series_len=200), 1 << 15, use_cache=False)
         assert len(g["entries"]) == len(P.GARCH_SHAPES)
     finally:
