@@ -54,8 +54,9 @@ def test_philox_known_answers(P, torch):
         assert out.cpu().numpy().view(np.uint32).tolist() == list(expect)
 
 
-def test_path_normals_fp32_vs_fp64(P, torch):
-    seed, first, n, m = 3, 2**32 - 37, 1500, 22  # draw indices cross the 2^32 boundary
+@pytest.mark.parametrize("m", [22, 25, 29])  # 4, 1 and 5 normals past whole blocks of six
+def test_path_normals_fp32_vs_fp64(P, torch, m):
+    seed, first, n = 3, 2**32 - 37, 1500  # draw indices cross the 2^32 boundary
     out = torch.empty((m, n), dtype=torch.float32, device="cuda")
     P.pps_normals(seed, first, n, m, out)
     got = out.cpu().numpy().astype(np.float64)
